@@ -1,0 +1,157 @@
+/*
+ * pauli.h -- C ABI of libpauli, a gfx950 (MI355X) library for the dense Pauli
+ * decomposition of T. Jones, "Decomposing dense matrices into dense Pauli
+ * tensors" (2024).
+ *
+ * Operation (paper, section 1, Eq. (1) and Eq. (cn_compact)): a complex
+ * 2^N x 2^N matrix G is written as G = sum_n c_n P_n over the 4^N Pauli
+ * strings P_n, with c_n = 2^-N Tr(P_n G).
+ *
+ * Conventions fixed by the paper and used by every entry point:
+ *   - Matrices are row-major, G[r][c] at element r * 2^N + c, complex values
+ *     stored as interleaved (re, im) pairs: float pairs for PAULI_C64,
+ *     double pairs for PAULI_C128.
+ *   - Bit t of a row or column index belongs to qubit t, the t-th Kronecker
+ *     factor counted from the RIGHT (section 2, notation paragraph).
+ *   - Coefficient n takes operator t from bits (2t+1, 2t) of n:
+ *     0 = identity, 1 = X, 2 = Y, 3 = Z (section 2, last paragraph), so
+ *     c_1 multiplies I (x) X and c_4 multiplies X (x) I for N = 2 (Eq. (2)).
+ *   - The Pauli matrices are those of Eq. (3), Y = [[0, -i], [i, 0]].
+ *
+ * Memory: every data pointer (G, coefficients, gradients, workspace) is a
+ * DEVICE pointer, allocated and owned by the caller, aligned to 16 bytes
+ * (256 for the batched workspace).  Input and output buffers must not
+ * overlap.  The library keeps no device allocations of its
+ * own except in pauli_decompose_batched's graph cache (see there).
+ *
+ * Execution: work is enqueued on opts->stream (a hipStream_t passed as
+ * void*, NULL = the null stream) and the call returns without waiting.  The
+ * caller synchronises before reading results.  No C++ exception crosses this
+ * interface.
+ *
+ * Errors: every function returns a pauli_status.  On failure nothing has been
+ * enqueued and pauli_last_error() returns a message for the calling thread.
+ */
+#ifndef PAULI_H
+#define PAULI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pauli_status {
+    PAULI_OK = 0,
+    PAULI_EINVAL = 1,       /* bad argument: N out of range, NULL, misaligned, overlap, count */
+    PAULI_EUNSUPPORTED = 2, /* valid request this build does not implement */
+    PAULI_EHIP = 3,         /* HIP runtime error; message carries hipGetErrorString */
+    PAULI_ENOMEM = 4        /* caller workspace smaller than required */
+} pauli_status;
+
+typedef enum pauli_dtype {
+    PAULI_C64 = 0,  /* complex float: (float re, float im) */
+    PAULI_C128 = 1  /* complex double: (double re, double im) */
+} pauli_dtype;
+
+typedef enum pauli_algo {
+    /* Binary64 VALU kernel that sums every coefficient in Gray-code order
+     * with the one-sign recurrence of section 2, Eq. (lambda_recurrence_over_i),
+     * as the paper's algorithm (section 3, Fig. 1b) does. */
+    PAULI_ALGO_FP64_GRAY = 0,
+    /* Binary32 matrix-core (MFMA) contraction of the gathered XOR diagonals
+     * against the +-1 sign matrix, FP32 accumulation. */
+    PAULI_ALGO_FP32 = 1,
+    /* Each binary32 input component split exactly into three bfloat16 parts
+     * (hi, mid, lo); bf16 MFMA with two FP32 accumulators (hi; mid+lo),
+     * recombined in binary64 before the phase and 2^-N scaling. */
+    PAULI_ALGO_SPLIT_BF16 = 2
+} pauli_algo;
+
+typedef struct pauli_opts {
+    int algo;               /* pauli_algo */
+    int in_dtype;           /* pauli_dtype of the input */
+    int out_dtype;          /* pauli_dtype of the output */
+    int tile;               /* 0 = tuned/default tile; >0 forces a tile id (pauli_tile_count) */
+    void* stream;           /* hipStream_t, NULL = null stream */
+    void* workspace;        /* device scratch for pauli_decompose_batched */
+    size_t workspace_bytes; /* its size in bytes */
+} pauli_opts;
+
+/* Fill *o with the defaults: SPLIT_BF16, C64 in, C64 out, tile 0, null stream,
+ * no workspace. */
+void pauli_opts_default(pauli_opts* o);
+
+/*
+ * Decompose `batch` matrices of order 2^N stored back to back in G
+ * (batch * 4^N elements) into out (batch * 4^N coefficients):
+ *     out[b * 4^N + n] = 2^-N Tr(P_n G_b)                (Eq. (cn_compact))
+ * evaluated as in section 2, Eq. (c_def_in_terms_of_fn):
+ *     c_n = 2^-N sum_i lambda_i^(n) G[i xor m^(n)][i].
+ * 0 <= N <= 16 (the coefficient index needs 2N bits, section 2); batch >= 1.
+ * The MFMA algorithms read C128 input rounded to binary32.
+ * opts may be NULL (defaults).
+ */
+int pauli_decompose(const void* G, int N, int batch, void* out, const pauli_opts* opts);
+
+/*
+ * Recompose matrices from coefficients, G = sum_n c_n P_n (Eq. (1)), for
+ * `batch` coefficient vectors of length 4^N stored back to back.  Exact
+ * inverse of pauli_decompose up to rounding.  Same limits as above.
+ */
+int pauli_reconstruct(const void* c, int N, int batch, void* G, const pauli_opts* opts);
+
+/*
+ * Adjoint of pauli_decompose, used for reverse-mode differentiation: given
+ * grad_c = dL/dRe(c) + i dL/dIm(c) for a real loss L, write
+ *     grad_G = dL/dRe(G) + i dL/dIm(G) = 2^-N sum_n grad_c[n] P_n,
+ * which follows from the linear form Eq. (cn_compact) and the Hermiticity of
+ * every Pauli string.  Layout, limits and batching as pauli_reconstruct.
+ */
+int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
+                             const pauli_opts* opts);
+
+/*
+ * Decompose `count` matrices of uneven sizes in one persistent launch:
+ * G[k] (device pointer) holds a 2^N[k] x 2^N[k] matrix, out[k] receives its
+ * 4^N[k] coefficients.  G, N and out are HOST arrays of length count.
+ * 1 <= N[k] <= 12, count >= 1; algo SPLIT_BF16 or FP32, C64 in and out.
+ * opts->workspace must hold pauli_batched_workspace_bytes(count) bytes of
+ * device memory that stays valid and untouched while the launch runs.  The
+ * launch is captured in a HIP graph cached per (stream, workspace, sizes) and
+ * replayed on later calls with the same key; the descriptor table is copied
+ * into the workspace on every call, so new pointers are honoured.  Calls that
+ * share a workspace must be ordered on one stream.
+ */
+int pauli_decompose_batched(int count, const void* const* G, const int* N, void* const* out,
+                            const pauli_opts* opts);
+
+/* Device workspace bytes pauli_decompose_batched needs for `count` matrices. */
+size_t pauli_batched_workspace_bytes(int count);
+
+/*
+ * Time every tile configuration of `algo` for N_min <= N <= N_max on the
+ * current device (allocating and freeing its own scratch matrices), keep the
+ * fastest per N in the process-wide tune table, and write the table to the
+ * file named by the PAULI_TUNE_CACHE environment variable if it is set.
+ * Blocking.  opts supplies algo and stream (may be NULL: SPLIT_BF16).
+ */
+int pauli_autotune(int N_min, int N_max, const pauli_opts* opts);
+
+/* Number of selectable tile configurations for `algo` (ids 1..count). */
+int pauli_tile_count(int algo);
+
+/* Tile id pauli_decompose would use for (algo, N) right now. */
+int pauli_tile_selected(int algo, int N);
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* pauli_last_error(void);
+
+/* Library ABI version, currently 1. */
+int pauli_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAULI_H */

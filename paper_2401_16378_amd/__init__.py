@@ -1,0 +1,225 @@
+"""MI355X (gfx950) dense Pauli decomposition.
+
+Python binding of libpauli (include/pauli.h): every computation runs in the
+library's HIP kernels; this module only marshals torch tensors (device memory
+and the current stream) into the C ABI.  It raises if the library is not
+built or no GPU is visible -- there is no CPU fallback.
+
+    c = decompose(G)            # G: complex [..., 2^N, 2^N] on cuda -> [..., 4^N]
+    G = reconstruct(c)          # sum_n c_n P_n
+    g = decompose_backward(gc)  # 2^-N sum_n gc_n P_n  (adjoint of decompose)
+    cs = decompose_batched([G0, G1, ...])   # uneven N, one persistent launch
+    PauliDecompose.apply(G)     # differentiable
+
+Coefficient n takes operator t (0=I, 1=X, 2=Y, 3=Z) from bits (2t+1, 2t);
+qubit t is the t-th Kronecker factor from the right (T. Jones 2024, section 2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpauli.so")
+
+ALGOS = {"fp64_gray": 0, "fp32": 1, "split_bf16": 2}
+_DT = {torch.complex64: 0, torch.complex128: 1}
+_TORCH_DT = {0: torch.complex64, 1: torch.complex128}
+_STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSUPPORTED", 3: "EHIP", 4: "ENOMEM"}
+
+
+class PauliError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("pauli status %s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int), ("in_dtype", ctypes.c_int), ("out_dtype", ctypes.c_int),
+                ("tile", ctypes.c_int), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward",
+           "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_autotune",
+           "pauli_tile_count", "pauli_tile_selected", "pauli_last_error", "pauli_version"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpauli.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError("libpauli.so is not built (python -m paper_2401_16378_amd.build)")
+        lib = ctypes.CDLL(path)
+        vp, ci, op = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Opts)
+        lib.pauli_opts_default.argtypes = [op]
+        lib.pauli_opts_default.restype = None
+        for name in ("pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward"):
+            getattr(lib, name).argtypes = [vp, ci, ci, vp, op]
+            getattr(lib, name).restype = ci
+        lib.pauli_decompose_batched.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(ci),
+                                                ctypes.POINTER(vp), op]
+        lib.pauli_decompose_batched.restype = ci
+        lib.pauli_batched_workspace_bytes.argtypes = [ci]
+        lib.pauli_batched_workspace_bytes.restype = ctypes.c_size_t
+        lib.pauli_autotune.argtypes = [ci, ci, op]
+        lib.pauli_autotune.restype = ci
+        lib.pauli_tile_count.argtypes = [ci]
+        lib.pauli_tile_count.restype = ci
+        lib.pauli_tile_selected.argtypes = [ci, ci]
+        lib.pauli_tile_selected.restype = ci
+        lib.pauli_last_error.argtypes = []
+        lib.pauli_last_error.restype = ctypes.c_char_p
+        lib.pauli_version.argtypes = []
+        lib.pauli_version.restype = ci
+        _lib = lib
+        return lib
+
+
+def last_error() -> str:
+    return load_library().pauli_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise PauliError(status, last_error())
+
+
+def _opts(algo: str, in_dt: int, out_dt: int, tile: int = 0, stream=None, workspace=None) -> _Opts:
+    o = _Opts()
+    o.algo = ALGOS[algo]
+    o.in_dtype = in_dt
+    o.out_dtype = out_dt
+    o.tile = tile
+    o.stream = stream
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return o
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _qubits_of_matrix(G: torch.Tensor) -> int:
+    D = G.shape[-1]
+    if G.dim() < 2 or G.shape[-2] != D or D & (D - 1):
+        raise ValueError("expected [..., 2^N, 2^N], got %s" % (tuple(G.shape),))
+    return D.bit_length() - 1
+
+
+def _qubits_of_coeffs(c: torch.Tensor) -> int:
+    L = c.shape[-1]
+    N = (L.bit_length() - 1) // 2
+    if c.dim() < 1 or L != 1 << (2 * N):
+        raise ValueError("expected [..., 4^N], got %s" % (tuple(c.shape),))
+    return N
+
+
+def _prep(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("tensor must be on a GPU device")
+    if t.dtype not in _DT:
+        raise TypeError("tensor must be complex64 or complex128, got %s" % t.dtype)
+    return t.contiguous()
+
+
+def decompose(G: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: int = 0) -> torch.Tensor:
+    """c[..., n] = 2^-N Tr(P_n G[...]) for complex G of shape [..., 2^N, 2^N]."""
+    G = _prep(G)
+    N = _qubits_of_matrix(G)
+    out_dtype = out_dtype or G.dtype
+    batch = G.numel() // (1 << (2 * N))
+    out = torch.empty(G.shape[:-2] + (1 << (2 * N),), dtype=out_dtype, device=G.device)
+    o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G))
+    _check(load_library().pauli_decompose(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def reconstruct(c: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: int = 0) -> torch.Tensor:
+    """G = sum_n c_n P_n for c of shape [..., 4^N]."""
+    c = _prep(c)
+    N = _qubits_of_coeffs(c)
+    out_dtype = out_dtype or c.dtype
+    D = 1 << N
+    batch = c.numel() // (D * D)
+    G = torch.empty(c.shape[:-1] + (D, D), dtype=out_dtype, device=c.device)
+    o = _opts(algo, _DT[c.dtype], _DT[out_dtype], tile, _stream(c))
+    _check(load_library().pauli_reconstruct(c.data_ptr(), N, batch, G.data_ptr(), ctypes.byref(o)))
+    return G
+
+
+def decompose_backward(grad_c: torch.Tensor, algo: str = "split_bf16", out_dtype=None,
+                       tile: int = 0) -> torch.Tensor:
+    """Adjoint of decompose: 2^-N sum_n grad_c[n] P_n."""
+    g = _prep(grad_c)
+    N = _qubits_of_coeffs(g)
+    out_dtype = out_dtype or g.dtype
+    D = 1 << N
+    batch = g.numel() // (D * D)
+    G = torch.empty(g.shape[:-1] + (D, D), dtype=out_dtype, device=g.device)
+    o = _opts(algo, _DT[g.dtype], _DT[out_dtype], tile, _stream(g))
+    _check(load_library().pauli_decompose_backward(g.data_ptr(), N, batch, G.data_ptr(), ctypes.byref(o)))
+    return G
+
+
+_workspaces = {}
+
+
+def decompose_batched(mats, algo: str = "split_bf16", outs=None):
+    """Decompose complex64 matrices of uneven size in one persistent launch.
+    Returns a list of coefficient tensors (or fills `outs`)."""
+    mats = [_prep(m) for m in mats]
+    count = len(mats)
+    if count == 0:
+        return []
+    dev = mats[0].device
+    Ns = [_qubits_of_matrix(m) for m in mats]
+    if outs is None:
+        outs = [torch.empty(1 << (2 * n), dtype=torch.complex64, device=dev) for n in Ns]
+    lib = load_library()
+    need = lib.pauli_batched_workspace_bytes(count)
+    key = (dev, count)
+    ws = _workspaces.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        _workspaces[key] = ws
+    Gp = (ctypes.c_void_p * count)(*[m.data_ptr() for m in mats])
+    Op = (ctypes.c_void_p * count)(*[o.data_ptr() for o in outs])
+    Na = (ctypes.c_int * count)(*Ns)
+    o = _opts(algo, 0, 0, 0, _stream(mats[0]), ws)
+    _check(lib.pauli_decompose_batched(count, Gp, Na, Op, ctypes.byref(o)))
+    return outs
+
+
+def autotune(n_min: int, n_max: int, algo: str = "split_bf16", device=None) -> dict:
+    """Time every tile id for n_min..n_max and keep the fastest (blocking)."""
+    dev = torch.device(device or "cuda")
+    o = _opts(algo, 0, 0, 0, ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    lib = load_library()
+    _check(lib.pauli_autotune(n_min, n_max, ctypes.byref(o)))
+    return {n: lib.pauli_tile_selected(ALGOS[algo], n) for n in range(n_min, n_max + 1)}
+
+
+def tile_count(algo: str = "split_bf16") -> int:
+    return load_library().pauli_tile_count(ALGOS[algo])
+
+
+def tile_selected(N: int, algo: str = "split_bf16") -> int:
+    return load_library().pauli_tile_selected(ALGOS[algo], N)
+
+
+from .autograd import PauliDecompose  # noqa: E402
+
+__all__ = ["decompose", "reconstruct", "decompose_backward", "decompose_batched", "autotune",
+           "PauliDecompose", "PauliError", "load_library", "last_error", "ALGOS", "EXPORTS"]

@@ -1,0 +1,384 @@
+// C-ABI layer of libpauli: argument validation, algorithm/tile dispatch,
+// per-thread error messages, the tune table and the batched graph cache.
+// Every check runs before any HIP call, so invalid requests fail without a
+// device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pauli.h"
+#include "internal.hpp"
+
+using namespace pauli;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(PAULI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int N_MAX = 16;
+constexpr int N_MAX_BATCHED = 12;
+
+size_t elem_bytes(int dtype) { return dtype == PAULI_C128 ? 16 : 8; }
+
+bool valid_dtype(int d) { return d == PAULI_C64 || d == PAULI_C128; }
+bool valid_algo(int a) {
+    return a == PAULI_ALGO_FP64_GRAY || a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+pauli_opts resolve(const pauli_opts* o) {
+    pauli_opts r;
+    pauli_opts_default(&r);
+    if (o) r = *o;
+    return r;
+}
+
+// Tune table: (algo, N) -> tile id chosen by pauli_autotune.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tune;
+bool g_tune_loaded = false;
+
+void load_tune_cache_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("PAULI_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    // one entry per line: "algo N tile"
+    int a, n, t;
+    while (fscanf(f, "%d %d %d", &a, &n, &t) == 3) g_tune[{a, n}] = t;
+    fclose(f);
+}
+
+int planes_of(int algo) { return algo == PAULI_ALGO_SPLIT_BF16 ? 3 : 1; }
+
+int pick_tile(int algo, int N, int forced) {
+    if (algo == PAULI_ALGO_FP64_GRAY) return 0;
+    const int planes = planes_of(algo);
+    if (forced > 0) return forced;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    auto it = g_tune.find({algo, N});
+    if (it != g_tune.end() && mfma_tile_valid(planes, it->second, N)) return it->second;
+    return mfma_default_tile(planes, N);
+}
+
+int check_common(const void* in, int N, int batch, const void* out, const pauli_opts& o,
+                 const char* fn) {
+    if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
+    if (batch < 1) return fail(PAULI_EINVAL, "%s: batch=%d must be >= 1", fn, batch);
+    if (!in || !out) return fail(PAULI_EINVAL, "%s: NULL data pointer", fn);
+    if (!valid_algo(o.algo)) return fail(PAULI_EINVAL, "%s: unknown algo %d", fn, o.algo);
+    if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
+        return fail(PAULI_EINVAL, "%s: unknown dtype (in %d, out %d)", fn, o.in_dtype, o.out_dtype);
+    if ((uintptr_t)in % 16) return fail(PAULI_EINVAL, "%s: input not aligned to 16 bytes", fn);
+    if ((uintptr_t)out % 16) return fail(PAULI_EINVAL, "%s: output not aligned to 16 bytes", fn);
+    const size_t count = ((size_t)1 << (2 * N)) * (size_t)batch;
+    if (overlaps(in, count * elem_bytes(o.in_dtype), out, count * elem_bytes(o.out_dtype)))
+        return fail(PAULI_EINVAL, "%s: input and output overlap", fn);
+    if (o.tile < 0) return fail(PAULI_EINVAL, "%s: tile=%d must be >= 0", fn, o.tile);
+    if (o.tile > 0 && o.algo != PAULI_ALGO_FP64_GRAY &&
+        !mfma_tile_valid(planes_of(o.algo), o.tile, N))
+        return fail(PAULI_EINVAL, "%s: tile %d not valid for algo %d at N=%d", fn, o.tile, o.algo, N);
+    return PAULI_OK;
+}
+
+int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& o, double scale,
+        const char* fn) {
+    hipError_t e;
+    hipStream_t s = (hipStream_t)o.stream;
+    const bool in128 = o.in_dtype == PAULI_C128, out128 = o.out_dtype == PAULI_C128;
+    if (o.algo == PAULI_ALGO_FP64_GRAY) {
+        e = launch_gray(dir, in, in128, out, out128, N, batch, scale, s);
+    } else {
+        const int planes = planes_of(o.algo);
+        const int tile = pick_tile(o.algo, N, o.tile);
+        e = launch_mfma(dir, planes, in, in128, out, out128, N, batch, scale, tile, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, fn);
+    g_last_error.clear();
+    return PAULI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pauli_opts_default(pauli_opts* o) {
+    if (!o) return;
+    o->algo = PAULI_ALGO_SPLIT_BF16;
+    o->in_dtype = PAULI_C64;
+    o->out_dtype = PAULI_C64;
+    o->tile = 0;
+    o->stream = nullptr;
+    o->workspace = nullptr;
+    o->workspace_bytes = 0;
+}
+
+int pauli_decompose(const void* G, int N, int batch, void* out, const pauli_opts* opts) {
+    const pauli_opts o = resolve(opts);
+    int st = check_common(G, N, batch, out, o, "pauli_decompose");
+    if (st != PAULI_OK) return st;
+    return run(FORWARD, G, N, batch, out, o, 1.0 / (double)(1u << N), "pauli_decompose");
+}
+
+int pauli_reconstruct(const void* c, int N, int batch, void* G, const pauli_opts* opts) {
+    const pauli_opts o = resolve(opts);
+    int st = check_common(c, N, batch, G, o, "pauli_reconstruct");
+    if (st != PAULI_OK) return st;
+    return run(ADJOINT, c, N, batch, G, o, 1.0, "pauli_reconstruct");
+}
+
+int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
+                             const pauli_opts* opts) {
+    const pauli_opts o = resolve(opts);
+    int st = check_common(grad_c, N, batch, grad_G, o, "pauli_decompose_backward");
+    if (st != PAULI_OK) return st;
+    return run(ADJOINT, grad_c, N, batch, grad_G, o, 1.0 / (double)(1u << N),
+               "pauli_decompose_backward");
+}
+
+size_t pauli_batched_workspace_bytes(int count) {
+    if (count < 1) return 0;
+    return batched_workspace_bytes(count);
+}
+
+int pauli_tile_count(int algo) {
+    if (algo == PAULI_ALGO_FP64_GRAY) return 1;
+    if (!valid_algo(algo)) return 0;
+    return mfma_tile_count(planes_of(algo));
+}
+
+int pauli_tile_selected(int algo, int N) {
+    if (!valid_algo(algo) || N < 0 || N > N_MAX) return 0;
+    return pick_tile(algo, N, 0);
+}
+
+const char* pauli_last_error(void) { return g_last_error.c_str(); }
+
+int pauli_version(void) { return 1; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Uneven batch: persistent launch behind a cached HIP graph.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GraphKey {
+    hipStream_t stream;
+    void* workspace;
+    int planes;
+    std::vector<int> ns;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(stream, workspace, planes, ns) < std::tie(o.stream, o.workspace, o.planes, o.ns);
+    }
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> order;  // matrix index of every descriptor slot
+    int total_tiles = 0;
+    BatchItem* pinned = nullptr;  // host staging of the descriptor table
+    hipEvent_t copied = nullptr;  // staging may be rewritten once this fires
+};
+
+std::mutex g_graph_mu;
+std::map<GraphKey, GraphEntry> g_graphs;
+
+}  // namespace
+
+extern "C" int pauli_decompose_batched(int count, const void* const* G, const int* N,
+                                       void* const* out, const pauli_opts* opts) {
+    const char* fn = "pauli_decompose_batched";
+    const pauli_opts o = resolve(opts);
+    if (count < 1) return fail(PAULI_EINVAL, "%s: count=%d must be >= 1", fn, count);
+    if (!G || !N || !out) return fail(PAULI_EINVAL, "%s: NULL array", fn);
+    if (o.algo != PAULI_ALGO_SPLIT_BF16 && o.algo != PAULI_ALGO_FP32)
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d not available batched (SPLIT_BF16 or FP32)", fn,
+                    o.algo);
+    if (o.in_dtype != PAULI_C64 || o.out_dtype != PAULI_C64)
+        return fail(PAULI_EUNSUPPORTED, "%s: only C64 input and output", fn);
+    for (int k = 0; k < count; ++k) {
+        if (N[k] < 1 || N[k] > N_MAX_BATCHED)
+            return fail(PAULI_EINVAL, "%s: N[%d]=%d outside [1, %d]", fn, k, N[k], N_MAX_BATCHED);
+        if (!G[k] || !out[k]) return fail(PAULI_EINVAL, "%s: NULL pointer for matrix %d", fn, k);
+        if ((uintptr_t)G[k] % 16 || (uintptr_t)out[k] % 16)
+            return fail(PAULI_EINVAL, "%s: matrix %d not 16-byte aligned", fn, k);
+        const size_t bytes = ((size_t)1 << (2 * N[k])) * 8;
+        if (overlaps(G[k], bytes, out[k], bytes))
+            return fail(PAULI_EINVAL, "%s: input and output of matrix %d overlap", fn, k);
+    }
+    const size_t need = batched_workspace_bytes(count);
+    if (!o.workspace || o.workspace_bytes < need)
+        return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
+                    o.workspace ? o.workspace_bytes : (size_t)0);
+    if ((uintptr_t)o.workspace % 256)
+        return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+
+    const int planes = planes_of(o.algo);
+    hipStream_t s = (hipStream_t)o.stream;
+    GraphKey key{s, o.workspace, planes, std::vector<int>(N, N + count)};
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    GraphEntry& ge = g_graphs[key];
+    hipError_t e;
+    BatchItem* items_dev = (BatchItem*)o.workspace;
+    unsigned int* counter_dev =
+        (unsigned int*)((char*)o.workspace + ((sizeof(BatchItem) * count + 255) / 256) * 256);
+    if (!ge.exec) {
+        // Longest-processing-time order: largest matrices first.
+        ge.order.resize(count);
+        for (int k = 0; k < count; ++k) ge.order[k] = k;
+        std::stable_sort(ge.order.begin(), ge.order.end(),
+                         [&](int a, int b) { return N[a] > N[b]; });
+        int tiles = 0;
+        for (int k = 0; k < count; ++k) tiles += batched_tiles_for(N[ge.order[k]]);
+        ge.total_tiles = tiles;
+        if ((e = hipHostMalloc((void**)&ge.pinned, sizeof(BatchItem) * count)) != hipSuccess) {
+            g_graphs.erase(key);
+            return hip_fail(e, fn);
+        }
+        if ((e = hipEventCreateWithFlags(&ge.copied, hipEventDisableTiming)) != hipSuccess) {
+            g_graphs.erase(key);
+            return hip_fail(e, fn);
+        }
+        hipStream_t cap;
+        if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, fn);
+        hipGraph_t graph;
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_batched(planes, items_dev, count, ge.total_tiles, counter_dev, cap);
+            e = hipStreamEndCapture(cap, &graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+        }
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) {
+            ge.exec = nullptr;
+            return hip_fail(e, fn);
+        }
+    }
+    // Refresh the descriptor table (pointers may differ between calls).
+    if ((e = hipEventSynchronize(ge.copied)) != hipSuccess) return hip_fail(e, fn);
+    int tile0 = 0;
+    for (int slot = 0; slot < count; ++slot) {
+        const int k = ge.order[slot];
+        ge.pinned[slot].in = G[k];
+        ge.pinned[slot].out = out[k];
+        ge.pinned[slot].n = N[k];
+        ge.pinned[slot].tile0 = tile0;
+        tile0 += batched_tiles_for(N[k]);
+    }
+    if ((e = hipMemcpyAsync(items_dev, ge.pinned, sizeof(BatchItem) * count, hipMemcpyHostToDevice,
+                            s)) != hipSuccess)
+        return hip_fail(e, fn);
+    if ((e = hipEventRecord(ge.copied, s)) != hipSuccess) return hip_fail(e, fn);
+    if ((e = hipGraphLaunch(ge.exec, s)) != hipSuccess) return hip_fail(e, fn);
+    g_last_error.clear();
+    return PAULI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: time each tile id per N on scratch matrices, keep the fastest.
+// ---------------------------------------------------------------------------
+extern "C" int pauli_autotune(int N_min, int N_max, const pauli_opts* opts) {
+    const char* fn = "pauli_autotune";
+    pauli_opts o = resolve(opts);
+    if (o.algo != PAULI_ALGO_SPLIT_BF16 && o.algo != PAULI_ALGO_FP32)
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no tile choice", fn, o.algo);
+    if (N_min < 1 || N_max > N_MAX || N_min > N_max)
+        return fail(PAULI_EINVAL, "%s: bad range [%d, %d]", fn, N_min, N_max);
+    const int planes = planes_of(o.algo);
+    hipStream_t s = (hipStream_t)o.stream;
+    hipError_t e;
+    for (int N = N_min; N <= N_max; ++N) {
+        const size_t elems = (size_t)1 << (2 * N);
+        void *in = nullptr, *out = nullptr;
+        if ((e = hipMalloc(&in, elems * 8)) != hipSuccess) return hip_fail(e, fn);
+        if ((e = hipMalloc(&out, elems * 8)) != hipSuccess) {
+            (void)hipFree(in);
+            return hip_fail(e, fn);
+        }
+        // the data values do not affect timing; zero is enough
+        hipEvent_t a = nullptr, b = nullptr;
+        e = hipMemsetAsync(in, 0, elems * 8, s);
+        if (e == hipSuccess) e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        int best = 0;
+        float best_ms = 1e30f;
+        const int ntiles = mfma_tile_count(planes);
+        const int reps = N >= 12 ? 2 : (N >= 9 ? 5 : 20);
+        for (int t = 1; t <= ntiles && e == hipSuccess; ++t) {
+            if (!mfma_tile_valid(planes, t, N)) continue;
+            double sc = 1.0 / (double)(1u << N);
+            e = launch_mfma(FORWARD, planes, in, false, out, false, N, 1, sc, t, s);  // warm-up
+            if (e != hipSuccess) break;
+            e = hipEventRecord(a, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = launch_mfma(FORWARD, planes, in, false, out, false, N, 1, sc, t, s);
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        (void)hipFree(in);
+        (void)hipFree(out);
+        if (e != hipSuccess) return hip_fail(e, fn);
+        if (best > 0) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            load_tune_cache_locked();
+            g_tune[{o.algo, N}] = best;
+        }
+    }
+    const char* path = getenv("PAULI_TUNE_CACHE");
+    if (path) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        FILE* f = fopen(path, "w");
+        if (!f) return fail(PAULI_EINVAL, "%s: cannot write %s", fn, path);
+        for (auto& kv : g_tune) fprintf(f, "%d %d %d\n", kv.first.first, kv.first.second, kv.second);
+        fclose(f);
+    }
+    g_last_error.clear();
+    return PAULI_OK;
+}
