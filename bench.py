@@ -1,0 +1,208 @@
+"""Benchmark of the dense Pauli decomposition on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--N 14] [--no-cpu] [--no-fp64]
+
+Workload: one complex64 Hermitian 16384 x 16384 matrix (N = 14 qubits),
+G = (A + A^H)/2 with A iid complex N(0,1) (numpy PCG64, seed 1014), resident in
+HBM before timing.  One step = one full decomposition into all 4^14
+coefficients (complex64 out) with the split-bf16 MFMA path
+(gather, exact 3-way bf16 split, +-1 contraction, binary64 recombination,
+phase, 2^-N, store) -- a single kernel launch.
+
+Printed: one JSON line with coefficients/s, the roofline of that kernel
+(executed bf16 MFMA flops per launch / mean launch time, against the 2.5
+PFLOP/s dense bf16 peak), the binary64 Gray-code GPU kernel on the same input
+for the speed ratio and the error (max |c - c_fp64| / max |c_fp64|), and the
+CPU oracle timed on a bounded sample of the same coefficients on the host's
+cores (which also checks those coefficients).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "Pauli coeffs/sec + % MFMA peak at N=14, split-BF16 vs FP64 at err≤1e-6"
+PEAK_BF16_TFLOPS = 2500.0
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2401_16378_amd/csrc/mfma.hip", "paper_2401_16378_amd/csrc/common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_bf16_n14.json")
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the kernel as it stands now."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(G64: np.ndarray, c_gpu: np.ndarray, sample: int):
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    N = G64.shape[0].bit_length() - 1
+    import workloads
+    ns = workloads.sample_indices(4 ** N, sample, seed=workloads.SEED_SAMPLE)
+    t0 = time.perf_counter()
+    ref = oracle.coeffs_at(G64, ns, threads=cores)
+    dt = time.perf_counter() - t0
+    got = c_gpu[ns.astype(np.int64)]
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    return {"value": sample / dt, "unit": "coeffs/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of the 4^%d coefficients (uniform without replacement, seed %d) of the same "
+                      "matrix, binary64 Gray-code oracle, %d threads over disjoint ranges, %.1f s"
+                      % (sample, N, workloads.SEED_SAMPLE, cores, dt)}, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=14)
+    ap.add_argument("--algo", default="split_bf16")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=131072)
+    ap.add_argument("--fp64-reps", type=int, default=3)
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="also run a device copy of this many GiB (counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2401_16378_amd as pauli
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N = a.N
+    log("[bench] generating N=%d Hermitian complex64 input (seed %d)" % (N, workloads.SEED_N14))
+    t0 = time.perf_counter()
+    G = workloads.hermitian(N, workloads.SEED_N14)
+    log("[bench] generated in %.1f s" % (time.perf_counter() - t0))
+    Gd = torch.from_numpy(G).to(dev)
+    out = torch.empty(1 << (2 * N), dtype=torch.complex64, device=dev)
+    lib = pauli.load_library()
+    import ctypes
+    stream = torch.cuda.current_stream(dev)
+    o = pauli._opts(a.algo, 0, 0, a.tile, ctypes.c_void_p(stream.cuda_stream))
+
+    def step():
+        st = lib.pauli_decompose(Gd.data_ptr(), N, 1, out.data_ptr(), ctypes.byref(o))
+        if st != 0:
+            raise RuntimeError(pauli.last_error())
+
+    if a.copy_probe_gib > 0:
+        nb = int(a.copy_probe_gib * (1 << 30))
+        src = torch.empty(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("[bench] warm-up done; timing %d steps" % a.steps)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        evs[s][0].record(stream)
+        step()
+        evs[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [b.elapsed_time(e) for b, e in evs]
+    ms_step = wall * 1000.0 / a.steps
+    mean_launch = float(np.mean(launch_ms))
+    coeffs = float(4 ** N)
+    value = coeffs / (ms_step / 1000.0)
+    planes = 3 if a.algo == "split_bf16" else 1
+    flops_exec = 2.0 * 2.0 * planes * float(8 ** N)   # 2 (re,im) x 2 flop/MAC x planes x D^3
+    flops_useful = 4.0 * float(8 ** N)
+    achieved = flops_exec / (mean_launch / 1000.0) / 1e12
+    peak = PEAK_BF16_TFLOPS if a.algo == "split_bf16" else 157.3
+    log("[bench] %.3f ms/step, %.3f ms/launch, %.1f TFLOP/s executed" % (ms_step, mean_launch, achieved))
+
+    c_bf16 = out.cpu().numpy()
+    res = {}
+    if not a.no_fp64:
+        out64 = torch.empty(1 << (2 * N), dtype=torch.complex128, device=dev)
+        o64 = pauli._opts("fp64_gray", 0, 1, 0, ctypes.c_void_p(stream.cuda_stream))
+        st = lib.pauli_decompose(Gd.data_ptr(), N, 1, out64.data_ptr(), ctypes.byref(o64))
+        if st != 0:
+            raise RuntimeError(pauli.last_error())
+        torch.cuda.synchronize()
+        b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.record(stream)
+        for _ in range(a.fp64_reps):
+            lib.pauli_decompose(Gd.data_ptr(), N, 1, out64.data_ptr(), ctypes.byref(o64))
+        e.record(stream)
+        torch.cuda.synchronize()
+        fp64_ms = b.elapsed_time(e) / a.fp64_reps
+        c64 = out64.cpu().numpy()
+        err = float(np.abs(c_bf16 - c64).max() / np.abs(c64).max())
+        im_ratio = float(np.abs(c64.imag).max() / np.abs(c64).max())
+        res.update({"fp64_gray_ms": round(fp64_ms, 3), "speedup_vs_fp64_gray": round(fp64_ms / mean_launch, 2),
+                    "max_err_vs_fp64": err, "fp64_imag_ratio": im_ratio})
+        log("[bench] fp64 gray %.1f ms, ratio %.2f, err %.3g" % (fp64_ms, fp64_ms / mean_launch, err))
+        del out64
+
+    cpu = None
+    if not a.no_cpu:
+        log("[bench] timing the CPU oracle on a %d-coefficient sample" % a.cpu_sample)
+        cpu, err_cpu = cpu_baseline(G.astype(np.complex128), c_bf16.astype(np.complex128), a.cpu_sample)
+        res["max_err_vs_oracle_sample"] = err_cpu
+        log("[bench] oracle %.0f coeffs/s on %d cores, sample err %.3g" % (cpu["value"], cpu["cores"], err_cpu))
+
+    traffic = measured_traffic()
+    line = {
+        "metric": METRIC, "value": value, "unit": "coeffs/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16" if a.algo == "split_bf16" else "f32", "data": "synthetic",
+        "config": {"workload": "dense Pauli decomposition, N=%d (%dx%d complex64 Hermitian, "
+                               "G=(A+A^H)/2, A iid N(0,1)), all 4^%d coefficients, %s"
+                               % (N, 1 << N, 1 << N, N, a.algo), "N": N, "batch": 1,
+                   "algo": a.algo, "tile": pauli.tile_selected(N, a.algo) if a.tile == 0 else a.tile},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "useful_frac": flops_useful / (mean_launch / 1000.0) / 1e12 / peak,
+                     "launch_ms": mean_launch, "flops_per_launch": flops_exec},
+        "cpu_baseline": cpu,
+    }
+    line.update(res)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

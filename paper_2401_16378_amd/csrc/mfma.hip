@@ -16,11 +16,11 @@
 // registers and picks them at compile time, with one extra sign per wave and
 // K-tile.
 //
-// Precision.  PLANES = 3: each binary32 component g is split exactly as
-// g = hi + mid + lo with hi = bf16(g), mid = bf16(g - hi), lo = g - hi - mid
-// (exact in bf16 for normal g); bf16 MFMA accumulates hi into one FP32
-// accumulator and mid + lo into a second, and the two are added in binary64
-// in the epilogue before the phase and scale.  PLANES = 1: binary32 MFMA on
+// Precision.  PLANES = 3: each binary32 component g is split as
+// g ~ hi + mid + lo (three bf16 numbers, hi on a power-of-two grid shared by
+// the 4x4 micro-block, see split3); bf16 MFMA accumulates hi into one FP32
+// accumulator, where the sums stay exact, and mid + lo into a second, and the
+// two are added in binary64 in the epilogue before the phase and scale.  PLANES = 1: binary32 MFMA on
 // the binary32 components.
 //
 // Tiling.  A workgroup owns 32 flip masks x (64 real B columns: re then im)
@@ -54,13 +54,34 @@ __device__ inline uint32_t pack_bf16(float a, float b) {
 __device__ inline float lo_half(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
 __device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u & 0xFFFF0000u); }
 
-// Exact three-way bf16 split of two binary32 values (round-to-nearest-even).
-__device__ inline void split3(float a, float b, uint32_t& h, uint32_t& m, uint32_t& l) {
-    h = pack_bf16(a, b);
-    const float ra = a - lo_half(h), rb = b - hi_half(h);
+// Three-way bf16 split of two binary32 values a, b against a power-of-two
+// grid u (with inv_u = 1/u, both exact):
+//   hi  = u * rint(x / u)        (|x| < 256 u, so hi has <= 8 significant bits
+//                                 and is exact in bf16)
+//   mid = bf16(x - hi),  lo = bf16(x - hi - mid)
+// x - hi and x - hi - mid are exact in binary32, so hi + mid + lo carries
+// every bit of x except at most those below 2^-17 |x - hi|.  All hi terms of
+// a micro-block are multiples of the same u, which keeps the FP32 sums of hi
+// terms exact over the whole K range for any input whose partial sums stay
+// below 2^24 times the smallest grid (about 2^16 times the smallest block
+// maximum), instead of rounding away the low bits of small terms.
+__device__ inline void split3(float a, float b, float u, float inv_u, uint32_t& h, uint32_t& m,
+                              uint32_t& l) {
+    const float ha = __builtin_rintf(a * inv_u) * u, hb = __builtin_rintf(b * inv_u) * u;
+    h = pack_bf16(ha, hb);
+    const float ra = a - ha, rb = b - hb;
     m = pack_bf16(ra, rb);
     const float qa = ra - lo_half(m), qb = rb - hi_half(m);
     l = pack_bf16(qa, qb);
+}
+
+// Grid of a micro-block: u = 2^(e-8) for the exponent e with max|x| < 2^e,
+// clamped so that u and 1/u stay normal binary32 numbers.
+__device__ inline void block_grid(float maxabs, float& u, float& inv_u) {
+    int e = (int)((__builtin_bit_cast(uint32_t, maxabs) >> 23) & 0xFFu) - 126;
+    e = e < -110 ? -110 : (e > 120 ? 120 : e);
+    u = __builtin_bit_cast(float, (uint32_t)(127 + e - 8) << 23);
+    inv_u = __builtin_bit_cast(float, (uint32_t)(127 - e + 8) << 23);
 }
 
 template <int PLANES, int RB, int WAVES>
@@ -84,29 +105,34 @@ struct Params {
     const void* in;
     void* out;
     int N;
-    int in128;
     int out128;
     double scale;
 };
 
-__device__ inline f32x2 load_elem(const void* base, size_t idx, int is128) {
-    if (is128) {
+template <bool IN128>
+__device__ inline f32x2 load_elem(const unsigned char* base, size_t idx) {
+    if constexpr (IN128) {
         const double2 v = ((const double2*)base)[idx];
         return f32x2{(float)v.x, (float)v.y};
+    } else {
+        const float2 v = ((const float2*)base)[idx];
+        return f32x2{v.x, v.y};
     }
-    const float2 v = ((const float2*)base)[idx];
-    return f32x2{v.x, v.y};
 }
 
-template <int PLANES, int RB, int WAVES, int DIR>
+template <int PLANES, int RB, int WAVES, int DIR, bool IN128>
 __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
     using C = Cfg<PLANES, RB, WAVES>;
     constexpr int KT = C::KT;
     constexpr int ACC = PLANES == 3 ? 2 : 1;
+    constexpr int UPT = C::UPT;
+    constexpr int NPARTS = 4 * UPT;                          // deposit pieces per K-tile
+    constexpr int S = PLANES == 3 ? KT / 16 : KT / 8;        // K-slices per tile
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
 
     const int N = prm.N;
     const uint32_t D = 1u << N;
+    const bool full = D >= 32u;                               // no padding needed
     const uint32_t nMB = D > (uint32_t)C::MT ? D / C::MT : 1u;   // row blocks
     const uint32_t nK = D > (uint32_t)KT ? D / KT : 1u;          // K tiles
     const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
@@ -116,31 +142,40 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
     const int l32 = lane & 31, h = lane >> 5;
     const uint32_t Pw = mb * C::MT + wave * RB * 32;            // first row of this wave
     const size_t mat = (size_t)D * D;
-    const unsigned char* src = (const unsigned char*)prm.in + (size_t)blockIdx.y * mat * (prm.in128 ? 16 : 8);
+    const unsigned char* src = (const unsigned char*)prm.in + (size_t)blockIdx.y * mat * (IN128 ? 16 : 8);
     unsigned char* dst = (unsigned char*)prm.out + (size_t)blockIdx.y * mat * (prm.out128 ? 16 : 8);
 
-    // ---- prologue: fetch one K-tile (registers) and deposit it (LDS) ----
-    f32x2 stg[C::UPT][16];
+    // ---- prologue pieces: fetch a K-tile into registers, deposit it into LDS ----
+    f32x2 stg[UPT][16];
+    float gu[UPT], ginv[UPT];
     auto fetch = [&](uint32_t kt) {
         const uint32_t Q0 = kt * KT;
 #pragma unroll
-        for (int u = 0; u < C::UPT; ++u) {
+        for (int u = 0; u < UPT; ++u) {
             const int ub = tid + u * C::NT;
-            if (ub >= C::UBLK) break;
+            if constexpr (C::UBLK < UPT * C::NT) {
+                if (ub >= C::UBLK) break;
+            }
             const int g = ub >> 6, w6 = ub & 63;   // 32x32 square g of the tile, block w6 in it
-            if (DIR == FORWARD) {
+            if constexpr (DIR == FORWARD) {
                 const int mr = w6 >> 3, mc = w6 & 7;
                 const uint32_t q0 = Q0 + 32 * g + 4 * mc;
-                const uint32_t r0 = ((Q0 + 32 * g) ^ X0) & ~31u;
+                const uint32_t r0 = (((Q0 + 32 * g) ^ X0) & ~31u) + 4 * mr;
+                if (full) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const uint32_t r = r0 + 4 * mr + a;
+                    for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const uint32_t q = q0 + b;
-                        stg[u][a * 4 + b] = (r < D && q < D) ? load_elem(src, (size_t)r * D + q, prm.in128)
-                                                             : f32x2{0.f, 0.f};
-                    }
+                        for (int b = 0; b < 4; ++b)
+                            stg[u][a * 4 + b] = load_elem<IN128>(src, (size_t)(r0 + a) * D + q0 + b);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const uint32_t r = r0 + a, q = q0 + b;
+                            stg[u][a * 4 + b] = (r < D && q < D) ? load_elem<IN128>(src, (size_t)r * D + q)
+                                                                 : f32x2{0.f, 0.f};
+                        }
                 }
             } else {
                 const uint32_t zb = Q0 + 32 * g;
@@ -150,71 +185,79 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
                     const uint32_t o = 16 * w6 + r;
                     const uint32_t zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
                     const uint32_t z = zb + zl, x = X0 + xl;
-                    f32x2 v = {0.f, 0.f};
-                    if (z < D && x < D) {
-                        const f32x2 c = load_elem(src, nb + o, prm.in128);
-                        float re = c.x, im = c.y;
-                        rotate_minus_i(re, im, 3u * (uint32_t)__popc(x & z));  // i^{popc}
-                        v = f32x2{re, im};
-                    }
-                    stg[u][r] = v;
+                    f32x2 c = {0.f, 0.f};
+                    if (full || (z < D && x < D)) c = load_elem<IN128>(src, nb + o);
+                    float re = c.x, im = c.y;
+                    rotate_minus_i(re, im, 3u * (uint32_t)__popc(x & z));  // i^{popc(x&z)}
+                    stg[u][r] = f32x2{re, im};
                 }
             }
         }
     };
-    auto deposit = [&](int buf) {
-        unsigned char* base = lds + buf * C::BUF;
+    // grid of micro-block u (split-bf16 only)
+    auto grid = [&](int u) {
+        float mx = 0.f;
 #pragma unroll
-        for (int u = 0; u < C::UPT; ++u) {
-            const int ub = tid + u * C::NT;
-            if (ub >= C::UBLK) break;
-            const int g = ub >> 6, w6 = ub & 63;
-            int xh, kh;  // micro-block column group (x_l / 4) and first K slot
-            if (DIR == FORWARD) {
-                const int mr = w6 >> 3, mc = w6 & 7;
-                xh = mr ^ mc;
-                kh = 32 * g + 4 * mc;
+        for (int r = 0; r < 16; ++r)
+            mx = __builtin_fmaxf(mx, __builtin_fmaxf(__builtin_fabsf(stg[u][r].x), __builtin_fabsf(stg[u][r].y)));
+        block_grid(mx, gu[u], ginv[u]);
+    };
+    // row x2 of micro-block u: 4 consecutive K slots of one column, all planes
+    auto deposit_part = [&](int buf, int u, int x2) {
+        const int ub = tid + u * C::NT;
+        if constexpr (C::UBLK < UPT * C::NT) {
+            if (ub >= C::UBLK) return;
+        }
+        const int g = ub >> 6, w6 = ub & 63;
+        if constexpr (PLANES == 3) {
+            if (x2 == 0) grid(u);
+        }
+        int xh, kh;  // column group (x_l / 4) and first K slot of the micro-block
+        if constexpr (DIR == FORWARD) {
+            const int mr = w6 >> 3, mc = w6 & 7;
+            xh = mr ^ mc;
+            kh = 32 * g + 4 * mc;
+        } else {
+            // 16 consecutive coefficients o = 16*w6 + r, r = (x^z)_0 | z_0<<1 | (x^z)_1<<2 | z_1<<3
+            const uint32_t o = 16 * w6;
+            const int zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
+            xh = xl >> 2;
+            kh = 32 * g + zl;
+        }
+        f32x2 e[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if constexpr (DIR == FORWARD) {
+                e[b] = stg[u][((x2 ^ b) << 2) | b];  // row a = x2 ^ b, column b
             } else {
-                // 16 consecutive coefficients: o = 16*w6 + r, r = (x^z)_0 | z_0<<1 | (x^z)_1<<2 | z_1<<3
-                const uint32_t o = 16 * w6;
-                const int zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
-                xh = xl >> 2;
-                kh = 32 * g + zl;
-            }
-#pragma unroll
-            for (int x2 = 0; x2 < 4; ++x2) {
-                f32x2 e[4];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if (DIR == FORWARD) {
-                        e[b] = stg[u][((x2 ^ b) << 2) | b];  // row a = x2 ^ b, column b
-                    } else {
-                        const int d = x2 ^ b;                 // (x ^ z) low bits
-                        e[b] = stg[u][(d & 1) | ((b & 1) << 1) | ((d >> 1) << 2) | ((b >> 1) << 3)];
-                    }
-                }
-                const int col = xh * 4 + x2;
-                unsigned char* cbase = base + col * C::PITCH + kh * C::ESZ;
-                if constexpr (PLANES == 3) {
-                    uint32_t hr0, mr0, lr0, hr1, mr1, lr1, hi0, mi0, li0, hi1, mi1, li1;
-                    split3(e[0].x, e[1].x, hr0, mr0, lr0);
-                    split3(e[2].x, e[3].x, hr1, mr1, lr1);
-                    split3(e[0].y, e[1].y, hi0, mi0, li0);
-                    split3(e[2].y, e[3].y, hi1, mi1, li1);
-                    constexpr int PS = XT * C::PITCH;  // plane stride
-                    *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
-                    *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
-                    *(u32x2*)(cbase + 2 * PS) = u32x2{mr0, mr1};
-                    *(u32x2*)(cbase + 3 * PS) = u32x2{mi0, mi1};
-                    *(u32x2*)(cbase + 4 * PS) = u32x2{lr0, lr1};
-                    *(u32x2*)(cbase + 5 * PS) = u32x2{li0, li1};
-                } else {
-                    constexpr int PS = XT * C::PITCH;
-                    *(f32x4*)(cbase) = f32x4{e[0].x, e[1].x, e[2].x, e[3].x};
-                    *(f32x4*)(cbase + PS) = f32x4{e[0].y, e[1].y, e[2].y, e[3].y};
-                }
+                const int d = x2 ^ b;                 // (x ^ z) low bits
+                e[b] = stg[u][(d & 1) | ((b & 1) << 1) | ((d >> 1) << 2) | ((b >> 1) << 3)];
             }
         }
+        unsigned char* cbase = lds + buf * C::BUF + (xh * 4 + x2) * C::PITCH + kh * C::ESZ;
+        constexpr int PS = XT * C::PITCH;  // plane stride
+        if constexpr (PLANES == 3) {
+            uint32_t hr0, mr0, lr0, hr1, mr1, lr1, hi0, mi0, li0, hi1, mi1, li1;
+            split3(e[0].x, e[1].x, gu[u], ginv[u], hr0, mr0, lr0);
+            split3(e[2].x, e[3].x, gu[u], ginv[u], hr1, mr1, lr1);
+            split3(e[0].y, e[1].y, gu[u], ginv[u], hi0, mi0, li0);
+            split3(e[2].y, e[3].y, gu[u], ginv[u], hi1, mi1, li1);
+            *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
+            *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
+            *(u32x2*)(cbase + 2 * PS) = u32x2{mr0, mr1};
+            *(u32x2*)(cbase + 3 * PS) = u32x2{mi0, mi1};
+            *(u32x2*)(cbase + 4 * PS) = u32x2{lr0, lr1};
+            *(u32x2*)(cbase + 5 * PS) = u32x2{li0, li1};
+        } else {
+            *(f32x4*)(cbase) = f32x4{e[0].x, e[1].x, e[2].x, e[3].x};
+            *(f32x4*)(cbase + PS) = f32x4{e[0].y, e[1].y, e[2].y, e[3].y};
+        }
+    };
+    auto deposit_all = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < UPT; ++u)
+#pragma unroll
+            for (int x2 = 0; x2 < 4; ++x2) deposit_part(buf, u, x2);
     };
 
     // ---- sign fragments of the 32x32 Sylvester block ----
@@ -252,17 +295,20 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
                 for (int r = 0; r < 16; ++r) acc[a][rb][cb][r] = 0.f;
 
     fetch(0);
-    deposit(0);
+    deposit_all(0);
     __syncthreads();
     for (uint32_t kt = 0; kt < nK; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nK) fetch(kt + 1);
+        // Next tile's loads go out now; its split and LDS writes are spread over
+        // the second half of this tile's K-slices so they overlap the MFMAs.
+        // On the last tile the last tile is fetched again into the idle buffer.
+        fetch(kt + 1 < nK ? kt + 1 : kt);
         // sign of this wave's rows against this K-tile from the bits above the tile
         const bool neg_tile = __popc((Pw >> 5) & ((kt * KT) >> 5)) & 1;
         const unsigned char* bbase = lds + buf * C::BUF + l32 * C::PITCH;
+        bf16x8 Ap[2], An[2];
         if constexpr (PLANES == 3) {
             const uint32_t tm = neg_tile ? 0x80008000u : 0u;
-            bf16x8 Ap[2], An[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 u32x4 p = {fA[e][0] ^ tm, fA[e][1] ^ tm, fA[e][2] ^ tm, fA[e][3] ^ tm};
@@ -270,15 +316,17 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
                 Ap[e] = __builtin_bit_cast(bf16x8, p);
                 An[e] = __builtin_bit_cast(bf16x8, n);
             }
+        }
+        const float ts = neg_tile ? -1.f : 1.f;
 #pragma unroll
-            for (int s = 0; s < KT / 16; ++s) {
+        for (int s = 0; s < S; ++s) {
+            if constexpr (PLANES == 3) {
                 bf16x8 B[3][2];
 #pragma unroll
                 for (int pl = 0; pl < 3; ++pl)
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb)
-                        B[pl][cb] = *(const bf16x8*)(bbase + (pl * 2 + cb) * XT * C::PITCH +
-                                                     (16 * s + 8 * h) * 2);
+                        B[pl][cb] = *(const bf16x8*)(bbase + (pl * 2 + cb) * XT * C::PITCH + (16 * s + 8 * h) * 2);
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
                     const bool neg = popc_const((uint32_t)rb & (uint32_t)(s >> 1)) & 1;
@@ -290,11 +338,7 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
                         acc[ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B[2][cb], acc[ACC - 1][rb][cb], 0, 0, 0);
                     }
                 }
-            }
-        } else {
-            const float ts = neg_tile ? -1.f : 1.f;
-#pragma unroll
-            for (int s = 0; s < KT / 8; ++s) {
+            } else {
                 f32x4 B[2];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
@@ -311,8 +355,33 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
                     }
                 }
             }
+            // deposit pieces scheduled after this slice
+            int nparts = 0;
+#pragma unroll
+            for (int part = 0; part < NPARTS; ++part) {
+                constexpr int H0 = S / 2;
+                const int sp = H0 + part * (S - H0) / NPARTS;
+                if (sp == s) {
+                    deposit_part(buf ^ 1, part / 4, part % 4);
+                    ++nparts;
+                }
+            }
+            // Scheduling: this slice's LDS reads first, then its MFMAs with the
+            // split arithmetic of the deposit pieces threaded between them, then
+            // the pieces' LDS writes.
+            constexpr int MF = PLANES == 3 ? RB * 6 : RB * 8;   // MFMAs per slice
+            __builtin_amdgcn_sched_group_barrier(0x100, PLANES == 3 ? 6 : 2, 0);
+            if (nparts > 0) {
+#pragma unroll
+                for (int i = 0; i < MF; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, PLANES == 3 ? 6 : 2, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x200, 16, 0);
+            } else {
+                __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
+            }
         }
-        if (kt + 1 < nK) deposit(buf ^ 1);
         __syncthreads();
     }
 
@@ -335,7 +404,7 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
             re *= scale;
             im *= scale;
             uint32_t slot;
-            if (DIR == FORWARD) {
+            if constexpr (DIR == FORWARD) {
                 rotate_minus_i(re, im, (uint32_t)__popc((X0 + l32) & (pb + pl)));
                 slot = pauli_index((uint32_t)l32, pl);           // offset inside the 1024-run
             } else {
@@ -345,7 +414,7 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
             else *(float2*)(stage + slot * 8) = make_float2((float)re, (float)im);
         }
         __syncthreads();
-        if (DIR == FORWARD) {
+        if constexpr (DIR == FORWARD) {
             // contiguous run of min(1024, 4^N) coefficients starting at n(X0, pb)
             const uint32_t run = D < 32u ? D * D : 1024u;
             unsigned char* o = dst + (size_t)pauli_index(X0, pb) * esz;
@@ -392,12 +461,12 @@ constexpr TileDesc TILES[] = {
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
 template <int PLANES, int RB, int WAVES, int DIR>
-hipError_t launch_cfg(const Params& p, int batch, hipStream_t s) {
+hipError_t launch_cfg(const Params& p, bool in128, int batch, hipStream_t s) {
     using C = Cfg<PLANES, RB, WAVES>;
     const uint32_t D = 1u << p.N;
     const uint32_t nMB = D > (uint32_t)C::MT ? D / C::MT : 1u;
     const uint32_t nXB = D > (uint32_t)XT ? D / XT : 1u;
-    auto kern = mfma_kernel<PLANES, RB, WAVES, DIR>;
+    auto kern = in128 ? mfma_kernel<PLANES, RB, WAVES, DIR, true> : mfma_kernel<PLANES, RB, WAVES, DIR, false>;
     const int lds = C::lds_bytes(p.out128 ? 16 : 8);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
@@ -406,14 +475,14 @@ hipError_t launch_cfg(const Params& p, int batch, hipStream_t s) {
 }
 
 template <int PLANES, int DIR>
-hipError_t launch_tile(int tile, const Params& p, int batch, hipStream_t s) {
+hipError_t launch_tile(int tile, const Params& p, bool in128, int batch, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_cfg<PLANES, 4, 4, DIR>(p, batch, s);
-        case 2: return launch_cfg<PLANES, 2, 4, DIR>(p, batch, s);
-        case 3: return launch_cfg<PLANES, 2, 8, DIR>(p, batch, s);
-        case 4: return launch_cfg<PLANES, 1, 4, DIR>(p, batch, s);
-        case 5: return launch_cfg<PLANES, 1, 1, DIR>(p, batch, s);
-        case 6: return launch_cfg<PLANES, 1, 2, DIR>(p, batch, s);
+        case 1: return launch_cfg<PLANES, 4, 4, DIR>(p, in128, batch, s);
+        case 2: return launch_cfg<PLANES, 2, 4, DIR>(p, in128, batch, s);
+        case 3: return launch_cfg<PLANES, 2, 8, DIR>(p, in128, batch, s);
+        case 4: return launch_cfg<PLANES, 1, 4, DIR>(p, in128, batch, s);
+        case 5: return launch_cfg<PLANES, 1, 1, DIR>(p, in128, batch, s);
+        case 6: return launch_cfg<PLANES, 1, 2, DIR>(p, in128, batch, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -444,12 +513,12 @@ hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* 
                        hipStream_t stream) {
     if (tile == 0) tile = mfma_default_tile(planes, N);
     if (!mfma_tile_valid(planes, tile, N)) return hipErrorInvalidValue;
-    Params p{in, out, N, in_c128 ? 1 : 0, out_c128 ? 1 : 0, scale};
+    Params p{in, out, N, out_c128 ? 1 : 0, scale};
     if (planes == 3)
-        return dir == FORWARD ? launch_tile<3, FORWARD>(tile, p, batch, stream)
-                              : launch_tile<3, ADJOINT>(tile, p, batch, stream);
-    return dir == FORWARD ? launch_tile<1, FORWARD>(tile, p, batch, stream)
-                          : launch_tile<1, ADJOINT>(tile, p, batch, stream);
+        return dir == FORWARD ? launch_tile<3, FORWARD>(tile, p, in_c128, batch, stream)
+                              : launch_tile<3, ADJOINT>(tile, p, in_c128, batch, stream);
+    return dir == FORWARD ? launch_tile<1, FORWARD>(tile, p, in_c128, batch, stream)
+                          : launch_tile<1, ADJOINT>(tile, p, in_c128, batch, stream);
 }
 
 }  // namespace pauli
