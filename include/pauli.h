@@ -20,9 +20,11 @@
  *
  * Memory: every data pointer (G, coefficients, gradients, workspace) is a
  * DEVICE pointer, allocated and owned by the caller, aligned to 16 bytes
- * (256 for the batched workspace).  Input and output buffers must not
- * overlap.  The library keeps no device allocations of its
- * own except in pauli_decompose_batched's graph cache (see there).
+ * (256 for a workspace).  Input, output and workspace must not overlap.
+ * The matrix-core algorithms need a scratch buffer for their packed operand
+ * (pauli_workspace_bytes); when opts->workspace is NULL the library takes it
+ * from a stream-ordered memory pool of its own (one per device, kept for
+ * reuse until the process ends) and returns it on the same stream.
  *
  * Execution: work is enqueued on opts->stream (a hipStream_t passed as
  * void*, NULL = the null stream) and the call returns without waiting.  The
@@ -74,7 +76,7 @@ typedef struct pauli_opts {
     int out_dtype;          /* pauli_dtype of the output */
     int tile;               /* 0 = tuned/default tile; >0 forces a tile id (pauli_tile_count) */
     void* stream;           /* hipStream_t, NULL = null stream */
-    void* workspace;        /* device scratch for pauli_decompose_batched */
+    void* workspace;        /* optional device scratch, see pauli_workspace_bytes */
     size_t workspace_bytes; /* its size in bytes */
 } pauli_opts;
 
@@ -128,6 +130,15 @@ int pauli_decompose_batched(int count, const void* const* G, const int* N, void*
 
 /* Device workspace bytes pauli_decompose_batched needs for `count` matrices. */
 size_t pauli_batched_workspace_bytes(int count);
+
+/*
+ * Device scratch bytes pauli_decompose, pauli_reconstruct and
+ * pauli_decompose_backward need for (algo, N, batch) when the caller supplies
+ * opts->workspace: 12 bytes per matrix element for SPLIT_BF16 (six bf16
+ * planes), 8 for FP32, 0 for FP64_GRAY; N < 5 counts as N = 5.  A smaller
+ * workspace fails with PAULI_ENOMEM.  Returns 0 for invalid arguments.
+ */
+size_t pauli_workspace_bytes(int algo, int N, int batch);
 
 /*
  * Time every tile configuration of `algo` for N_min <= N <= N_max on the

@@ -47,7 +47,7 @@ _lib = None
 _lock = threading.Lock()
 
 EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward",
-           "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_autotune",
+           "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_workspace_bytes", "pauli_autotune",
            "pauli_tile_count", "pauli_tile_selected", "pauli_last_error", "pauli_version"]
 
 
@@ -71,6 +71,8 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_decompose_batched.restype = ci
         lib.pauli_batched_workspace_bytes.argtypes = [ci]
         lib.pauli_batched_workspace_bytes.restype = ctypes.c_size_t
+        lib.pauli_workspace_bytes.argtypes = [ci, ci, ci]
+        lib.pauli_workspace_bytes.restype = ctypes.c_size_t
         lib.pauli_autotune.argtypes = [ci, ci, op]
         lib.pauli_autotune.restype = ci
         lib.pauli_tile_count.argtypes = [ci]
@@ -107,6 +109,25 @@ def _opts(algo: str, in_dt: int, out_dt: int, tile: int = 0, stream=None, worksp
     return o
 
 
+_scratch = {}
+
+
+def workspace(algo: str, N: int, batch: int, device) -> torch.Tensor:
+    """A cached device scratch buffer large enough for (algo, N, batch), or
+    None when the algorithm needs none.  Reused across calls on the device
+    (calls are ordered on torch's current stream)."""
+    need = load_library().pauli_workspace_bytes(ALGOS[algo], N, batch)
+    if need == 0:
+        return None
+    key = torch.device(device)
+    ws = _scratch.get(key)
+    if ws is None or ws.numel() < need:
+        _scratch.pop(key, None)
+        ws = torch.empty(need, dtype=torch.uint8, device=key)
+        _scratch[key] = ws
+    return ws
+
+
 def _stream(t: torch.Tensor):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
@@ -141,7 +162,7 @@ def decompose(G: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: i
     out_dtype = out_dtype or G.dtype
     batch = G.numel() // (1 << (2 * N))
     out = torch.empty(G.shape[:-2] + (1 << (2 * N),), dtype=out_dtype, device=G.device)
-    o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G))
+    o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G), workspace(algo, N, batch, G.device))
     _check(load_library().pauli_decompose(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
     return out
 
@@ -154,7 +175,7 @@ def reconstruct(c: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile:
     D = 1 << N
     batch = c.numel() // (D * D)
     G = torch.empty(c.shape[:-1] + (D, D), dtype=out_dtype, device=c.device)
-    o = _opts(algo, _DT[c.dtype], _DT[out_dtype], tile, _stream(c))
+    o = _opts(algo, _DT[c.dtype], _DT[out_dtype], tile, _stream(c), workspace(algo, N, batch, c.device))
     _check(load_library().pauli_reconstruct(c.data_ptr(), N, batch, G.data_ptr(), ctypes.byref(o)))
     return G
 
@@ -168,7 +189,7 @@ def decompose_backward(grad_c: torch.Tensor, algo: str = "split_bf16", out_dtype
     D = 1 << N
     batch = g.numel() // (D * D)
     G = torch.empty(g.shape[:-1] + (D, D), dtype=out_dtype, device=g.device)
-    o = _opts(algo, _DT[g.dtype], _DT[out_dtype], tile, _stream(g))
+    o = _opts(algo, _DT[g.dtype], _DT[out_dtype], tile, _stream(g), workspace(algo, N, batch, g.device))
     _check(load_library().pauli_decompose_backward(g.data_ptr(), N, batch, G.data_ptr(), ctypes.byref(o)))
     return G
 

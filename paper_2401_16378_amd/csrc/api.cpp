@@ -107,10 +107,47 @@ int check_common(const void* in, int N, int batch, const void* out, const pauli_
     if (overlaps(in, count * elem_bytes(o.in_dtype), out, count * elem_bytes(o.out_dtype)))
         return fail(PAULI_EINVAL, "%s: input and output overlap", fn);
     if (o.tile < 0) return fail(PAULI_EINVAL, "%s: tile=%d must be >= 0", fn, o.tile);
+    if (o.workspace && o.algo != PAULI_ALGO_FP64_GRAY) {
+        if ((uintptr_t)o.workspace % 256)
+            return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+        if (overlaps(o.workspace, o.workspace_bytes, in, count * elem_bytes(o.in_dtype)) ||
+            overlaps(o.workspace, o.workspace_bytes, out, count * elem_bytes(o.out_dtype)))
+            return fail(PAULI_EINVAL, "%s: workspace overlaps input or output", fn);
+    }
     if (o.tile > 0 && o.algo != PAULI_ALGO_FP64_GRAY &&
         !mfma_tile_valid(planes_of(o.algo), o.tile, N))
         return fail(PAULI_EINVAL, "%s: tile %d not valid for algo %d at N=%d", fn, o.tile, o.algo, N);
     return PAULI_OK;
+}
+
+// Library-owned stream-ordered pool per device for the packed operand when
+// the caller passes no workspace; its release threshold keeps freed blocks
+// for reuse by later calls instead of returning them at each synchronisation.
+std::mutex g_pool_mu;
+std::map<int, hipMemPool_t> g_pools;
+
+hipError_t pool_for_current_device(hipMemPool_t* pool) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pools.find(dev);
+    if (it != g_pools.end()) {
+        *pool = it->second;
+        return hipSuccess;
+    }
+    hipMemPoolProps props;
+    memset(&props, 0, sizeof props);
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    e = hipMemPoolCreate(pool, &props);
+    if (e != hipSuccess) return e;
+    uint64_t keep = ~(uint64_t)0;
+    e = hipMemPoolSetAttribute(*pool, hipMemPoolAttrReleaseThreshold, &keep);
+    if (e != hipSuccess) return e;
+    g_pools[dev] = *pool;
+    return hipSuccess;
 }
 
 int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& o, double scale,
@@ -123,7 +160,21 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
     } else {
         const int planes = planes_of(o.algo);
         const int tile = pick_tile(o.algo, N, o.tile);
-        e = launch_mfma(dir, planes, in, in128, out, out128, N, batch, scale, tile, s);
+        const size_t need = mfma_workspace_bytes(planes, N, batch);
+        void* ws = o.workspace;
+        if (ws) {
+            if (o.workspace_bytes < need)
+                return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
+                            o.workspace_bytes);
+            e = launch_mfma(dir, planes, in, in128, out, out128, N, batch, scale, tile, ws, s);
+        } else {
+            hipMemPool_t pool;
+            if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
+            if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
+            e = launch_mfma(dir, planes, in, in128, out, out128, N, batch, scale, tile, ws, s);
+            const hipError_t ef = hipFreeAsync(ws, s);
+            if (e == hipSuccess) e = ef;
+        }
     }
     if (e != hipSuccess) return hip_fail(e, fn);
     g_last_error.clear();
@@ -166,6 +217,12 @@ int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
     if (st != PAULI_OK) return st;
     return run(ADJOINT, grad_c, N, batch, grad_G, o, 1.0 / (double)(1u << N),
                "pauli_decompose_backward");
+}
+
+size_t pauli_workspace_bytes(int algo, int N, int batch) {
+    if (!valid_algo(algo) || N < 0 || N > N_MAX || batch < 1) return 0;
+    if (algo == PAULI_ALGO_FP64_GRAY) return 0;
+    return mfma_workspace_bytes(planes_of(algo), N, batch);
 }
 
 size_t pauli_batched_workspace_bytes(int count) {
@@ -327,10 +384,15 @@ extern "C" int pauli_autotune(int N_min, int N_max, const pauli_opts* opts) {
     hipError_t e;
     for (int N = N_min; N <= N_max; ++N) {
         const size_t elems = (size_t)1 << (2 * N);
-        void *in = nullptr, *out = nullptr;
+        void *in = nullptr, *out = nullptr, *ws = nullptr;
         if ((e = hipMalloc(&in, elems * 8)) != hipSuccess) return hip_fail(e, fn);
         if ((e = hipMalloc(&out, elems * 8)) != hipSuccess) {
             (void)hipFree(in);
+            return hip_fail(e, fn);
+        }
+        if ((e = hipMalloc(&ws, mfma_workspace_bytes(planes, N, 1))) != hipSuccess) {
+            (void)hipFree(in);
+            (void)hipFree(out);
             return hip_fail(e, fn);
         }
         // the data values do not affect timing; zero is enough
@@ -345,11 +407,11 @@ extern "C" int pauli_autotune(int N_min, int N_max, const pauli_opts* opts) {
         for (int t = 1; t <= ntiles && e == hipSuccess; ++t) {
             if (!mfma_tile_valid(planes, t, N)) continue;
             double sc = 1.0 / (double)(1u << N);
-            e = launch_mfma(FORWARD, planes, in, false, out, false, N, 1, sc, t, s);  // warm-up
+            e = launch_mfma(FORWARD, planes, in, false, out, false, N, 1, sc, t, ws, s);  // warm-up
             if (e != hipSuccess) break;
             e = hipEventRecord(a, s);
             for (int r = 0; r < reps && e == hipSuccess; ++r)
-                e = launch_mfma(FORWARD, planes, in, false, out, false, N, 1, sc, t, s);
+                e = launch_mfma(FORWARD, planes, in, false, out, false, N, 1, sc, t, ws, s);
             if (e == hipSuccess) e = hipEventRecord(b, s);
             if (e == hipSuccess) e = hipEventSynchronize(b);
             float ms = 0;
@@ -364,6 +426,7 @@ extern "C" int pauli_autotune(int N_min, int N_max, const pauli_opts* opts) {
         if (b) (void)hipEventDestroy(b);
         (void)hipFree(in);
         (void)hipFree(out);
+        (void)hipFree(ws);
         if (e != hipSuccess) return hip_fail(e, fn);
         if (best > 0) {
             std::lock_guard<std::mutex> lk(g_tune_mu);

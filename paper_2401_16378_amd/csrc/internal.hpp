@@ -17,10 +17,12 @@ hipError_t launch_gray(Dir dir, const void* in, bool in_c128, void* out, bool ou
                        int batch, double scale, hipStream_t stream);
 
 // Matrix-core contraction.  planes = 3 (split bf16) or 1 (fp32).
-// tile = 1-based tile id (0 = default for N).
+// tile = 1-based tile id (0 = default for N).  ws = device scratch of
+// mfma_workspace_bytes(planes, N, batch) bytes for the packed operand.
 hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* out,
-                       bool out_c128, int N, int batch, double scale, int tile,
+                       bool out_c128, int N, int batch, double scale, int tile, void* ws,
                        hipStream_t stream);
+size_t mfma_workspace_bytes(int planes, int N, int batch);
 int mfma_tile_count(int planes);
 bool mfma_tile_valid(int planes, int tile, int N);
 int mfma_default_tile(int planes, int N);

@@ -9,28 +9,36 @@
 // adjoint (recomposition / gradient):  q = z, p = i,
 //   In[z][x] = i^{popc(x&z)} c[n(x,z)],  G[i^x][i] = scale * C[i][x].
 //
-// H is the Sylvester-Hadamard sign matrix: every entry is +-1, exact in any
-// format, so it never touches memory.  Over an aligned 32-row block it is
-// one fixed 32x32 block times a sign fixed by the blocks' high bits; the
-// kernel keeps the two fragments of that block (and their negations) in
-// registers and picks them at compile time, with one extra sign per wave and
-// K-tile.
+// Two kernels.
+//
+// pack: an HBM-bound pass that gathers In (the XOR diagonals of G, or the
+//   phased coefficient blocks), converts it to the matrix-core operand
+//   format and stores it in the exact lane order of the MFMA B operand, one
+//   contiguous 1 KiB fragment (64 lanes x 16 bytes) per (32 flip masks,
+//   16 or 8 K values, plane, re/im).  A thread owns an aligned 4x4
+//   micro-block: 4 rows x 4 columns of G, which the XOR map sends to 4 flip
+//   masks x 4 consecutive q, or 16 consecutive coefficients, which form a
+//   4x4 (z,x) block; the block is transposed through LDS so every global
+//   store is a full 1 KiB fragment.
+//
+// contract: each wave owns RB*32 rows p and 32 flip masks x (64 real B
+//   columns: re, then im) and walks the whole K range, streaming its B
+//   fragments from L2 through a register ring PF slices deep.  H is the
+//   Sylvester-Hadamard sign matrix: every entry is +-1, exact in any format,
+//   so it never touches memory; over an aligned 32-row block it is one fixed
+//   32x32 block times a sign fixed by the blocks' high bits, and the kernel
+//   keeps that block's fragments and their negations in registers, choosing
+//   among them at compile time plus one uniform sign per group of slices.
+//   No LDS and no barrier in the main loop; the epilogue stages each 32x32
+//   output block in LDS so it leaves as one contiguous run of coefficients
+//   (forward) or one aligned 32x32 square of G (adjoint).
 //
 // Precision.  PLANES = 3: each binary32 component g is split as
 // g ~ hi + mid + lo (three bf16 numbers, hi on a power-of-two grid shared by
 // the 4x4 micro-block, see split3); bf16 MFMA accumulates hi into one FP32
 // accumulator, where the sums stay exact, and mid + lo into a second, and the
-// two are added in binary64 in the epilogue before the phase and scale.  PLANES = 1: binary32 MFMA on
-// the binary32 components.
-//
-// Tiling.  A workgroup owns 32 flip masks x (64 real B columns: re then im)
-// and WAVES*RB*32 rows p; each wave owns RB*32 rows and the whole K range.
-// K is walked in tiles of KT = 32*RB, staged through double-buffered LDS.
-// A thread loads one aligned 4x4 micro-block per K-tile: in the forward
-// direction 4 rows x 4 columns of G, which the XOR map sends to 4 columns x
-// 4 consecutive q of In; in the adjoint, 16 consecutive coefficients, which
-// form a 4x4 (z,x) block.  Each LDS write is therefore 4 consecutive q of one
-// column: 8 bytes per bf16 plane, 16 bytes for fp32.
+// two are added in binary64 in the epilogue before the phase and scale.
+// PLANES = 1: binary32 MFMA on the binary32 components.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -45,7 +53,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int XT = 32;  // flip masks per workgroup
+constexpr int XT = 32;       // flip masks per fragment column block
+constexpr int FRAG = 1024;   // bytes per B fragment (64 lanes x 16 bytes)
 
 __device__ inline uint32_t pack_bf16(float a, float b) {
     f32x2 v = {a, b};
@@ -84,31 +93,6 @@ __device__ inline void block_grid(float maxabs, float& u, float& inv_u) {
     inv_u = __builtin_bit_cast(float, (uint32_t)(127 - e + 8) << 23);
 }
 
-template <int PLANES, int RB, int WAVES>
-struct Cfg {
-    static constexpr int KT = 32 * RB;                 // K per tile
-    static constexpr int NT = WAVES * 64;              // threads
-    static constexpr int MT = WAVES * RB * 32;         // rows per workgroup
-    static constexpr int NPL = PLANES == 3 ? 6 : 2;    // LDS planes (plane x re/im)
-    static constexpr int ESZ = PLANES == 3 ? 2 : 4;    // bytes per LDS element
-    static constexpr int PITCH = KT * ESZ + 16;        // bytes per LDS column (padded)
-    static constexpr int BUF = NPL * XT * PITCH;       // bytes per K-tile buffer
-    static constexpr int UBLK = 2 * KT;                // 4x4 micro-blocks per K-tile
-    static constexpr int UPT = (UBLK + NT - 1) / NT;   // micro-blocks per thread
-    static int lds_bytes(int esz) {                     // K-tile buffers or epilogue staging
-        const int stage = WAVES * 1024 * esz;
-        return 2 * BUF > stage ? 2 * BUF : stage;
-    }
-};
-
-struct Params {
-    const void* in;
-    void* out;
-    int N;
-    int out128;
-    double scale;
-};
-
 template <bool IN128>
 __device__ inline f32x2 load_elem(const unsigned char* base, size_t idx) {
     if constexpr (IN128) {
@@ -120,152 +104,176 @@ __device__ inline f32x2 load_elem(const unsigned char* base, size_t idx) {
     }
 }
 
-template <int PLANES, int RB, int WAVES, int DIR, bool IN128>
-__global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
-    using C = Cfg<PLANES, RB, WAVES>;
-    constexpr int KT = C::KT;
-    constexpr int ACC = PLANES == 3 ? 2 : 1;
-    constexpr int UPT = C::UPT;
-    constexpr int NPARTS = 4 * UPT;                          // deposit pieces per K-tile
-    constexpr int S = PLANES == 3 ? KT / 16 : KT / 8;        // K-slices per tile
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+// ---------------------------------------------------------------------------
+// Packed operand layout, per matrix, with Dp = max(2^N, 32):
+//   bf16: fragment (xb, s, pl, cb) at ((xb * Dp/16 + s) * 6 + pl * 2 + cb) KiB,
+//         lane l = x_l + 32h holds K = 16s + 8h + j, j < 8, of column x_l;
+//   fp32: fragment (xb, s, cb) at ((xb * Dp/8 + s) * 2 + cb) KiB,
+//         lane l holds K = 8s + 4h + t, t < 4.
+// pl = hi/mid/lo plane, cb = 0 real parts, 1 imaginary parts.
+// ---------------------------------------------------------------------------
+template <int PLANES>
+struct Pack {
+    static constexpr int SK = PLANES == 3 ? 16 : 8;        // K per slice
+    static constexpr int NPL = PLANES == 3 ? 6 : 2;        // fragments per slice
+    static constexpr int ESZ = PLANES == 3 ? 2 : 4;        // bytes per element
+    static constexpr int SLICE_BYTES = NPL * FRAG;
+    static constexpr int EB = NPL * ESZ;                   // packed bytes per matrix element
+};
 
-    const int N = prm.N;
-    const uint32_t D = 1u << N;
-    const bool full = D >= 32u;                               // no padding needed
-    const uint32_t nMB = D > (uint32_t)C::MT ? D / C::MT : 1u;   // row blocks
-    const uint32_t nK = D > (uint32_t)KT ? D / KT : 1u;          // K tiles
-    const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t xb = L / nMB, mb = L % nMB;
-    const uint32_t X0 = xb * XT;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l32 = lane & 31, h = lane >> 5;
-    const uint32_t Pw = mb * C::MT + wave * RB * 32;            // first row of this wave
+__host__ __device__ inline uint32_t padded_dim(int N) { return N < 5 ? 32u : (1u << N); }
+
+constexpr int PACK_KT = 128;   // K per pack workgroup (less when Dp < 128)
+
+template <int PLANES, int DIR, bool IN128>
+__global__ __launch_bounds__(256) void pack_kernel(const void* __restrict__ in, void* __restrict__ ws, int N) {
+    using P = Pack<PLANES>;
+    constexpr int PITCH_MAX = PACK_KT * P::ESZ + 16;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[P::NPL * XT * PITCH_MAX];
+
+    const uint32_t D = 1u << N, Dp = padded_dim(N);
+    const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
+    const uint32_t pitch = KT * P::ESZ + 16;
+    const uint32_t nKT = Dp / KT;
+    const uint32_t xb = blockIdx.x / nKT, kt = blockIdx.x % nKT;
+    const uint32_t X0 = xb * XT, Q0 = kt * KT;
+    const bool full = D >= 32u;
+    const int tid = threadIdx.x;
     const size_t mat = (size_t)D * D;
-    const unsigned char* src = (const unsigned char*)prm.in + (size_t)blockIdx.y * mat * (IN128 ? 16 : 8);
-    unsigned char* dst = (unsigned char*)prm.out + (size_t)blockIdx.y * mat * (prm.out128 ? 16 : 8);
+    const unsigned char* src = (const unsigned char*)in + (size_t)blockIdx.y * mat * (IN128 ? 16 : 8);
 
-    // ---- prologue pieces: fetch a K-tile into registers, deposit it into LDS ----
-    f32x2 stg[UPT][16];
-    float gu[UPT], ginv[UPT];
-    auto fetch = [&](uint32_t kt) {
-        const uint32_t Q0 = kt * KT;
-#pragma unroll
-        for (int u = 0; u < UPT; ++u) {
-            const int ub = tid + u * C::NT;
-            if constexpr (C::UBLK < UPT * C::NT) {
-                if (ub >= C::UBLK) break;
-            }
-            const int g = ub >> 6, w6 = ub & 63;   // 32x32 square g of the tile, block w6 in it
-            if constexpr (DIR == FORWARD) {
-                const int mr = w6 >> 3, mc = w6 & 7;
-                const uint32_t q0 = Q0 + 32 * g + 4 * mc;
-                const uint32_t r0 = (((Q0 + 32 * g) ^ X0) & ~31u) + 4 * mr;
-                if (full) {
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b)
-                            stg[u][a * 4 + b] = load_elem<IN128>(src, (size_t)(r0 + a) * D + q0 + b);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const uint32_t r = r0 + a, q = q0 + b;
-                            stg[u][a * 4 + b] = (r < D && q < D) ? load_elem<IN128>(src, (size_t)r * D + q)
-                                                                 : f32x2{0.f, 0.f};
-                        }
-                }
-            } else {
-                const uint32_t zb = Q0 + 32 * g;
-                const uint32_t nb = pauli_index(X0, zb);
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const uint32_t o = 16 * w6 + r;
-                    const uint32_t zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
-                    const uint32_t z = zb + zl, x = X0 + xl;
-                    f32x2 c = {0.f, 0.f};
-                    if (full || (z < D && x < D)) c = load_elem<IN128>(src, nb + o);
-                    float re = c.x, im = c.y;
-                    rotate_minus_i(re, im, 3u * (uint32_t)__popc(x & z));  // i^{popc(x&z)}
-                    stg[u][r] = f32x2{re, im};
-                }
-            }
-        }
-    };
-    // grid of micro-block u (split-bf16 only)
-    auto grid = [&](int u) {
-        float mx = 0.f;
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            mx = __builtin_fmaxf(mx, __builtin_fmaxf(__builtin_fabsf(stg[u][r].x), __builtin_fabsf(stg[u][r].y)));
-        block_grid(mx, gu[u], ginv[u]);
-    };
-    // row x2 of micro-block u: 4 consecutive K slots of one column, all planes
-    auto deposit_part = [&](int buf, int u, int x2) {
-        const int ub = tid + u * C::NT;
-        if constexpr (C::UBLK < UPT * C::NT) {
-            if (ub >= C::UBLK) return;
-        }
-        const int g = ub >> 6, w6 = ub & 63;
-        if constexpr (PLANES == 3) {
-            if (x2 == 0) grid(u);
-        }
-        int xh, kh;  // column group (x_l / 4) and first K slot of the micro-block
+    // one 4x4 micro-block per thread: 2*KT of them in the 32 x KT tile
+    if ((uint32_t)tid < 2 * KT) {
+        const int g = tid >> 6, w6 = tid & 63;   // 32x32 square g, block w6 in it
+        f32x2 v[16];
+        int xh, kh;                              // column group (x_l / 4), first K slot
         if constexpr (DIR == FORWARD) {
             const int mr = w6 >> 3, mc = w6 & 7;
+            const uint32_t q0 = Q0 + 32 * g + 4 * mc;
+            const uint32_t r0 = (((Q0 + 32 * g) ^ X0) & ~31u) + 4 * mr;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t r = r0 + a, q = q0 + b;
+                    v[a * 4 + b] = (full || (r < D && q < D)) ? load_elem<IN128>(src, (size_t)r * D + q)
+                                                              : f32x2{0.f, 0.f};
+                }
             xh = mr ^ mc;
             kh = 32 * g + 4 * mc;
         } else {
+            const uint32_t zb = Q0 + 32 * g;
+            const uint32_t nb = pauli_index(X0, zb);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t o = 16 * w6 + r;
+                const uint32_t zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
+                const uint32_t z = zb + zl, x = X0 + xl;
+                f32x2 c = {0.f, 0.f};
+                if (full || (z < D && x < D)) c = load_elem<IN128>(src, nb + o);
+                float re = c.x, im = c.y;
+                rotate_minus_i(re, im, 3u * (uint32_t)__popc(x & z));  // i^{popc(x&z)}
+                v[r] = f32x2{re, im};
+            }
             // 16 consecutive coefficients o = 16*w6 + r, r = (x^z)_0 | z_0<<1 | (x^z)_1<<2 | z_1<<3
             const uint32_t o = 16 * w6;
             const int zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
             xh = xl >> 2;
             kh = 32 * g + zl;
         }
-        f32x2 e[4];
+        float gu = 1.f, ginv = 1.f;
+        if constexpr (PLANES == 3) {
+            float mx = 0.f;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            if constexpr (DIR == FORWARD) {
-                e[b] = stg[u][((x2 ^ b) << 2) | b];  // row a = x2 ^ b, column b
+            for (int r = 0; r < 16; ++r)
+                mx = __builtin_fmaxf(mx, __builtin_fmaxf(__builtin_fabsf(v[r].x), __builtin_fabsf(v[r].y)));
+            block_grid(mx, gu, ginv);
+        }
+#pragma unroll
+        for (int x2 = 0; x2 < 4; ++x2) {
+            f32x2 e[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if constexpr (DIR == FORWARD) {
+                    e[b] = v[((x2 ^ b) << 2) | b];  // row a = x2 ^ b, column b
+                } else {
+                    const int d = x2 ^ b;             // (x ^ z) low bits
+                    e[b] = v[(d & 1) | ((b & 1) << 1) | ((d >> 1) << 2) | ((b >> 1) << 3)];
+                }
+            }
+            unsigned char* cbase = lds + (xh * 4 + x2) * pitch + kh * P::ESZ;
+            const uint32_t PS = XT * pitch;  // plane stride
+            if constexpr (PLANES == 3) {
+                uint32_t hr0, mr0, lr0, hr1, mr1, lr1, hi0, mi0, li0, hi1, mi1, li1;
+                split3(e[0].x, e[1].x, gu, ginv, hr0, mr0, lr0);
+                split3(e[2].x, e[3].x, gu, ginv, hr1, mr1, lr1);
+                split3(e[0].y, e[1].y, gu, ginv, hi0, mi0, li0);
+                split3(e[2].y, e[3].y, gu, ginv, hi1, mi1, li1);
+                *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
+                *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
+                *(u32x2*)(cbase + 2 * PS) = u32x2{mr0, mr1};
+                *(u32x2*)(cbase + 3 * PS) = u32x2{mi0, mi1};
+                *(u32x2*)(cbase + 4 * PS) = u32x2{lr0, lr1};
+                *(u32x2*)(cbase + 5 * PS) = u32x2{li0, li1};
             } else {
-                const int d = x2 ^ b;                 // (x ^ z) low bits
-                e[b] = stg[u][(d & 1) | ((b & 1) << 1) | ((d >> 1) << 2) | ((b >> 1) << 3)];
+                *(f32x4*)(cbase) = f32x4{e[0].x, e[1].x, e[2].x, e[3].x};
+                *(f32x4*)(cbase + PS) = f32x4{e[0].y, e[1].y, e[2].y, e[3].y};
             }
         }
-        unsigned char* cbase = lds + buf * C::BUF + (xh * 4 + x2) * C::PITCH + kh * C::ESZ;
-        constexpr int PS = XT * C::PITCH;  // plane stride
-        if constexpr (PLANES == 3) {
-            uint32_t hr0, mr0, lr0, hr1, mr1, lr1, hi0, mi0, li0, hi1, mi1, li1;
-            split3(e[0].x, e[1].x, gu[u], ginv[u], hr0, mr0, lr0);
-            split3(e[2].x, e[3].x, gu[u], ginv[u], hr1, mr1, lr1);
-            split3(e[0].y, e[1].y, gu[u], ginv[u], hi0, mi0, li0);
-            split3(e[2].y, e[3].y, gu[u], ginv[u], hi1, mi1, li1);
-            *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
-            *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
-            *(u32x2*)(cbase + 2 * PS) = u32x2{mr0, mr1};
-            *(u32x2*)(cbase + 3 * PS) = u32x2{mi0, mi1};
-            *(u32x2*)(cbase + 4 * PS) = u32x2{lr0, lr1};
-            *(u32x2*)(cbase + 5 * PS) = u32x2{li0, li1};
-        } else {
-            *(f32x4*)(cbase) = f32x4{e[0].x, e[1].x, e[2].x, e[3].x};
-            *(f32x4*)(cbase + PS) = f32x4{e[0].y, e[1].y, e[2].y, e[3].y};
-        }
-    };
-    auto deposit_all = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < UPT; ++u)
-#pragma unroll
-            for (int x2 = 0; x2 < 4; ++x2) deposit_part(buf, u, x2);
-    };
+    }
+    __syncthreads();
+
+    // Write whole fragments: KT/SK slices x NPL fragments, 64 lanes x 16 bytes.
+    const int lane = tid & 63, wave = tid >> 6;
+    const int xl = lane & 31, h = lane >> 5;
+    const uint32_t nfrag = (KT / P::SK) * P::NPL;
+    unsigned char* dst = (unsigned char*)ws + (size_t)blockIdx.y * Dp * Dp * P::EB +
+                         ((size_t)xb * (Dp / P::SK) + Q0 / P::SK) * P::SLICE_BYTES;
+    for (uint32_t f = wave; f < nfrag; f += 4) {
+        const uint32_t s = f / P::NPL, pl = f % P::NPL;
+        const unsigned char* srcl = lds + pl * XT * pitch + xl * pitch + (s * P::SK + h * (P::SK / 2)) * P::ESZ;
+        *(u32x4*)(dst + (size_t)f * FRAG + lane * 16) = *(const u32x4*)srcl;
+    }
+}
+
+struct Params {
+    const void* ws;
+    void* out;
+    int N;
+    int out128;
+    double scale;
+};
+
+template <int PLANES, int RB, int WAVES, int DIR, int PF>
+__global__ __launch_bounds__(WAVES * 64) void contract_kernel(Params prm) {
+    using P = Pack<PLANES>;
+    constexpr int ACC = PLANES == 3 ? 2 : 1;
+    constexpr int MT = WAVES * RB * 32;                    // rows per workgroup
+    constexpr int U = 32 * RB / P::SK;                     // slices per sign group (32*RB K)
+    constexpr int GS = U > PF ? U : PF;                    // slices per unrolled step
+    static_assert(GS % U == 0 && GS % PF == 0, "ring depth and sign group must nest");
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+
+    const int N = prm.N;
+    const uint32_t D = 1u << N, Dp = padded_dim(N);
+    const uint32_t nMB = Dp / MT;
+    const uint32_t nS = Dp / P::SK;
+    const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t xb = L / nMB, mb = L % nMB;
+    const uint32_t X0 = xb * XT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, h = lane >> 5;
+    const uint32_t Pw = mb * MT + wave * RB * 32;          // first row of this wave
+    const unsigned char* wsx = (const unsigned char*)prm.ws + (size_t)blockIdx.y * Dp * Dp * P::EB +
+                               (size_t)xb * nS * P::SLICE_BYTES + lane * 16;
+    unsigned char* dst = (unsigned char*)prm.out + (size_t)blockIdx.y * D * D * (prm.out128 ? 16 : 8);
 
     // ---- sign fragments of the 32x32 Sylvester block ----
     // bf16: lane (row p_l = l32, half h) holds K slots q_l = 16e + 8h + j, j < 8,
     //       for the two 16-wide slices e of a 32-wide block.
-    // fp32: lane holds q_l = 8e + 4h + st for slice e < 4, step st < 4.
+    // fp32: lane holds q_l = 8e + 4h + t for slice e < 4, step t < 4.
     uint32_t fA[2][4];   // bf16 pairs, [e][j/2]
-    float fF[4][4];      // fp32, [e][st]
+    float fF[4][4];      // fp32, [e][t]
     if constexpr (PLANES == 3) {
 #pragma unroll
         for (int e = 0; e < 2; ++e)
@@ -280,8 +288,8 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int st = 0; st < 4; ++st)
-                fF[e][st] = (__popc(l32 & (8 * e + 4 * h + st)) & 1) ? -1.f : 1.f;
+            for (int t = 0; t < 4; ++t)
+                fF[e][t] = (__popc(l32 & (8 * e + 4 * h + t)) & 1) ? -1.f : 1.f;
     }
 
     f32x16 acc[ACC][RB][2];
@@ -294,95 +302,73 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[a][rb][cb][r] = 0.f;
 
-    fetch(0);
-    deposit_all(0);
-    __syncthreads();
-    for (uint32_t kt = 0; kt < nK; ++kt) {
-        const int buf = kt & 1;
-        // Next tile's loads go out now; its split and LDS writes are spread over
-        // the second half of this tile's K-slices so they overlap the MFMAs.
-        // On the last tile the last tile is fetched again into the idle buffer.
-        fetch(kt + 1 < nK ? kt + 1 : kt);
-        // sign of this wave's rows against this K-tile from the bits above the tile
-        const bool neg_tile = __popc((Pw >> 5) & ((kt * KT) >> 5)) & 1;
-        const unsigned char* bbase = lds + buf * C::BUF + l32 * C::PITCH;
-        bf16x8 Ap[2], An[2];
-        if constexpr (PLANES == 3) {
-            const uint32_t tm = neg_tile ? 0x80008000u : 0u;
+    // ---- B fragment ring ----
+    u32x4 ring[PF][P::NPL];
+    auto fetch = [&](int slot, uint32_t s) {
+        const unsigned char* p = wsx + (size_t)s * P::SLICE_BYTES;
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                u32x4 p = {fA[e][0] ^ tm, fA[e][1] ^ tm, fA[e][2] ^ tm, fA[e][3] ^ tm};
-                u32x4 n = p ^ 0x80008000u;
-                Ap[e] = __builtin_bit_cast(bf16x8, p);
-                An[e] = __builtin_bit_cast(bf16x8, n);
+        for (int f = 0; f < P::NPL; ++f) ring[slot][f] = *(const u32x4*)(p + f * FRAG);
+    };
+#pragma unroll
+    for (int k = 0; k < PF; ++k) fetch(k, (uint32_t)k < nS ? k : nS - 1);
+
+    bf16x8 Ap[2], An[2];
+    float ts = 1.f;
+    for (uint32_t s0 = 0; s0 < nS; s0 += GS) {
+#pragma unroll
+        for (int uu = 0; uu < GS; ++uu) {
+            const int u = uu % U, slot = uu % PF;
+            if (u == 0) {
+                // sign of this wave's rows against this group of 32*RB K values
+                const bool neg_grp = __popc((Pw >> 5) & (((s0 + uu) * P::SK) >> 5)) & 1;
+                if constexpr (PLANES == 3) {
+                    const uint32_t tm = neg_grp ? 0x80008000u : 0u;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const u32x4 p = {fA[e][0] ^ tm, fA[e][1] ^ tm, fA[e][2] ^ tm, fA[e][3] ^ tm};
+                        Ap[e] = __builtin_bit_cast(bf16x8, p);
+                        An[e] = __builtin_bit_cast(bf16x8, p ^ 0x80008000u);
+                    }
+                } else {
+                    ts = neg_grp ? -1.f : 1.f;
+                }
             }
-        }
-        const float ts = neg_tile ? -1.f : 1.f;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
             if constexpr (PLANES == 3) {
-                bf16x8 B[3][2];
+                // plane-outer order: consecutive MFMAs never share an accumulator
 #pragma unroll
                 for (int pl = 0; pl < 3; ++pl)
 #pragma unroll
-                    for (int cb = 0; cb < 2; ++cb)
-                        B[pl][cb] = *(const bf16x8*)(bbase + (pl * 2 + cb) * XT * C::PITCH + (16 * s + 8 * h) * 2);
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const bool neg = popc_const((uint32_t)rb & (uint32_t)(s >> 1)) & 1;
-                    const bf16x8 A = neg ? An[s & 1] : Ap[s & 1];
-#pragma unroll
-                    for (int cb = 0; cb < 2; ++cb) {
-                        acc[0][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B[0][cb], acc[0][rb][cb], 0, 0, 0);
-                        acc[ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B[1][cb], acc[ACC - 1][rb][cb], 0, 0, 0);
-                        acc[ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B[2][cb], acc[ACC - 1][rb][cb], 0, 0, 0);
-                    }
-                }
-            } else {
-                f32x4 B[2];
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-                    B[cb] = *(const f32x4*)(bbase + cb * XT * C::PITCH + (8 * s + 4 * h) * 4);
-#pragma unroll
-                for (int st = 0; st < 4; ++st) {
-#pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
-                        const bool neg = popc_const((uint32_t)rb & (uint32_t)(s >> 2)) & 1;
-                        const float A = (neg ? -ts : ts) * fF[s & 3][st];
+                        const bool neg = popc_const((uint32_t)rb & (uint32_t)(u >> 1)) & 1;
+                        const bf16x8 A = neg ? An[u & 1] : Ap[u & 1];
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
-                            acc[0][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, B[cb][st], acc[0][rb][cb], 0, 0, 0);
+                            acc[pl == 0 ? 0 : ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                A, __builtin_bit_cast(bf16x8, ring[slot][pl * 2 + cb]),
+                                acc[pl == 0 ? 0 : ACC - 1][rb][cb], 0, 0, 0);
                     }
-                }
-            }
-            // deposit pieces scheduled after this slice
-            int nparts = 0;
-#pragma unroll
-            for (int part = 0; part < NPARTS; ++part) {
-                constexpr int H0 = S / 2;
-                const int sp = H0 + part * (S - H0) / NPARTS;
-                if (sp == s) {
-                    deposit_part(buf ^ 1, part / 4, part % 4);
-                    ++nparts;
-                }
-            }
-            // Scheduling: this slice's LDS reads first, then its MFMAs with the
-            // split arithmetic of the deposit pieces threaded between them, then
-            // the pieces' LDS writes.
-            constexpr int MF = PLANES == 3 ? RB * 6 : RB * 8;   // MFMAs per slice
-            __builtin_amdgcn_sched_group_barrier(0x100, PLANES == 3 ? 6 : 2, 0);
-            if (nparts > 0) {
-#pragma unroll
-                for (int i = 0; i < MF; ++i) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, PLANES == 3 ? 6 : 2, 0);
-                }
-                __builtin_amdgcn_sched_group_barrier(0x200, 16, 0);
             } else {
-                __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
+                const f32x4 Bv[2] = {__builtin_bit_cast(f32x4, ring[slot][0]),
+                                     __builtin_bit_cast(f32x4, ring[slot][1])};
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const bool neg = popc_const((uint32_t)rb & (uint32_t)(u >> 2)) & 1;
+                        const float A = (neg ? -ts : ts) * fF[u & 3][t];
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            acc[0][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, Bv[cb][t], acc[0][rb][cb], 0, 0, 0);
+                    }
             }
+            // Refill this slot with slice s+PF.  The fences keep the loads
+            // here, PF slices ahead of their use, instead of letting the
+            // scheduler sink them next to the MFMAs that consume them.
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t nxt = s0 + uu + PF;
+            fetch(slot, nxt < nS ? nxt : nS - 1);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();
     }
 
     // ---- epilogue: binary64 recombination, phase, scale, staged store ----
@@ -431,43 +417,49 @@ __global__ __launch_bounds__(WAVES * 64) void mfma_kernel(Params prm) {
             const uint32_t w = D < 32u ? D : 32u;
             const uint32_t rowbytes = w * esz;
             const uint32_t r0 = (pb ^ X0) & ~31u;
-            if (rowbytes >= 16) {
-                for (uint32_t b = lane * 16; b < w * rowbytes; b += 64 * 16) {
-                    const uint32_t rl = b / rowbytes, cb = b % rowbytes;
-                    if (pb < D)
+            if (pb < D) {
+                if (rowbytes >= 16) {
+                    for (uint32_t b = lane * 16; b < w * rowbytes; b += 64 * 16) {
+                        const uint32_t rl = b / rowbytes, cb = b % rowbytes;
                         *(u32x4*)(dst + ((size_t)(r0 + rl) * D + pb) * esz + cb) =
                             *(const u32x4*)(stage + rl * 32 * esz + cb);
+                    }
+                } else if (lane == 0) {
+                    *(u32x2*)dst = *(const u32x2*)stage;     // N = 0, binary32 output
                 }
-            } else if (lane == 0) {
-                *(u32x2*)dst = *(const u32x2*)stage;     // N = 0, binary32 output
             }
         }
         __syncthreads();
     }
 }
 
-// ---- tile table ----
+// ---- tile table: (rows per wave / 32, waves per workgroup, ring depth) ----
 struct TileDesc {
-    int rb, waves;
+    int rb, waves, pf;
 };
 constexpr TileDesc TILES[] = {
-    {4, 4},  // 1: 512 rows x 32 x, K-tile 128
-    {2, 4},  // 2: 256 rows, K-tile 64
-    {2, 8},  // 3: 512 rows, K-tile 64
-    {1, 4},  // 4: 128 rows, K-tile 32
-    {1, 1},  // 5: 32 rows, K-tile 32 (zero-padded below 32)
-    {1, 2},  // 6: 64 rows, K-tile 32
+    {4, 4, 4},  // 1: 512 rows
+    {4, 2, 4},  // 2: 256 rows
+    {2, 4, 4},  // 3: 256 rows
+    {2, 8, 2},  // 4: 512 rows, two waves per SIMD
+    {1, 1, 2},  // 5: 32 rows (zero-padded below 32)
+    {1, 4, 2},  // 6: 128 rows
+    {4, 1, 4},  // 7: 128 rows
+    {2, 2, 4},  // 8: 128 rows
+    {1, 2, 2},  // 9: 64 rows
+    {4, 4, 8},  // 10: 512 rows, deeper ring
+    {4, 2, 8},  // 11: 256 rows, deeper ring
+    {2, 4, 8},  // 12: 256 rows, deeper ring
 };
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
-template <int PLANES, int RB, int WAVES, int DIR>
-hipError_t launch_cfg(const Params& p, bool in128, int batch, hipStream_t s) {
-    using C = Cfg<PLANES, RB, WAVES>;
-    const uint32_t D = 1u << p.N;
-    const uint32_t nMB = D > (uint32_t)C::MT ? D / C::MT : 1u;
-    const uint32_t nXB = D > (uint32_t)XT ? D / XT : 1u;
-    auto kern = in128 ? mfma_kernel<PLANES, RB, WAVES, DIR, true> : mfma_kernel<PLANES, RB, WAVES, DIR, false>;
-    const int lds = C::lds_bytes(p.out128 ? 16 : 8);
+template <int PLANES, int RB, int WAVES, int PF, int DIR>
+hipError_t launch_contract(const Params& p, int batch, hipStream_t s) {
+    constexpr int MT = WAVES * RB * 32;
+    const uint32_t Dp = padded_dim(p.N);
+    const uint32_t nMB = Dp / MT, nXB = Dp / XT;
+    auto kern = contract_kernel<PLANES, RB, WAVES, DIR, PF>;
+    const int lds = WAVES * 1024 * (p.out128 ? 16 : 8);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(WAVES * 64), lds, s, p);
@@ -475,16 +467,32 @@ hipError_t launch_cfg(const Params& p, bool in128, int batch, hipStream_t s) {
 }
 
 template <int PLANES, int DIR>
-hipError_t launch_tile(int tile, const Params& p, bool in128, int batch, hipStream_t s) {
+hipError_t launch_tile(int tile, const Params& p, int batch, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_cfg<PLANES, 4, 4, DIR>(p, in128, batch, s);
-        case 2: return launch_cfg<PLANES, 2, 4, DIR>(p, in128, batch, s);
-        case 3: return launch_cfg<PLANES, 2, 8, DIR>(p, in128, batch, s);
-        case 4: return launch_cfg<PLANES, 1, 4, DIR>(p, in128, batch, s);
-        case 5: return launch_cfg<PLANES, 1, 1, DIR>(p, in128, batch, s);
-        case 6: return launch_cfg<PLANES, 1, 2, DIR>(p, in128, batch, s);
+        case 1: return launch_contract<PLANES, 4, 4, 4, DIR>(p, batch, s);
+        case 2: return launch_contract<PLANES, 4, 2, 4, DIR>(p, batch, s);
+        case 3: return launch_contract<PLANES, 2, 4, 4, DIR>(p, batch, s);
+        case 4: return launch_contract<PLANES, 2, 8, 2, DIR>(p, batch, s);
+        case 5: return launch_contract<PLANES, 1, 1, 2, DIR>(p, batch, s);
+        case 6: return launch_contract<PLANES, 1, 4, 2, DIR>(p, batch, s);
+        case 7: return launch_contract<PLANES, 4, 1, 4, DIR>(p, batch, s);
+        case 8: return launch_contract<PLANES, 2, 2, 4, DIR>(p, batch, s);
+        case 9: return launch_contract<PLANES, 1, 2, 2, DIR>(p, batch, s);
+        case 10: return launch_contract<PLANES, 4, 4, 8, DIR>(p, batch, s);
+        case 11: return launch_contract<PLANES, 4, 2, 8, DIR>(p, batch, s);
+        case 12: return launch_contract<PLANES, 2, 4, 8, DIR>(p, batch, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int PLANES, int DIR>
+hipError_t launch_pack(const void* in, bool in128, void* ws, int N, int batch, hipStream_t s) {
+    const uint32_t Dp = padded_dim(N);
+    const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
+    const dim3 grid((Dp / XT) * (Dp / KT), batch);
+    if (in128) hipLaunchKernelGGL((pack_kernel<PLANES, DIR, true>), grid, dim3(256), 0, s, in, ws, N);
+    else hipLaunchKernelGGL((pack_kernel<PLANES, DIR, false>), grid, dim3(256), 0, s, in, ws, N);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -494,31 +502,42 @@ int mfma_tile_count(int /*planes*/) { return NTILES; }
 bool mfma_tile_valid(int /*planes*/, int tile, int N) {
     if (tile < 1 || tile > NTILES) return false;
     const TileDesc t = TILES[tile - 1];
-    const uint32_t D = 1u << N;
-    if (t.rb == 1 && t.waves == 1) return true;       // pads any N up to 32
-    return D >= (uint32_t)(t.rb * t.waves * 32);      // full row and K tiles
+    return padded_dim(N) >= (uint32_t)(t.rb * t.waves * 32);
 }
 
 int mfma_default_tile(int planes, int N) {
     (void)planes;
     if (N >= 9) return 1;
-    if (N == 8) return 2;
-    if (N == 7) return 4;
-    if (N == 6) return 6;
+    if (N == 8) return 3;
+    if (N == 7) return 6;
+    if (N == 6) return 9;
     return 5;
 }
 
+size_t mfma_workspace_bytes(int planes, int N, int batch) {
+    const size_t Dp = padded_dim(N);
+    return Dp * Dp * (size_t)(planes == 3 ? Pack<3>::EB : Pack<1>::EB) * (size_t)batch;
+}
+
 hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* out,
-                       bool out_c128, int N, int batch, double scale, int tile,
+                       bool out_c128, int N, int batch, double scale, int tile, void* ws,
                        hipStream_t stream) {
     if (tile == 0) tile = mfma_default_tile(planes, N);
     if (!mfma_tile_valid(planes, tile, N)) return hipErrorInvalidValue;
-    Params p{in, out, N, out_c128 ? 1 : 0, scale};
+    hipError_t e;
     if (planes == 3)
-        return dir == FORWARD ? launch_tile<3, FORWARD>(tile, p, in_c128, batch, stream)
-                              : launch_tile<3, ADJOINT>(tile, p, in_c128, batch, stream);
-    return dir == FORWARD ? launch_tile<1, FORWARD>(tile, p, in_c128, batch, stream)
-                          : launch_tile<1, ADJOINT>(tile, p, in_c128, batch, stream);
+        e = dir == FORWARD ? launch_pack<3, FORWARD>(in, in_c128, ws, N, batch, stream)
+                           : launch_pack<3, ADJOINT>(in, in_c128, ws, N, batch, stream);
+    else
+        e = dir == FORWARD ? launch_pack<1, FORWARD>(in, in_c128, ws, N, batch, stream)
+                           : launch_pack<1, ADJOINT>(in, in_c128, ws, N, batch, stream);
+    if (e != hipSuccess) return e;
+    Params p{ws, out, N, out_c128 ? 1 : 0, scale};
+    if (planes == 3)
+        return dir == FORWARD ? launch_tile<3, FORWARD>(tile, p, batch, stream)
+                              : launch_tile<3, ADJOINT>(tile, p, batch, stream);
+    return dir == FORWARD ? launch_tile<1, FORWARD>(tile, p, batch, stream)
+                          : launch_tile<1, ADJOINT>(tile, p, batch, stream);
 }
 
 }  // namespace pauli
