@@ -114,22 +114,41 @@ int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
                              const pauli_opts* opts);
 
 /*
- * Decompose `count` matrices of uneven sizes in one persistent launch:
- * G[k] (device pointer) holds a 2^N[k] x 2^N[k] matrix, out[k] receives its
- * 4^N[k] coefficients.  G, N and out are HOST arrays of length count.
- * 1 <= N[k] <= 12, count >= 1; algo SPLIT_BF16 or FP32, C64 in and out.
- * opts->workspace must hold pauli_batched_workspace_bytes(count) bytes of
- * device memory that stays valid and untouched while the launch runs.  The
- * launch is captured in a HIP graph cached per (stream, workspace, sizes) and
- * replayed on later calls with the same key; the descriptor table is copied
- * into the workspace on every call, so new pointers are honoured.  Calls that
- * share a workspace must be ordered on one stream.
+ * Decompose `count` matrices of uneven sizes (section 3: coefficients are
+ * independent, here also across matrices): G[k] (device pointer) holds a
+ * 2^N[k] x 2^N[k] matrix, out[k] receives its 4^N[k] coefficients.  G, N and
+ * out are HOST arrays of length count.  1 <= N[k] <= 12, count >= 1; algo
+ * SPLIT_BF16 or FP32, C64 in and out.
+ * opts->workspace (required) must hold pauli_batched_workspace_bytes(count,
+ * N, algo) bytes of device memory that stays untouched while the work runs.
+ * The work is one batched pack launch and one persistent contraction launch
+ * whose workgroups take output tiles (largest matrices first) from a counter
+ * in the workspace.  Both are captured once per (stream, workspace, algo,
+ * tile, N list) in a HIP graph that later calls replay; the descriptor table
+ * (pointers) is copied into the workspace on every call, so new buffers are
+ * honoured.  opts->tile: 0 = the tuned or default shape, 1..
+ * pauli_batched_tile_count() forces one.  Calls sharing a workspace must be
+ * ordered on one stream.
  */
 int pauli_decompose_batched(int count, const void* const* G, const int* N, void* const* out,
                             const pauli_opts* opts);
 
-/* Device workspace bytes pauli_decompose_batched needs for `count` matrices. */
-size_t pauli_batched_workspace_bytes(int count);
+/* Workspace bytes pauli_decompose_batched needs (0 for invalid arguments). */
+size_t pauli_batched_workspace_bytes(int count, const int* N, int algo);
+
+/* Number of persistent-kernel tile shapes for the uneven batch. */
+int pauli_batched_tile_count(void);
+
+/*
+ * Run pauli_decompose_batched with every tile shape on the given buffers
+ * (outputs are overwritten with the same correct result), time each and keep
+ * the fastest for this list of N values.  Blocking.
+ */
+int pauli_autotune_batched(int count, const void* const* G, const int* N, void* const* out,
+                           const pauli_opts* opts);
+
+/* Tile shape pauli_decompose_batched would use for this N list and algo. */
+int pauli_batched_tile_selected(int count, const int* N, int algo);
 
 /*
  * Device scratch bytes pauli_decompose, pauli_reconstruct and

@@ -47,7 +47,8 @@ _lib = None
 _lock = threading.Lock()
 
 EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward",
-           "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_workspace_bytes", "pauli_autotune",
+           "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_workspace_bytes",
+           "pauli_batched_tile_count", "pauli_autotune_batched", "pauli_batched_tile_selected", "pauli_autotune",
            "pauli_tile_count", "pauli_tile_selected", "pauli_last_error", "pauli_version"]
 
 
@@ -69,8 +70,15 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_decompose_batched.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(ci),
                                                 ctypes.POINTER(vp), op]
         lib.pauli_decompose_batched.restype = ci
-        lib.pauli_batched_workspace_bytes.argtypes = [ci]
+        ip = ctypes.POINTER(ci)
+        lib.pauli_batched_workspace_bytes.argtypes = [ci, ip, ci]
         lib.pauli_batched_workspace_bytes.restype = ctypes.c_size_t
+        lib.pauli_autotune_batched.argtypes = [ci, ctypes.POINTER(vp), ip, ctypes.POINTER(vp), op]
+        lib.pauli_autotune_batched.restype = ci
+        lib.pauli_batched_tile_count.argtypes = []
+        lib.pauli_batched_tile_count.restype = ci
+        lib.pauli_batched_tile_selected.argtypes = [ci, ip, ci]
+        lib.pauli_batched_tile_selected.restype = ci
         lib.pauli_workspace_bytes.argtypes = [ci, ci, ci]
         lib.pauli_workspace_bytes.restype = ctypes.c_size_t
         lib.pauli_autotune.argtypes = [ci, ci, op]
@@ -194,33 +202,53 @@ def decompose_backward(grad_c: torch.Tensor, algo: str = "split_bf16", out_dtype
     return G
 
 
-_workspaces = {}
+_batch_ws = {}
 
 
-def decompose_batched(mats, algo: str = "split_bf16", outs=None):
-    """Decompose complex64 matrices of uneven size in one persistent launch.
-    Returns a list of coefficient tensors (or fills `outs`)."""
+def _batch_args(mats, algo, outs):
     mats = [_prep(m) for m in mats]
+    for m in mats:
+        if m.dtype != torch.complex64:
+            raise TypeError("decompose_batched takes complex64 matrices")
     count = len(mats)
-    if count == 0:
-        return []
     dev = mats[0].device
     Ns = [_qubits_of_matrix(m) for m in mats]
     if outs is None:
         outs = [torch.empty(1 << (2 * n), dtype=torch.complex64, device=dev) for n in Ns]
     lib = load_library()
-    need = lib.pauli_batched_workspace_bytes(count)
-    key = (dev, count)
-    ws = _workspaces.get(key)
-    if ws is None or ws.numel() < need:
+    Na = (ctypes.c_int * count)(*Ns)
+    need = lib.pauli_batched_workspace_bytes(count, Na, ALGOS[algo])
+    key = (dev, algo, tuple(Ns))
+    ws = _batch_ws.get(key)
+    if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-        _workspaces[key] = ws
+        _batch_ws[key] = ws
     Gp = (ctypes.c_void_p * count)(*[m.data_ptr() for m in mats])
     Op = (ctypes.c_void_p * count)(*[o.data_ptr() for o in outs])
-    Na = (ctypes.c_int * count)(*Ns)
-    o = _opts(algo, 0, 0, 0, _stream(mats[0]), ws)
-    _check(lib.pauli_decompose_batched(count, Gp, Na, Op, ctypes.byref(o)))
+    return mats, outs, count, Na, Gp, Op, ws
+
+
+def decompose_batched(mats, algo: str = "split_bf16", outs=None, tile: int = 0):
+    """Decompose complex64 matrices of uneven size: one batched pack launch and
+    one persistent contraction launch, replayed from a cached HIP graph.
+    Returns a list of coefficient tensors (or fills `outs`).  The workspace is
+    cached per N list, so repeated calls with the same sizes replay the graph."""
+    if len(mats) == 0:
+        return []
+    mats, outs, count, Na, Gp, Op, ws = _batch_args(mats, algo, outs)
+    o = _opts(algo, 0, 0, tile, _stream(mats[0]), ws)
+    _check(load_library().pauli_decompose_batched(count, Gp, Na, Op, ctypes.byref(o)))
     return outs
+
+
+def autotune_batched(mats, algo: str = "split_bf16", outs=None) -> int:
+    """Time every persistent tile shape on this batch and keep the fastest for
+    its N list; returns the chosen tile (outputs hold the decomposition)."""
+    mats, outs, count, Na, Gp, Op, ws = _batch_args(mats, algo, outs)
+    o = _opts(algo, 0, 0, 0, _stream(mats[0]), ws)
+    lib = load_library()
+    _check(lib.pauli_autotune_batched(count, Gp, Na, Op, ctypes.byref(o)))
+    return lib.pauli_batched_tile_selected(count, Na, ALGOS[algo])
 
 
 def autotune(n_min: int, n_max: int, algo: str = "split_bf16", device=None) -> dict:
@@ -243,4 +271,5 @@ def tile_selected(N: int, algo: str = "split_bf16") -> int:
 from .autograd import PauliDecompose  # noqa: E402
 
 __all__ = ["decompose", "reconstruct", "decompose_backward", "decompose_batched", "autotune",
+           "autotune_batched", "workspace",
            "PauliDecompose", "PauliError", "load_library", "last_error", "ALGOS", "EXPORTS"]

@@ -225,11 +225,6 @@ size_t pauli_workspace_bytes(int algo, int N, int batch) {
     return mfma_workspace_bytes(planes_of(algo), N, batch);
 }
 
-size_t pauli_batched_workspace_bytes(int count) {
-    if (count < 1) return 0;
-    return batched_workspace_bytes(count);
-}
-
 int pauli_tile_count(int algo) {
     if (algo == PAULI_ALGO_FP64_GRAY) return 1;
     if (!valid_algo(algo)) return 0;
@@ -248,44 +243,75 @@ int pauli_version(void) { return 1; }
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Uneven batch: persistent launch behind a cached HIP graph.
+// Uneven batch: batched pack + persistent contraction behind a cached graph.
+// Workspace layout: [descriptor table | counter | packed operands].
 // ---------------------------------------------------------------------------
 namespace {
+
+size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+struct BatchLayout {
+    std::vector<int> order;        // matrix index of every descriptor slot (LPT: larger N first)
+    std::vector<size_t> ws_off;    // per slot
+    std::vector<uint32_t> pack0;   // per slot
+    std::vector<uint32_t> tile0;   // per slot
+    uint32_t pack_total = 0, tile_total = 0;
+    size_t table_bytes = 0, counter_off = 0, packed_off = 0, total_bytes = 0;
+};
+
+BatchLayout batch_layout(int count, const int* N, int planes, int btile) {
+    BatchLayout L;
+    L.order.resize(count);
+    for (int k = 0; k < count; ++k) L.order[k] = k;
+    std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) { return N[a] > N[b]; });
+    size_t off = 0;
+    for (int slot = 0; slot < count; ++slot) {
+        const int n = N[L.order[slot]];
+        L.ws_off.push_back(off);
+        L.pack0.push_back(L.pack_total);
+        L.tile0.push_back(L.tile_total);
+        off += round256(batched_packed_bytes(planes, n));
+        L.pack_total += batched_pack_tiles(n);
+        L.tile_total += batched_output_tiles(btile, n);
+    }
+    L.table_bytes = round256(sizeof(BatchItem) * (size_t)count);
+    L.counter_off = L.table_bytes;
+    L.packed_off = L.counter_off + 256;
+    L.total_bytes = L.packed_off + off;
+    return L;
+}
 
 struct GraphKey {
     hipStream_t stream;
     void* workspace;
-    int planes;
+    int planes, btile;
     std::vector<int> ns;
     bool operator<(const GraphKey& o) const {
-        return std::tie(stream, workspace, planes, ns) < std::tie(o.stream, o.workspace, o.planes, o.ns);
+        return std::tie(stream, workspace, planes, btile, ns) < std::tie(o.stream, o.workspace, o.planes, o.btile, o.ns);
     }
 };
 
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
-    std::vector<int> order;  // matrix index of every descriptor slot
-    int total_tiles = 0;
-    BatchItem* pinned = nullptr;  // host staging of the descriptor table
-    hipEvent_t copied = nullptr;  // staging may be rewritten once this fires
+    BatchLayout layout;
+    BatchItem* pinned = nullptr;   // host staging of the descriptor table
+    hipEvent_t copied = nullptr;   // the staging may be rewritten once this has fired
 };
 
 std::mutex g_graph_mu;
 std::map<GraphKey, GraphEntry> g_graphs;
+std::map<std::pair<int, std::vector<int>>, int> g_btile;   // (planes, sorted Ns) -> tuned tile
 
-}  // namespace
-
-extern "C" int pauli_decompose_batched(int count, const void* const* G, const int* N,
-                                       void* const* out, const pauli_opts* opts) {
-    const char* fn = "pauli_decompose_batched";
-    const pauli_opts o = resolve(opts);
+int validate_batch(int count, const void* const* G, const int* N, void* const* out, const pauli_opts& o,
+                   const char* fn) {
     if (count < 1) return fail(PAULI_EINVAL, "%s: count=%d must be >= 1", fn, count);
     if (!G || !N || !out) return fail(PAULI_EINVAL, "%s: NULL array", fn);
     if (o.algo != PAULI_ALGO_SPLIT_BF16 && o.algo != PAULI_ALGO_FP32)
-        return fail(PAULI_EUNSUPPORTED, "%s: algo %d not available batched (SPLIT_BF16 or FP32)", fn,
-                    o.algo);
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d not available batched (SPLIT_BF16 or FP32)", fn, o.algo);
     if (o.in_dtype != PAULI_C64 || o.out_dtype != PAULI_C64)
         return fail(PAULI_EUNSUPPORTED, "%s: only C64 input and output", fn);
+    if (o.tile < 0 || o.tile > batched_tile_count())
+        return fail(PAULI_EINVAL, "%s: tile %d outside [0, %d]", fn, o.tile, batched_tile_count());
     for (int k = 0; k < count; ++k) {
         if (N[k] < 1 || N[k] > N_MAX_BATCHED)
             return fail(PAULI_EINVAL, "%s: N[%d]=%d outside [1, %d]", fn, k, N[k], N_MAX_BATCHED);
@@ -296,77 +322,155 @@ extern "C" int pauli_decompose_batched(int count, const void* const* G, const in
         if (overlaps(G[k], bytes, out[k], bytes))
             return fail(PAULI_EINVAL, "%s: input and output of matrix %d overlap", fn, k);
     }
-    const size_t need = batched_workspace_bytes(count);
-    if (!o.workspace || o.workspace_bytes < need)
-        return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
-                    o.workspace ? o.workspace_bytes : (size_t)0);
-    if ((uintptr_t)o.workspace % 256)
-        return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+    return PAULI_OK;
+}
 
+int tuned_btile(int planes, int count, const int* N) {
+    std::vector<int> ns(N, N + count);
+    std::sort(ns.begin(), ns.end());
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_btile.find({planes, ns});
+    return it == g_btile.end() ? 1 : it->second;
+}
+
+int run_batched(int count, const void* const* G, const int* N, void* const* out, const pauli_opts& o, int btile,
+                const char* fn) {
     const int planes = planes_of(o.algo);
+    const BatchLayout probe = batch_layout(count, N, planes, btile);
+    if (!o.workspace || o.workspace_bytes < probe.total_bytes)
+        return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, probe.total_bytes,
+                    o.workspace ? o.workspace_bytes : (size_t)0);
+    if ((uintptr_t)o.workspace % 256) return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+    for (int k = 0; k < count; ++k) {
+        const size_t bytes = ((size_t)1 << (2 * N[k])) * 8;
+        if (overlaps(o.workspace, probe.total_bytes, G[k], bytes) ||
+            overlaps(o.workspace, probe.total_bytes, out[k], bytes))
+            return fail(PAULI_EINVAL, "%s: workspace overlaps matrix %d", fn, k);
+    }
     hipStream_t s = (hipStream_t)o.stream;
-    GraphKey key{s, o.workspace, planes, std::vector<int>(N, N + count)};
+    unsigned char* ws = (unsigned char*)o.workspace;
+    BatchItem* items_dev = (BatchItem*)ws;
+    unsigned int* counter_dev = (unsigned int*)(ws + probe.counter_off);
+    unsigned char* packed = ws + probe.packed_off;
+    GraphKey key{s, o.workspace, planes, btile, std::vector<int>(N, N + count)};
     std::lock_guard<std::mutex> lk(g_graph_mu);
     GraphEntry& ge = g_graphs[key];
     hipError_t e;
-    BatchItem* items_dev = (BatchItem*)o.workspace;
-    unsigned int* counter_dev =
-        (unsigned int*)((char*)o.workspace + ((sizeof(BatchItem) * count + 255) / 256) * 256);
     if (!ge.exec) {
-        // Longest-processing-time order: largest matrices first.
-        ge.order.resize(count);
-        for (int k = 0; k < count; ++k) ge.order[k] = k;
-        std::stable_sort(ge.order.begin(), ge.order.end(),
-                         [&](int a, int b) { return N[a] > N[b]; });
-        int tiles = 0;
-        for (int k = 0; k < count; ++k) tiles += batched_tiles_for(N[ge.order[k]]);
-        ge.total_tiles = tiles;
+        ge.layout = probe;
         if ((e = hipHostMalloc((void**)&ge.pinned, sizeof(BatchItem) * count)) != hipSuccess) {
             g_graphs.erase(key);
             return hip_fail(e, fn);
         }
         if ((e = hipEventCreateWithFlags(&ge.copied, hipEventDisableTiming)) != hipSuccess) {
+            (void)hipHostFree(ge.pinned);
             g_graphs.erase(key);
             return hip_fail(e, fn);
         }
+        // Capture on a private stream: batched pack, counter reset, persistent contraction.
         hipStream_t cap;
-        if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
-            return hip_fail(e, fn);
-        hipGraph_t graph;
+        if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, fn);
+        hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = launch_batched(planes, items_dev, count, ge.total_tiles, counter_dev, cap);
+            const hipError_t le = launch_batched(planes, btile, items_dev, count, probe.pack_total, probe.tile_total,
+                                                 packed, counter_dev, cap);
             e = hipStreamEndCapture(cap, &graph);
             if (le != hipSuccess) e = le;
         }
-        if (e == hipSuccess) {
-            e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
         (void)hipStreamDestroy(cap);
         if (e != hipSuccess) {
             ge.exec = nullptr;
             return hip_fail(e, fn);
         }
     }
-    // Refresh the descriptor table (pointers may differ between calls).
+    // Refresh the descriptor table: pointers may differ between calls.
     if ((e = hipEventSynchronize(ge.copied)) != hipSuccess) return hip_fail(e, fn);
-    int tile0 = 0;
+    const BatchLayout& L = ge.layout;
     for (int slot = 0; slot < count; ++slot) {
-        const int k = ge.order[slot];
+        const int k = L.order[slot];
         ge.pinned[slot].in = G[k];
         ge.pinned[slot].out = out[k];
+        ge.pinned[slot].ws_off = L.ws_off[slot];
         ge.pinned[slot].n = N[k];
-        ge.pinned[slot].tile0 = tile0;
-        tile0 += batched_tiles_for(N[k]);
+        ge.pinned[slot].pack0 = L.pack0[slot];
+        ge.pinned[slot].tile0 = L.tile0[slot];
     }
-    if ((e = hipMemcpyAsync(items_dev, ge.pinned, sizeof(BatchItem) * count, hipMemcpyHostToDevice,
-                            s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(items_dev, ge.pinned, sizeof(BatchItem) * count, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, fn);
     if ((e = hipEventRecord(ge.copied, s)) != hipSuccess) return hip_fail(e, fn);
     if ((e = hipGraphLaunch(ge.exec, s)) != hipSuccess) return hip_fail(e, fn);
     g_last_error.clear();
     return PAULI_OK;
+}
+
+}  // namespace
+
+extern "C" size_t pauli_batched_workspace_bytes(int count, const int* N, int algo) {
+    if (count < 1 || !N || (algo != PAULI_ALGO_SPLIT_BF16 && algo != PAULI_ALGO_FP32)) return 0;
+    for (int k = 0; k < count; ++k)
+        if (N[k] < 1 || N[k] > N_MAX_BATCHED) return 0;
+    return batch_layout(count, N, planes_of(algo), 1).total_bytes;
+}
+
+extern "C" int pauli_decompose_batched(int count, const void* const* G, const int* N, void* const* out,
+                                       const pauli_opts* opts) {
+    const char* fn = "pauli_decompose_batched";
+    const pauli_opts o = resolve(opts);
+    int st = validate_batch(count, G, N, out, o, fn);
+    if (st != PAULI_OK) return st;
+    const int btile = o.tile > 0 ? o.tile : tuned_btile(planes_of(o.algo), count, N);
+    return run_batched(count, G, N, out, o, btile, fn);
+}
+
+extern "C" int pauli_autotune_batched(int count, const void* const* G, const int* N, void* const* out,
+                                      const pauli_opts* opts) {
+    const char* fn = "pauli_autotune_batched";
+    const pauli_opts o = resolve(opts);
+    int st = validate_batch(count, G, N, out, o, fn);
+    if (st != PAULI_OK) return st;
+    const int planes = planes_of(o.algo);
+    hipStream_t s = (hipStream_t)o.stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    int best = 1;
+    float best_ms = 1e30f;
+    for (int t = 1; t <= batched_tile_count() && e == hipSuccess; ++t) {
+        if ((st = run_batched(count, G, N, out, o, t, fn)) != PAULI_OK) break;   // warm-up + capture
+        if ((e = hipEventRecord(a, s)) != hipSuccess) break;
+        for (int r = 0; r < 5 && st == PAULI_OK; ++r) st = run_batched(count, G, N, out, o, t, fn);
+        if (st != PAULI_OK) break;
+        if ((e = hipEventRecord(b, s)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+        float ms = 0;
+        if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (st != PAULI_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, fn);
+    std::vector<int> ns(N, N + count);
+    std::sort(ns.begin(), ns.end());
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_btile[{planes, ns}] = best;
+    }
+    g_last_error.clear();
+    return PAULI_OK;
+}
+
+extern "C" int pauli_batched_tile_count(void) { return batched_tile_count(); }
+
+extern "C" int pauli_batched_tile_selected(int count, const int* N, int algo) {
+    if (count < 1 || !N || (algo != PAULI_ALGO_SPLIT_BF16 && algo != PAULI_ALGO_FP32)) return 0;
+    return tuned_btile(planes_of(algo), count, N);
 }
 
 // ---------------------------------------------------------------------------

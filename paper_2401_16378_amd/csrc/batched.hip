@@ -1,11 +1,151 @@
-// Uneven batch (placeholder until the persistent kernel lands).
-#include "common.hpp"
-#include "internal.hpp"
+// Uneven batch: many matrices of different order decomposed by one batched
+// pack launch and one persistent contraction launch (the paper's embarrassing
+// parallelism over coefficients, section 3, extended over matrices).
+//
+// The host builds a descriptor table in device memory: one entry per matrix,
+// in decreasing order of N (longest-processing-time first), with the matrix's
+// packed-operand offset and its first pack tile and first output tile in the
+// batch-wide numbering.  The pack kernel maps its block index to (matrix,
+// tile) by binary search over the first-tile fields.  The contraction kernel
+// is persistent: each workgroup takes output tiles from a single atomic
+// counter until the list is exhausted, so every workgroup ends once the
+// counter passes the last tile and the grid drains.  A one-thread kernel
+// zeroes the counter before each contraction launch (no memset node, so the
+// sequence can be captured in a HIP graph and replayed).
+#include "mfma_tile.hpp"
 
 namespace pauli {
-size_t batched_workspace_bytes(int count) { return ((sizeof(BatchItem) * count + 255) / 256) * 256 + 256; }
-int batched_tiles_for(int n) { return 1 << (n > 5 ? n - 5 : 0); }
-hipError_t launch_batched(int, const BatchItem*, int, int, unsigned int*, hipStream_t) {
-    return hipErrorNotSupported;
+namespace {
+
+using namespace mfma;
+
+// Slot of the matrix owning batch-wide index t (first_of[k] increasing).
+__device__ inline int find_slot(const BatchItem* items, int count, uint32_t t, bool pack) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const uint32_t first = pack ? items[mid].pack0 : items[mid].tile0;
+        if (first <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
+
+template <int PLANES>
+__global__ __launch_bounds__(256) void pack_batched_kernel(const BatchItem* __restrict__ items, int count,
+                                                           unsigned char* __restrict__ ws) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES>()];
+    const int k = find_slot(items, count, blockIdx.x, true);
+    const BatchItem it = items[k];
+    pack_tile<PLANES, FORWARD, false>((const unsigned char*)it.in, ws + it.ws_off, it.n,
+                                      blockIdx.x - it.pack0, lds);
+}
+
+__global__ void reset_counter_kernel(unsigned int* counter) {
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+template <int PLANES, int RB, int WAVES, int PF>
+__global__ __launch_bounds__(WAVES * 64) void contract_batched_kernel(const BatchItem* __restrict__ items,
+                                                                      int count, uint32_t total,
+                                                                      const unsigned char* __restrict__ ws,
+                                                                      unsigned int* __restrict__ counter) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    __shared__ uint32_t next;
+    constexpr int MT = WAVES * RB * 32;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t t = next;
+        __syncthreads();           // everyone has read `next` before it is rewritten
+        if (t >= total) break;     // uniform: every workgroup leaves once the list is done
+        const int k = find_slot(items, count, t, false);
+        const BatchItem it = items[k];
+        const uint32_t Dp = padded_dim(it.n);
+        const uint32_t nMB = Dp > (uint32_t)MT ? Dp / MT : 1u;
+        const uint32_t local = t - it.tile0;
+        contract_tile<PLANES, RB, WAVES, FORWARD, PF>(ws + it.ws_off, (unsigned char*)it.out, it.n,
+                                                      local / nMB, local % nMB, 1.0 / (double)(1u << it.n),
+                                                      0, lds);
+    }
+}
+
+// Tile shapes the persistent kernel can run with: (RB, WAVES, PF).
+struct BTile {
+    int rb, waves, pf;
+};
+constexpr BTile BTILES[] = {
+    {2, 4, 4},  // 1: 256 rows per output tile
+    {1, 4, 2},  // 2: 128 rows
+    {4, 4, 4},  // 3: 512 rows
+    {1, 2, 2},  // 4: 64 rows
+};
+constexpr int NBTILES = sizeof(BTILES) / sizeof(BTILES[0]);
+
+template <int PLANES, int RB, int WAVES, int PF>
+hipError_t launch_contract_batched(const BatchItem* items, int count, uint32_t total, const unsigned char* ws,
+                                   unsigned int* counter, hipStream_t s) {
+    auto kern = contract_batched_kernel<PLANES, RB, WAVES, PF>;
+    const int lds = WAVES * 1024 * 8;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WAVES * 64, lds)) !=
+        hipSuccess)
+        return e;
+    if (per_cu < 1) per_cu = 1;
+    uint32_t grid = (uint32_t)cus * (uint32_t)per_cu;
+    if (grid > total) grid = total;   // never more workgroups than tiles
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES * 64), lds, s, items, count, total, ws, counter);
+    return hipGetLastError();
+}
+
+template <int PLANES>
+hipError_t launch_contract_btile(int btile, const BatchItem* items, int count, uint32_t total,
+                                 const unsigned char* ws, unsigned int* counter, hipStream_t s) {
+    switch (btile) {
+        case 1: return launch_contract_batched<PLANES, 2, 4, 4>(items, count, total, ws, counter, s);
+        case 2: return launch_contract_batched<PLANES, 1, 4, 2>(items, count, total, ws, counter, s);
+        case 3: return launch_contract_batched<PLANES, 4, 4, 4>(items, count, total, ws, counter, s);
+        case 4: return launch_contract_batched<PLANES, 1, 2, 2>(items, count, total, ws, counter, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int batched_tile_count() { return NBTILES; }
+
+uint32_t batched_output_tiles(int btile, int n) {
+    const BTile t = BTILES[btile - 1];
+    const uint32_t MT = t.rb * t.waves * 32;
+    const uint32_t Dp = mfma::padded_dim(n);
+    return (Dp > MT ? Dp / MT : 1u) * (Dp / mfma::XT);
+}
+
+uint32_t batched_pack_tiles(int n) { return mfma::pack_tiles(n); }
+
+size_t batched_packed_bytes(int planes, int n) {
+    const size_t Dp = mfma::padded_dim(n);
+    return Dp * Dp * (size_t)(planes == 3 ? mfma::Pack<3>::EB : mfma::Pack<1>::EB);
+}
+
+hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, int count, uint32_t pack_total,
+                          uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
+                          hipStream_t stream) {
+    if (btile < 1 || btile > NBTILES) return hipErrorInvalidValue;
+    if (planes == 3)
+        hipLaunchKernelGGL((pack_batched_kernel<3>), dim3(pack_total), dim3(256), 0, stream, items_dev, count, packed);
+    else
+        hipLaunchKernelGGL((pack_batched_kernel<1>), dim3(pack_total), dim3(256), 0, stream, items_dev, count, packed);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, counter_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return planes == 3 ? launch_contract_btile<3>(btile, items_dev, count, tile_total, packed, counter_dev, stream)
+                       : launch_contract_btile<1>(btile, items_dev, count, tile_total, packed, counter_dev, stream);
+}
+
 }  // namespace pauli

@@ -27,16 +27,22 @@ int mfma_tile_count(int planes);
 bool mfma_tile_valid(int planes, int tile, int N);
 int mfma_default_tile(int planes, int N);
 
-// Uneven batch: device descriptor table built by the host.
+// Uneven batch: device descriptor table built by the host, one entry per
+// matrix in processing order.
 struct BatchItem {
-    const void* in;   // matrix of order 2^n
-    void* out;        // 4^n coefficients
+    const void* in;   // complex64 matrix of order 2^n
+    void* out;        // its 4^n complex64 coefficients
+    size_t ws_off;    // byte offset of its packed operand in the packed area
     int n;            // qubit count
-    int tile0;        // first linear tile id of this matrix in the work list
+    uint32_t pack0;   // first pack tile of this matrix in the batch numbering
+    uint32_t tile0;   // first output tile of this matrix in the batch numbering
 };
-size_t batched_workspace_bytes(int count);
-hipError_t launch_batched(int planes, const BatchItem* items_dev, int count, int total_tiles,
-                          unsigned int* counter_dev, hipStream_t stream);
-int batched_tiles_for(int n);
+int batched_tile_count();
+uint32_t batched_output_tiles(int btile, int n);
+uint32_t batched_pack_tiles(int n);
+size_t batched_packed_bytes(int planes, int n);
+hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, int count, uint32_t pack_total,
+                          uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
+                          hipStream_t stream);
 
 }  // namespace pauli

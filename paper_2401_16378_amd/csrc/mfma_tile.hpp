@@ -1,0 +1,479 @@
+// Device building blocks of the matrix-core path, shared by the
+// single-matrix kernels (mfma.hip) and the persistent uneven-batch kernel
+// (batched.hip).
+#pragma once
+//
+// Matrix-core (MFMA) path for gfx950: the paper's O(2^N)-per-coefficient
+// sum (Eq. (c_def_in_terms_of_fn)) for all coefficients at once, i.e. the
+// O(8^N) total of section 3, evaluated as a dense contraction
+//
+//     C[p][x] = sum_q H[p][q] * In[q][x],      H[p][q] = (-1)^{popc(p & q)}
+//
+// forward (decomposition):  q = i, p = z, In[i][x] = G[i^x][i] (the gathered
+//   XOR diagonal v_x), out[n(x,z)] = 2^-N (-i)^{popc(x&z)} C[z][x];
+// adjoint (recomposition / gradient):  q = z, p = i,
+//   In[z][x] = i^{popc(x&z)} c[n(x,z)],  G[i^x][i] = scale * C[i][x].
+//
+// Two kernels.
+//
+// pack: an HBM-bound pass that gathers In (the XOR diagonals of G, or the
+//   phased coefficient blocks), converts it to the matrix-core operand
+//   format and stores it in the exact lane order of the MFMA B operand, one
+//   contiguous 1 KiB fragment (64 lanes x 16 bytes) per (32 flip masks,
+//   16 or 8 K values, plane, re/im).  A thread owns an aligned 4x4
+//   micro-block: 4 rows x 4 columns of G, which the XOR map sends to 4 flip
+//   masks x 4 consecutive q, or 16 consecutive coefficients, which form a
+//   4x4 (z,x) block; the block is transposed through LDS so every global
+//   store is a full 1 KiB fragment.
+//
+// contract: each wave owns RB*32 rows p and 32 flip masks x (64 real B
+//   columns: re, then im) and walks the whole K range, streaming its B
+//   fragments from L2 through a register ring PF slices deep.  H is the
+//   Sylvester-Hadamard sign matrix: every entry is +-1, exact in any format,
+//   so it never touches memory; over an aligned 32-row block it is one fixed
+//   32x32 block times a sign fixed by the blocks' high bits, and the kernel
+//   keeps that block's fragments and their negations in registers, choosing
+//   among them at compile time plus one uniform sign per group of slices.
+//   No LDS and no barrier in the main loop; the epilogue stages each 32x32
+//   output block in LDS so it leaves as one contiguous run of coefficients
+//   (forward) or one aligned 32x32 square of G (adjoint).
+//
+// Precision.  PLANES = 3: each binary32 component g is split as
+// g ~ hi + mid + lo (three bf16 numbers, hi on a power-of-two grid shared by
+// the 4x4 micro-block, see split3); bf16 MFMA accumulates hi into one FP32
+// accumulator, where the sums stay exact, and mid + lo into a second, and the
+// two are added in binary64 in the epilogue before the phase and scale.
+// PLANES = 1: binary32 MFMA on the binary32 components.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pauli {
+namespace mfma {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int XT = 32;       // flip masks per fragment column block
+constexpr int FRAG = 1024;   // bytes per B fragment (64 lanes x 16 bytes)
+
+__device__ inline uint32_t pack_bf16(float a, float b) {
+    f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ inline float lo_half(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
+__device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u & 0xFFFF0000u); }
+
+// Three-way bf16 split of two binary32 values a, b against a power-of-two
+// grid u (with inv_u = 1/u, both exact):
+//   hi  = u * rint(x / u)        (|x| < 256 u, so hi has <= 8 significant bits
+//                                 and is exact in bf16)
+//   mid = bf16(x - hi),  lo = bf16(x - hi - mid)
+// x - hi and x - hi - mid are exact in binary32, so hi + mid + lo carries
+// every bit of x except at most those below 2^-17 |x - hi|.  All hi terms of
+// a micro-block are multiples of the same u, which keeps the FP32 sums of hi
+// terms exact over the whole K range for any input whose partial sums stay
+// below 2^24 times the smallest grid (about 2^16 times the smallest block
+// maximum), instead of rounding away the low bits of small terms.
+__device__ inline void split3(float a, float b, float u, float inv_u, uint32_t& h, uint32_t& m,
+                              uint32_t& l) {
+    const float ha = __builtin_rintf(a * inv_u) * u, hb = __builtin_rintf(b * inv_u) * u;
+    h = pack_bf16(ha, hb);
+    const float ra = a - ha, rb = b - hb;
+    m = pack_bf16(ra, rb);
+    const float qa = ra - lo_half(m), qb = rb - hi_half(m);
+    l = pack_bf16(qa, qb);
+}
+
+// Grid of a micro-block: u = 2^(e-8) for the exponent e with max|x| < 2^e,
+// clamped so that u and 1/u stay normal binary32 numbers.
+__device__ inline void block_grid(float maxabs, float& u, float& inv_u) {
+    int e = (int)((__builtin_bit_cast(uint32_t, maxabs) >> 23) & 0xFFu) - 126;
+    e = e < -110 ? -110 : (e > 120 ? 120 : e);
+    u = __builtin_bit_cast(float, (uint32_t)(127 + e - 8) << 23);
+    inv_u = __builtin_bit_cast(float, (uint32_t)(127 - e + 8) << 23);
+}
+
+template <bool IN128>
+__device__ inline f32x2 load_elem(const unsigned char* base, size_t idx) {
+    if constexpr (IN128) {
+        const double2 v = ((const double2*)base)[idx];
+        return f32x2{(float)v.x, (float)v.y};
+    } else {
+        const float2 v = ((const float2*)base)[idx];
+        return f32x2{v.x, v.y};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Packed operand layout, per matrix, with Dp = max(2^N, 32):
+//   bf16: fragment (xb, s, pl, cb) at ((xb * Dp/16 + s) * 6 + pl * 2 + cb) KiB,
+//         lane l = x_l + 32h holds K = 16s + 8h + j, j < 8, of column x_l;
+//   fp32: fragment (xb, s, cb) at ((xb * Dp/8 + s) * 2 + cb) KiB,
+//         lane l holds K = 8s + 4h + t, t < 4.
+// pl = hi/mid/lo plane, cb = 0 real parts, 1 imaginary parts.
+// ---------------------------------------------------------------------------
+template <int PLANES>
+struct Pack {
+    static constexpr int SK = PLANES == 3 ? 16 : 8;        // K per slice
+    static constexpr int NPL = PLANES == 3 ? 6 : 2;        // fragments per slice
+    static constexpr int ESZ = PLANES == 3 ? 2 : 4;        // bytes per element
+    static constexpr int SLICE_BYTES = NPL * FRAG;
+    static constexpr int EB = NPL * ESZ;                   // packed bytes per matrix element
+};
+
+__host__ __device__ inline uint32_t padded_dim(int N) { return N < 5 ? 32u : (1u << N); }
+
+constexpr int PACK_KT = 128;   // K per pack workgroup (less when Dp < 128)
+
+template <int PLANES>
+constexpr int pack_lds_bytes() {
+    return Pack<PLANES>::NPL * XT * (PACK_KT * Pack<PLANES>::ESZ + 16);
+}
+
+inline uint32_t pack_tiles(int N) {
+    const uint32_t Dp = padded_dim(N);
+    const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
+    return (Dp / XT) * (Dp / KT);
+}
+
+// Pack tile t (of pack_tiles(N)) of one matrix: 32 flip masks x KT values of
+// q.  256 threads; src = the matrix (or coefficient vector), ws = its packed
+// operand; lds holds pack_lds_bytes<PLANES>() bytes.
+template <int PLANES, int DIR, bool IN128>
+__device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned char* __restrict__ ws,
+                                 int N, uint32_t t, unsigned char* lds) {
+    using P = Pack<PLANES>;
+    const uint32_t D = 1u << N, Dp = padded_dim(N);
+    const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
+    const uint32_t pitch = KT * P::ESZ + 16;
+    const uint32_t nKT = Dp / KT;
+    const uint32_t xb = t / nKT, kt = t % nKT;
+    const uint32_t X0 = xb * XT, Q0 = kt * KT;
+    const bool full = D >= 32u;
+    const int tid = threadIdx.x;
+
+    // one 4x4 micro-block per thread: 2*KT of them in the 32 x KT tile
+    if ((uint32_t)tid < 2 * KT) {
+        const int g = tid >> 6, w6 = tid & 63;   // 32x32 square g, block w6 in it
+        f32x2 v[16];
+        int xh, kh;                              // column group (x_l / 4), first K slot
+        if constexpr (DIR == FORWARD) {
+            const int mr = w6 >> 3, mc = w6 & 7;
+            const uint32_t q0 = Q0 + 32 * g + 4 * mc;
+            const uint32_t r0 = (((Q0 + 32 * g) ^ X0) & ~31u) + 4 * mr;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t r = r0 + a, q = q0 + b;
+                    v[a * 4 + b] = (full || (r < D && q < D)) ? load_elem<IN128>(src, (size_t)r * D + q)
+                                                              : f32x2{0.f, 0.f};
+                }
+            xh = mr ^ mc;
+            kh = 32 * g + 4 * mc;
+        } else {
+            const uint32_t zb = Q0 + 32 * g;
+            const uint32_t nb = pauli_index(X0, zb);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t o = 16 * w6 + r;
+                const uint32_t zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
+                const uint32_t z = zb + zl, x = X0 + xl;
+                f32x2 c = {0.f, 0.f};
+                if (full || (z < D && x < D)) c = load_elem<IN128>(src, nb + o);
+                float re = c.x, im = c.y;
+                rotate_minus_i(re, im, 3u * (uint32_t)__popc(x & z));  // i^{popc(x&z)}
+                v[r] = f32x2{re, im};
+            }
+            // 16 consecutive coefficients o = 16*w6 + r, r = (x^z)_0 | z_0<<1 | (x^z)_1<<2 | z_1<<3
+            const uint32_t o = 16 * w6;
+            const int zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
+            xh = xl >> 2;
+            kh = 32 * g + zl;
+        }
+        float gu = 1.f, ginv = 1.f;
+        if constexpr (PLANES == 3) {
+            float mx = 0.f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                mx = __builtin_fmaxf(mx, __builtin_fmaxf(__builtin_fabsf(v[r].x), __builtin_fabsf(v[r].y)));
+            block_grid(mx, gu, ginv);
+        }
+#pragma unroll
+        for (int x2 = 0; x2 < 4; ++x2) {
+            f32x2 e[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if constexpr (DIR == FORWARD) {
+                    e[b] = v[((x2 ^ b) << 2) | b];  // row a = x2 ^ b, column b
+                } else {
+                    const int d = x2 ^ b;             // (x ^ z) low bits
+                    e[b] = v[(d & 1) | ((b & 1) << 1) | ((d >> 1) << 2) | ((b >> 1) << 3)];
+                }
+            }
+            unsigned char* cbase = lds + (xh * 4 + x2) * pitch + kh * P::ESZ;
+            const uint32_t PS = XT * pitch;  // plane stride
+            if constexpr (PLANES == 3) {
+                uint32_t hr0, mr0, lr0, hr1, mr1, lr1, hi0, mi0, li0, hi1, mi1, li1;
+                split3(e[0].x, e[1].x, gu, ginv, hr0, mr0, lr0);
+                split3(e[2].x, e[3].x, gu, ginv, hr1, mr1, lr1);
+                split3(e[0].y, e[1].y, gu, ginv, hi0, mi0, li0);
+                split3(e[2].y, e[3].y, gu, ginv, hi1, mi1, li1);
+                *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
+                *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
+                *(u32x2*)(cbase + 2 * PS) = u32x2{mr0, mr1};
+                *(u32x2*)(cbase + 3 * PS) = u32x2{mi0, mi1};
+                *(u32x2*)(cbase + 4 * PS) = u32x2{lr0, lr1};
+                *(u32x2*)(cbase + 5 * PS) = u32x2{li0, li1};
+            } else {
+                *(f32x4*)(cbase) = f32x4{e[0].x, e[1].x, e[2].x, e[3].x};
+                *(f32x4*)(cbase + PS) = f32x4{e[0].y, e[1].y, e[2].y, e[3].y};
+            }
+        }
+    }
+    __syncthreads();
+
+    // Write whole fragments: KT/SK slices x NPL fragments, 64 lanes x 16 bytes.
+    const int lane = tid & 63, wave = tid >> 6;
+    const int xl = lane & 31, h = lane >> 5;
+    const uint32_t nfrag = (KT / P::SK) * P::NPL;
+    unsigned char* dst = ws + ((size_t)xb * (Dp / P::SK) + Q0 / P::SK) * P::SLICE_BYTES;
+    for (uint32_t f = wave; f < nfrag; f += 4) {
+        const uint32_t s = f / P::NPL, pl = f % P::NPL;
+        const unsigned char* srcl = lds + pl * XT * pitch + xl * pitch + (s * P::SK + h * (P::SK / 2)) * P::ESZ;
+        *(u32x4*)(dst + (size_t)f * FRAG + lane * 16) = *(const u32x4*)srcl;
+    }
+}
+
+// One output tile: flip masks xb*32.., rows mb*MT.. (MT = WAVES*RB*32) of a
+// matrix with padded order Dp.  Waves whose rows lie beyond Dp (only when
+// Dp < MT) skip the contraction but take part in the epilogue barriers.
+// wsm = the matrix's packed operand, dst = its output; lds holds
+// WAVES * 1024 * esz bytes of staging.
+template <int PLANES, int RB, int WAVES, int DIR, int PF>
+__device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsigned char* __restrict__ dst,
+                                     int N, uint32_t xb, uint32_t mb, double scale, int out128,
+                                     unsigned char* lds) {
+    using P = Pack<PLANES>;
+    constexpr int ACC = PLANES == 3 ? 2 : 1;
+    constexpr int MT = WAVES * RB * 32;                    // rows per workgroup
+    constexpr int U = 32 * RB / P::SK;                     // slices per sign group (32*RB K)
+    constexpr int GS = 2 * (U > PF ? U : PF);              // slices per unrolled step
+    static_assert(GS % U == 0 && GS % PF == 0, "ring depth and sign group must nest");
+
+    const uint32_t D = 1u << N, Dp = padded_dim(N);
+    const uint32_t nS = Dp / P::SK;
+    const uint32_t X0 = xb * XT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, h = lane >> 5;
+    const uint32_t Pw = mb * MT + wave * RB * 32;          // first row of this wave
+    const unsigned char* wsx = wsm + (size_t)xb * nS * P::SLICE_BYTES + lane * 16;
+
+    // ---- sign fragments of the 32x32 Sylvester block ----
+    // bf16: lane (row p_l = l32, half h) holds K slots q_l = 16e + 8h + j, j < 8,
+    //       for the two 16-wide slices e of a 32-wide block.
+    // fp32: lane holds q_l = 8e + 4h + t for slice e < 4, step t < 4.
+    uint32_t fA[2][4];   // bf16 pairs, [e][j/2]
+    float fF[4][4];      // fp32, [e][t]
+    if constexpr (PLANES == 3) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const uint32_t q0 = 16 * e + 8 * h + 2 * jj;
+                const uint32_t s0 = (__popc(l32 & q0) & 1) ? 0xBF80u : 0x3F80u;
+                const uint32_t s1 = (__popc(l32 & (q0 + 1)) & 1) ? 0xBF80u : 0x3F80u;
+                fA[e][jj] = s0 | (s1 << 16);
+            }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                fF[e][t] = (__popc(l32 & (8 * e + 4 * h + t)) & 1) ? -1.f : 1.f;
+    }
+
+    f32x16 acc[ACC][RB][2];
+#pragma unroll
+    for (int a = 0; a < ACC; ++a)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][rb][cb][r] = 0.f;
+
+    // ---- B fragment ring ----
+    u32x4 ring[PF][P::NPL];
+    auto fetch = [&](int slot, uint32_t s) {
+        const unsigned char* p = wsx + (size_t)s * P::SLICE_BYTES;
+#pragma unroll
+        for (int f = 0; f < P::NPL; ++f) ring[slot][f] = *(const u32x4*)(p + f * FRAG);
+    };
+    const bool active = Pw < Dp;                 // idle waves skip the contraction
+    if (active && nS % GS == 0) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) fetch(k, (uint32_t)k < nS ? k : nS - 1);
+
+    bf16x8 Ap[2], An[2];
+    float ts = 1.f;
+    for (uint32_t s0 = 0; s0 < nS; s0 += GS) {
+#pragma unroll
+        for (int uu = 0; uu < GS; ++uu) {
+            const int u = uu % U, slot = uu % PF;
+            if (u == 0) {
+                // sign of this wave's rows against this group of 32*RB K values
+                const bool neg_grp = __popc((Pw >> 5) & (((s0 + uu) * P::SK) >> 5)) & 1;
+                if constexpr (PLANES == 3) {
+                    const uint32_t tm = neg_grp ? 0x80008000u : 0u;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const u32x4 p = {fA[e][0] ^ tm, fA[e][1] ^ tm, fA[e][2] ^ tm, fA[e][3] ^ tm};
+                        Ap[e] = __builtin_bit_cast(bf16x8, p);
+                        An[e] = __builtin_bit_cast(bf16x8, p ^ 0x80008000u);
+                    }
+                } else {
+                    ts = neg_grp ? -1.f : 1.f;
+                }
+            }
+            if constexpr (PLANES == 3) {
+                // plane-outer order: consecutive MFMAs never share an accumulator
+#pragma unroll
+                for (int pl = 0; pl < 3; ++pl)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const bool neg = popc_const((uint32_t)rb & (uint32_t)(u >> 1)) & 1;
+                        const bf16x8 A = neg ? An[u & 1] : Ap[u & 1];
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            acc[pl == 0 ? 0 : ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                A, __builtin_bit_cast(bf16x8, ring[slot][pl * 2 + cb]),
+                                acc[pl == 0 ? 0 : ACC - 1][rb][cb], 0, 0, 0);
+                    }
+            } else {
+                const f32x4 Bv[2] = {__builtin_bit_cast(f32x4, ring[slot][0]),
+                                     __builtin_bit_cast(f32x4, ring[slot][1])};
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const bool neg = popc_const((uint32_t)rb & (uint32_t)(u >> 2)) & 1;
+                        const float A = (neg ? -ts : ts) * fF[u & 3][t];
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            acc[0][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, Bv[cb][t], acc[0][rb][cb], 0, 0, 0);
+                    }
+            }
+            // Refill this slot with slice s+PF.  The fences keep the loads
+            // here, PF slices ahead of their use, instead of letting the
+            // scheduler sink them next to the MFMAs that consume them.
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t nxt = s0 + uu + PF;
+            fetch(slot, nxt < nS ? nxt : nS - 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    } else if (active) {
+        // Fewer K slices than one unrolled group (small matrices in a batch
+        // whose tile shape was chosen for larger ones): one slice at a time,
+        // signs evaluated at run time.
+        for (uint32_t s = 0; s < nS; ++s) {
+            u32x4 B[P::NPL];
+            const unsigned char* p = wsx + (size_t)s * P::SLICE_BYTES;
+#pragma unroll
+            for (int f = 0; f < P::NPL; ++f) B[f] = *(const u32x4*)(p + f * FRAG);
+            const uint32_t qblk = (s * P::SK) >> 5;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const bool neg = __popc(((Pw >> 5) + rb) & qblk) & 1;
+                if constexpr (PLANES == 3) {
+                    const uint32_t m = neg ? 0x80008000u : 0u;
+                    const int e = s & 1;
+                    const bf16x8 A = __builtin_bit_cast(bf16x8, u32x4{fA[e][0] ^ m, fA[e][1] ^ m, fA[e][2] ^ m, fA[e][3] ^ m});
+#pragma unroll
+                    for (int pl = 0; pl < 3; ++pl)
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            acc[pl == 0 ? 0 : ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                A, __builtin_bit_cast(bf16x8, B[pl * 2 + cb]), acc[pl == 0 ? 0 : ACC - 1][rb][cb], 0, 0, 0);
+                } else {
+                    const f32x4 B0 = __builtin_bit_cast(f32x4, B[0]), B1 = __builtin_bit_cast(f32x4, B[1]);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float A = (neg ? -1.f : 1.f) * fF[s & 3][t];
+                        acc[0][rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, B0[t], acc[0][rb][0], 0, 0, 0);
+                        acc[0][rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, B1[t], acc[0][rb][1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- epilogue: binary64 recombination, phase, scale, staged store ----
+    const int esz = out128 ? 16 : 8;
+    unsigned char* stage = lds + wave * 1024 * esz;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const uint32_t pb = Pw + 32 * rb;   // first row of this 32x32 block
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t pl = 8 * (r >> 2) + 4 * h + (r & 3);
+            double re = (double)acc[0][rb][0][r];
+            double im = (double)acc[0][rb][1][r];
+            if constexpr (ACC == 2) {
+                re += (double)acc[ACC - 1][rb][0][r];
+                im += (double)acc[ACC - 1][rb][1][r];
+            }
+            re *= scale;
+            im *= scale;
+            uint32_t slot;
+            if constexpr (DIR == FORWARD) {
+                rotate_minus_i(re, im, (uint32_t)__popc((X0 + l32) & (pb + pl)));
+                slot = pauli_index((uint32_t)l32, pl);           // offset inside the 1024-run
+            } else {
+                slot = ((pl ^ (uint32_t)l32) << 5) | pl;        // (row, col) inside the 32x32 square
+            }
+            if (out128) *(double2*)(stage + slot * 16) = make_double2(re, im);
+            else *(float2*)(stage + slot * 8) = make_float2((float)re, (float)im);
+        }
+        __syncthreads();
+        if constexpr (DIR == FORWARD) {
+            // contiguous run of min(1024, 4^N) coefficients starting at n(X0, pb)
+            const uint32_t run = D < 32u ? D * D : 1024u;
+            unsigned char* o = dst + (size_t)pauli_index(X0, pb) * esz;
+            if (pb < D) {
+                if (run * esz >= 16) {
+                    for (uint32_t b = lane * 16; b < run * esz; b += 64 * 16)
+                        *(u32x4*)(o + b) = *(const u32x4*)(stage + b);
+                } else if (lane == 0) {
+                    *(u32x2*)o = *(const u32x2*)stage;   // N = 0, binary32 output
+                }
+            }
+        } else {
+            // 32x32 square of G: rows (pb ^ X0) + rl, columns pb + cl
+            const uint32_t w = D < 32u ? D : 32u;
+            const uint32_t rowbytes = w * esz;
+            const uint32_t r0 = (pb ^ X0) & ~31u;
+            if (pb < D) {
+                if (rowbytes >= 16) {
+                    for (uint32_t b = lane * 16; b < w * rowbytes; b += 64 * 16) {
+                        const uint32_t rl = b / rowbytes, cb = b % rowbytes;
+                        *(u32x4*)(dst + ((size_t)(r0 + rl) * D + pb) * esz + cb) =
+                            *(const u32x4*)(stage + rl * 32 * esz + cb);
+                    }
+                } else if (lane == 0) {
+                    *(u32x2*)dst = *(const u32x2*)stage;     // N = 0, binary32 output
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace mfma
+}  // namespace pauli
