@@ -1,17 +1,20 @@
 """Benchmark of the dense Pauli decomposition on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--N 14] [--no-cpu] [--no-fp64]
+    python bench.py --workload batch      # 512 uneven matrices, N in 3..9
+    python bench.py --workload backward   # 8 x N=11 forward + backward
 
 Workload: one complex64 Hermitian 16384 x 16384 matrix (N = 14 qubits),
 G = (A + A^H)/2 with A iid complex N(0,1) (numpy PCG64, seed 1014), resident in
 HBM before timing.  One step = one full decomposition into all 4^14
-coefficients (complex64 out) with the split-bf16 MFMA path
-(gather, exact 3-way bf16 split, +-1 contraction, binary64 recombination,
-phase, 2^-N, store) -- a single kernel launch.
+coefficients (complex64 out) with the split-bf16 MFMA path: the pack kernel
+(XOR gather, 3-way bf16 split, operand layout) then the contraction kernel
+(+-1 contraction, binary64 recombination, phase, 2^-N, store).
 
-Printed: one JSON line with coefficients/s, the roofline of that kernel
-(executed bf16 MFMA flops per launch / mean launch time, against the 2.5
-PFLOP/s dense bf16 peak), the binary64 Gray-code GPU kernel on the same input
+Printed: one JSON line with coefficients/s over the whole step, the roofline
+of the contraction kernel (executed bf16 MFMA flops per launch / its mean
+launch time from HIP events on its stream, against the 2.5 PFLOP/s dense
+bf16 peak), the binary64 Gray-code GPU kernel on the same input
 for the speed ratio and the error (max |c - c_fp64| / max |c_fp64|), and the
 CPU oracle timed on a bounded sample of the same coefficients on the host's
 cores (which also checks those coefficients).
@@ -19,6 +22,7 @@ cores (which also checks those coefficients).
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -31,7 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Pauli coeffs/sec + % MFMA peak at N=14, split-BF16 vs FP64 at err≤1e-6"
 PEAK_BF16_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2401_16378_amd/csrc/mfma.hip", "paper_2401_16378_amd/csrc/common.hpp"]
+KERNEL_SOURCES = ["paper_2401_16378_amd/csrc/mfma_tile.hpp", "paper_2401_16378_amd/csrc/mfma.hip",
+                  "paper_2401_16378_amd/csrc/common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_bf16_n14.json")
 
 
@@ -77,9 +82,98 @@ def cpu_baseline(G64: np.ndarray, c_gpu: np.ndarray, sample: int):
                       % (sample, N, workloads.SEED_SAMPLE, cores, dt)}, err
 
 
+def timed(fn, steps, warmup, stream):
+    """Mean ms per call of fn() over `steps` calls, after `warmup` calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record(stream)
+    for _ in range(steps):
+        fn()
+    e.record(stream)
+    torch.cuda.synchronize()
+    return b.elapsed_time(e) / steps
+
+
+def bench_batch(a):
+    """512 complex64 matrices, N uniform on 3..9 (102 Hermitian): one graph
+    replay (batched pack + persistent contraction) per step, against one
+    decomposition launch per matrix on the same buffers."""
+    import torch
+    import paper_2401_16378_amd as pauli
+    import workloads
+    dev = torch.device("cuda:0")
+    Ns, mats, herm = workloads.batch_spec()
+    G = [torch.from_numpy(m).to(dev) for m in mats]
+    outs = [torch.empty(1 << (2 * n), dtype=torch.complex64, device=dev) for n in Ns]
+    stream = torch.cuda.current_stream(dev)
+    tile = pauli.autotune_batched(G, outs=outs)
+    ms = timed(lambda: pauli.decompose_batched(G, outs=outs), a.steps, a.warmup, stream)
+    ws = pauli.workspace("split_bf16", 9, 1, dev)
+
+    def per_matrix():
+        for g, o in zip(G, outs):
+            n = g.shape[-1].bit_length() - 1
+            oo = pauli._opts("split_bf16", 0, 0, 0, ctypes.c_void_p(stream.cuda_stream), ws)
+            st = pauli.load_library().pauli_decompose(g.data_ptr(), n, 1, o.data_ptr(), ctypes.byref(oo))
+            if st:
+                raise RuntimeError(pauli.last_error())
+    ms_each = timed(per_matrix, max(2, a.steps // 4), 1, stream)
+    coeffs = float(sum(4 ** n for n in Ns))
+    flops = float(sum(12 * 8 ** n for n in Ns))
+    line = {"metric": "Pauli coeffs/sec, uneven batch", "value": coeffs / (ms / 1e3), "unit": "coeffs/s",
+            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "512 complex64 matrices, N uniform on 3..9 (seed %d), 20%% Hermitian, "
+                                   "split_bf16, one HIP graph replay per step" % workloads.SEED_BATCH,
+                       "batch": len(Ns), "tile": tile},
+            "executed_tflops": flops / (ms / 1e3) / 1e12,
+            "per_matrix_launch_ms": ms_each, "speedup_vs_per_matrix": ms_each / ms}
+    print(json.dumps(line), flush=True)
+
+
+def bench_backward(a):
+    """8 complex64 matrices at N=11: forward decomposition, loss
+    sum w |c - t|^2 and the adjoint backward, through torch.autograd."""
+    import torch
+    import paper_2401_16378_amd as pauli
+    import workloads
+    dev = torch.device("cuda:0")
+    G, G2, w = workloads.backward_problem(11, 8)
+    Gd = torch.from_numpy(G).to(dev)
+    t = pauli.decompose(torch.from_numpy(G2).to(dev)).to(torch.complex128)
+    wd = torch.from_numpy(w).to(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        g = Gd.detach().requires_grad_(True)
+        c = pauli.PauliDecompose.apply(g, "split_bf16")
+        loss = (wd * (c.to(torch.complex128) - t).abs() ** 2).sum()
+        loss.backward()
+        return g.grad
+
+    ms = timed(step, a.steps, a.warmup, stream)
+    ms_fwd = timed(lambda: pauli.decompose(Gd), a.steps, a.warmup, stream)
+    g = Gd.detach()
+    gc = torch.randn(8, 4 ** 11, dtype=torch.complex64, device=dev)
+    ms_bwd = timed(lambda: pauli.decompose_backward(gc), a.steps, a.warmup, stream)
+    flops = 2 * 8 * 12 * float(8 ** 11)
+    line = {"metric": "forward+backward steps/sec, 8 x N=11", "value": 1e3 / ms, "unit": "steps/s",
+            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "8 complex64 2048x2048 matrices, L = sum w|c-t|^2, split_bf16 forward "
+                                   "and adjoint backward through torch.autograd", "batch": 8, "N": 11},
+            "forward_ms": ms_fwd, "backward_kernel_ms": ms_bwd,
+            "executed_tflops_fwd_bwd_kernels": flops / ((ms_fwd + ms_bwd) / 1e3) / 1e12}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["n14", "batch", "backward"], default="n14")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--N", type=int, default=14)
@@ -103,6 +197,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.workload == "batch":
+        return bench_batch(a)
+    if a.workload == "backward":
+        return bench_backward(a)
     N = a.N
     log("[bench] generating N=%d Hermitian complex64 input (seed %d)" % (N, workloads.SEED_N14))
     t0 = time.perf_counter()
@@ -113,10 +211,16 @@ def main():
     lib = pauli.load_library()
     import ctypes
     stream = torch.cuda.current_stream(dev)
-    o = pauli._opts(a.algo, 0, 0, a.tile, ctypes.c_void_p(stream.cuda_stream))
+    ws = pauli.workspace(a.algo, N, 1, dev)
+    o = pauli._opts(a.algo, 0, 0, a.tile, ctypes.c_void_p(stream.cuda_stream), ws)
 
-    def step():
-        st = lib.pauli_decompose(Gd.data_ptr(), N, 1, out.data_ptr(), ctypes.byref(o))
+    def step(mid=None):
+        # pauli_pack + pauli_contract is pauli_decompose split at the kernel
+        # boundary, so the contraction kernel can be timed on its own.
+        st = lib.pauli_pack(Gd.data_ptr(), N, 1, 0, ctypes.byref(o))
+        if mid is not None:
+            mid.record(stream)
+        st = st or lib.pauli_contract(N, 1, 0, out.data_ptr(), ctypes.byref(o))
         if st != 0:
             raise RuntimeError(pauli.last_error())
 
@@ -132,17 +236,18 @@ def main():
         step()
     torch.cuda.synchronize()
     log("[bench] warm-up done; timing %d steps" % a.steps)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(a.steps)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(a.steps):
         evs[s][0].record(stream)
-        step()
-        evs[s][1].record(stream)
+        step(evs[s][1])
+        evs[s][2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_ms = [b.elapsed_time(e) for b, e in evs]
+    launch_ms = [m.elapsed_time(e) for b, m, e in evs]      # contraction kernel
+    pack_ms = float(np.mean([b.elapsed_time(m) for b, m, e in evs]))
     ms_step = wall * 1000.0 / a.steps
     mean_launch = float(np.mean(launch_ms))
     coeffs = float(4 ** N)
@@ -152,7 +257,8 @@ def main():
     flops_useful = 4.0 * float(8 ** N)
     achieved = flops_exec / (mean_launch / 1000.0) / 1e12
     peak = PEAK_BF16_TFLOPS if a.algo == "split_bf16" else 157.3
-    log("[bench] %.3f ms/step, %.3f ms/launch, %.1f TFLOP/s executed" % (ms_step, mean_launch, achieved))
+    log("[bench] %.3f ms/step, pack %.3f ms, contraction %.3f ms, %.1f TFLOP/s executed"
+        % (ms_step, pack_ms, mean_launch, achieved))
 
     c_bf16 = out.cpu().numpy()
     res = {}
@@ -173,9 +279,9 @@ def main():
         c64 = out64.cpu().numpy()
         err = float(np.abs(c_bf16 - c64).max() / np.abs(c64).max())
         im_ratio = float(np.abs(c64.imag).max() / np.abs(c64).max())
-        res.update({"fp64_gray_ms": round(fp64_ms, 3), "speedup_vs_fp64_gray": round(fp64_ms / mean_launch, 2),
+        res.update({"fp64_gray_ms": round(fp64_ms, 3), "speedup_vs_fp64_gray": round(fp64_ms / ms_step, 2),
                     "max_err_vs_fp64": err, "fp64_imag_ratio": im_ratio})
-        log("[bench] fp64 gray %.1f ms, ratio %.2f, err %.3g" % (fp64_ms, fp64_ms / mean_launch, err))
+        log("[bench] fp64 gray %.1f ms, ratio %.2f, err %.3g" % (fp64_ms, fp64_ms / ms_step, err))
         del out64
 
     cpu = None
@@ -197,7 +303,9 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "useful_frac": flops_useful / (mean_launch / 1000.0) / 1e12 / peak,
-                     "launch_ms": mean_launch, "flops_per_launch": flops_exec},
+                     "launch_ms": mean_launch, "flops_per_launch": flops_exec,
+                     "kernel": "contract_kernel (split-bf16, tile %d)" % (pauli.tile_selected(N, a.algo) if a.tile == 0 else a.tile),
+                     "pack_ms": pack_ms},
         "cpu_baseline": cpu,
     }
     line.update(res)

@@ -177,6 +177,24 @@ int pauli_tile_selected(int algo, int N);
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char* pauli_last_error(void);
 
+/*
+ * The two passes of the matrix-core algorithms (SPLIT_BF16, FP32), for
+ * callers that schedule or time them separately; opts->workspace is required
+ * (pauli_workspace_bytes).  mode: 0 = decompose, 1 = reconstruct,
+ * 2 = backward.
+ *   pauli_pack: gather the input of the contraction (for mode 0 the XOR
+ *     diagonals G[i ^ x][i] of section 2, Eq. (c_def_in_terms_of_fn); for
+ *     modes 1 and 2 the coefficient blocks) and store it, converted to the
+ *     matrix-core operand format, in the workspace.
+ *   pauli_contract: contract the packed operand against the +-1 sign matrix
+ *     and write the output of pauli_decompose / pauli_reconstruct /
+ *     pauli_decompose_backward.
+ * pauli_pack followed by pauli_contract on the same stream, workspace and
+ * arguments equals the one-call entry point bit for bit.
+ */
+int pauli_pack(const void* in, int N, int batch, int mode, const pauli_opts* opts);
+int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts);
+
 /* Library ABI version, currently 1. */
 int pauli_version(void);
 

@@ -49,7 +49,8 @@ _lock = threading.Lock()
 EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward",
            "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_workspace_bytes",
            "pauli_batched_tile_count", "pauli_autotune_batched", "pauli_batched_tile_selected", "pauli_autotune",
-           "pauli_tile_count", "pauli_tile_selected", "pauli_last_error", "pauli_version"]
+           "pauli_tile_count", "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_last_error",
+           "pauli_version"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -87,6 +88,10 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_tile_count.restype = ci
         lib.pauli_tile_selected.argtypes = [ci, ci]
         lib.pauli_tile_selected.restype = ci
+        lib.pauli_pack.argtypes = [vp, ci, ci, ci, op]
+        lib.pauli_pack.restype = ci
+        lib.pauli_contract.argtypes = [ci, ci, ci, vp, op]
+        lib.pauli_contract.restype = ci
         lib.pauli_last_error.argtypes = []
         lib.pauli_last_error.restype = ctypes.c_char_p
         lib.pauli_version.argtypes = []

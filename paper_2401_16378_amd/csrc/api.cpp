@@ -219,6 +219,61 @@ int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
                "pauli_decompose_backward");
 }
 
+static int stage_check(int N, int batch, int mode, const pauli_opts& o, const char* fn) {
+    if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
+    if (batch < 1) return fail(PAULI_EINVAL, "%s: batch=%d must be >= 1", fn, batch);
+    if (mode < 0 || mode > 2) return fail(PAULI_EINVAL, "%s: mode %d not in {0, 1, 2}", fn, mode);
+    if (o.algo != PAULI_ALGO_SPLIT_BF16 && o.algo != PAULI_ALGO_FP32)
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes", fn, o.algo);
+    if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
+        return fail(PAULI_EINVAL, "%s: unknown dtype (in %d, out %d)", fn, o.in_dtype, o.out_dtype);
+    const size_t need = mfma_workspace_bytes(planes_of(o.algo), N, batch);
+    if (!o.workspace || o.workspace_bytes < need)
+        return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
+                    o.workspace ? o.workspace_bytes : (size_t)0);
+    if ((uintptr_t)o.workspace % 256) return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+    if (o.tile < 0 || (o.tile > 0 && !mfma_tile_valid(planes_of(o.algo), o.tile, N)))
+        return fail(PAULI_EINVAL, "%s: tile %d not valid at N=%d", fn, o.tile, N);
+    return PAULI_OK;
+}
+
+int pauli_pack(const void* in, int N, int batch, int mode, const pauli_opts* opts) {
+    const char* fn = "pauli_pack";
+    const pauli_opts o = resolve(opts);
+    int st = stage_check(N, batch, mode, o, fn);
+    if (st != PAULI_OK) return st;
+    if (!in) return fail(PAULI_EINVAL, "%s: NULL input", fn);
+    if ((uintptr_t)in % 16) return fail(PAULI_EINVAL, "%s: input not aligned to 16 bytes", fn);
+    const size_t bytes = ((size_t)1 << (2 * N)) * (size_t)batch * elem_bytes(o.in_dtype);
+    if (overlaps(in, bytes, o.workspace, o.workspace_bytes))
+        return fail(PAULI_EINVAL, "%s: workspace overlaps the input", fn);
+    const hipError_t e = launch_mfma_pack(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), in,
+                                          o.in_dtype == PAULI_C128, N, batch, o.workspace, (hipStream_t)o.stream);
+    if (e != hipSuccess) return hip_fail(e, fn);
+    g_last_error.clear();
+    return PAULI_OK;
+}
+
+int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts) {
+    const char* fn = "pauli_contract";
+    const pauli_opts o = resolve(opts);
+    int st = stage_check(N, batch, mode, o, fn);
+    if (st != PAULI_OK) return st;
+    if (!out) return fail(PAULI_EINVAL, "%s: NULL output", fn);
+    if ((uintptr_t)out % 16) return fail(PAULI_EINVAL, "%s: output not aligned to 16 bytes", fn);
+    const size_t bytes = ((size_t)1 << (2 * N)) * (size_t)batch * elem_bytes(o.out_dtype);
+    if (overlaps(out, bytes, o.workspace, o.workspace_bytes))
+        return fail(PAULI_EINVAL, "%s: workspace overlaps the output", fn);
+    const double scale = mode == 1 ? 1.0 : 1.0 / (double)(1u << N);
+    const hipError_t e =
+        launch_mfma_contract(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), o.workspace, out,
+                             o.out_dtype == PAULI_C128, N, batch, scale, pick_tile(o.algo, N, o.tile),
+                             (hipStream_t)o.stream);
+    if (e != hipSuccess) return hip_fail(e, fn);
+    g_last_error.clear();
+    return PAULI_OK;
+}
+
 size_t pauli_workspace_bytes(int algo, int N, int batch) {
     if (!valid_algo(algo) || N < 0 || N > N_MAX || batch < 1) return 0;
     if (algo == PAULI_ALGO_FP64_GRAY) return 0;

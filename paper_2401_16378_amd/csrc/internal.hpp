@@ -23,6 +23,10 @@ hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* 
                        bool out_c128, int N, int batch, double scale, int tile, void* ws,
                        hipStream_t stream);
 size_t mfma_workspace_bytes(int planes, int N, int batch);
+hipError_t launch_mfma_pack(Dir dir, int planes, const void* in, bool in_c128, int N, int batch, void* ws,
+                            hipStream_t stream);
+hipError_t launch_mfma_contract(Dir dir, int planes, const void* ws, void* out, bool out_c128, int N, int batch,
+                                double scale, int tile, hipStream_t stream);
 int mfma_tile_count(int planes);
 bool mfma_tile_valid(int planes, int tile, int N);
 int mfma_default_tile(int planes, int N);

@@ -121,19 +121,19 @@ size_t mfma_workspace_bytes(int planes, int N, int batch) {
     return Dp * Dp * (size_t)(planes == 3 ? Pack<3>::EB : Pack<1>::EB) * (size_t)batch;
 }
 
-hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* out,
-                       bool out_c128, int N, int batch, double scale, int tile, void* ws,
-                       hipStream_t stream) {
+hipError_t launch_mfma_pack(Dir dir, int planes, const void* in, bool in_c128, int N, int batch, void* ws,
+                            hipStream_t stream) {
+    if (planes == 3)
+        return dir == FORWARD ? launch_pack<3, FORWARD>(in, in_c128, ws, N, batch, stream)
+                              : launch_pack<3, ADJOINT>(in, in_c128, ws, N, batch, stream);
+    return dir == FORWARD ? launch_pack<1, FORWARD>(in, in_c128, ws, N, batch, stream)
+                          : launch_pack<1, ADJOINT>(in, in_c128, ws, N, batch, stream);
+}
+
+hipError_t launch_mfma_contract(Dir dir, int planes, const void* ws, void* out, bool out_c128, int N, int batch,
+                                double scale, int tile, hipStream_t stream) {
     if (tile == 0) tile = mfma_default_tile(planes, N);
     if (!mfma_tile_valid(planes, tile, N)) return hipErrorInvalidValue;
-    hipError_t e;
-    if (planes == 3)
-        e = dir == FORWARD ? launch_pack<3, FORWARD>(in, in_c128, ws, N, batch, stream)
-                           : launch_pack<3, ADJOINT>(in, in_c128, ws, N, batch, stream);
-    else
-        e = dir == FORWARD ? launch_pack<1, FORWARD>(in, in_c128, ws, N, batch, stream)
-                           : launch_pack<1, ADJOINT>(in, in_c128, ws, N, batch, stream);
-    if (e != hipSuccess) return e;
     Params p{ws, out, N, out_c128 ? 1 : 0, scale};
     if (planes == 3)
         return dir == FORWARD ? launch_tile<3, FORWARD>(tile, p, batch, stream)
@@ -141,5 +141,16 @@ hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* 
     return dir == FORWARD ? launch_tile<1, FORWARD>(tile, p, batch, stream)
                           : launch_tile<1, ADJOINT>(tile, p, batch, stream);
 }
+
+hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* out,
+                       bool out_c128, int N, int batch, double scale, int tile, void* ws,
+                       hipStream_t stream) {
+    if (tile == 0) tile = mfma_default_tile(planes, N);
+    if (!mfma_tile_valid(planes, tile, N)) return hipErrorInvalidValue;
+    const hipError_t e = launch_mfma_pack(dir, planes, in, in_c128, N, batch, ws, stream);
+    if (e != hipSuccess) return e;
+    return launch_mfma_contract(dir, planes, ws, out, out_c128, N, batch, scale, tile, stream);
+}
+
 
 }  // namespace pauli

@@ -44,3 +44,14 @@ def n_of_labels(s: str) -> int:
 
 def count_y(n: int, N: int) -> int:
     return sum(1 for d in digits(n, N) if d == 2)
+
+
+def n_of_xz(x: int, z: int, N: int) -> int:
+    """Index of the string with flip mask x (X or Y on qubit t) and phase mask
+    z (Y or Z on qubit t): operator flag I=0, X=1, Y=2, Z=3 per qubit."""
+    n = 0
+    for t in range(N):
+        xt, zt = (x >> t) & 1, (z >> t) & 1
+        flag = {(0, 0): 0, (1, 0): 1, (1, 1): 2, (0, 1): 3}[(xt, zt)]
+        n |= flag << (2 * t)
+    return n
