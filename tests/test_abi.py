@@ -1,0 +1,150 @@
+"""C-ABI checks that need no GPU: the built library exports every function
+include/pauli.h declares, and invalid requests fail with the documented status
+before any device call (so these run in a container without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pauli.h")
+
+OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, 1, 2, 3, 4
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\*?(pauli_[a-z_]+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2401_16378_amd as p
+    if not os.path.exists(p.LIB_PATH):
+        pytest.fail("libpauli.so is not built (python -m paper_2401_16378_amd.build)")
+    return p.load_library()
+
+
+@pytest.fixture(scope="module")
+def pauli():
+    import paper_2401_16378_amd as p
+    return p
+
+
+def test_header_declarations_exported(lib, pauli):
+    names = declared_functions()
+    assert len(names) >= 15, names
+    raw = ctypes.CDLL(pauli.LIB_PATH)
+    for name in names:
+        assert hasattr(raw, name), "libpauli.so does not export %s" % name
+    assert sorted(pauli.EXPORTS) == names
+
+
+def test_version_and_defaults(lib, pauli):
+    assert lib.pauli_version() == 1
+    o = pauli._Opts()
+    lib.pauli_opts_default(ctypes.byref(o))
+    assert (o.algo, o.in_dtype, o.out_dtype, o.tile) == (2, 0, 0, 0)
+    assert o.stream is None and o.workspace is None and o.workspace_bytes == 0
+
+
+def opts(pauli, algo="split_bf16", in_dt=0, out_dt=0, tile=0, ws=None, ws_bytes=0):
+    o = pauli._opts(algo, in_dt, out_dt, tile, None)
+    if ws is not None:
+        o.workspace = ws
+        o.workspace_bytes = ws_bytes
+    return o
+
+
+FAKE_IN = 0x10000000      # never dereferenced: every call below fails validation first
+FAKE_OUT = 0x20000000
+
+
+@pytest.mark.parametrize("fn", ["pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward"])
+def test_validation_errors(lib, pauli, fn):
+    f = getattr(lib, fn)
+    o = opts(pauli)
+    cases = [
+        (FAKE_IN, -1, 1, FAKE_OUT, o, EINVAL),            # N < 0
+        (FAKE_IN, 17, 1, FAKE_OUT, o, EINVAL),            # N > 16
+        (FAKE_IN, 4, 0, FAKE_OUT, o, EINVAL),             # batch < 1
+        (None, 4, 1, FAKE_OUT, o, EINVAL),                # NULL input
+        (FAKE_IN, 4, 1, None, o, EINVAL),                 # NULL output
+        (FAKE_IN + 8, 4, 1, FAKE_OUT, o, EINVAL),         # input not 16-byte aligned
+        (FAKE_IN, 4, 1, FAKE_OUT + 8, o, EINVAL),         # output not 16-byte aligned
+        (FAKE_IN, 4, 1, FAKE_IN + 256, o, EINVAL),        # overlap
+        (FAKE_IN, 4, 1, FAKE_OUT, opts(pauli, in_dt=7), EINVAL),
+        (FAKE_IN, 4, 1, FAKE_OUT, opts(pauli, tile=99), EINVAL),
+        (FAKE_IN, 4, 1, FAKE_OUT, opts(pauli, tile=1), EINVAL),    # 512-row tile at N = 4
+        (FAKE_IN, 10, 1, FAKE_OUT, opts(pauli, ws=0x30000008, ws_bytes=1 << 30), EINVAL),  # misaligned ws
+        (FAKE_IN, 10, 1, FAKE_OUT, opts(pauli, ws=0x30000000, ws_bytes=1024), ENOMEM),
+    ]
+    for a, N, b, out, oo, want in cases:
+        st = f(a, N, b, out, ctypes.byref(oo))
+        assert st == want, (fn, N, b, st, want, pauli.last_error())
+        assert pauli.last_error() != ""
+    o.algo = 9
+    assert f(FAKE_IN, 4, 1, FAKE_OUT, ctypes.byref(o)) == EINVAL
+
+
+def test_workspace_sizes(lib):
+    # split-bf16: 12 bytes per element, fp32: 8, binary64 Gray: none; N < 5 padded to 32 x 32
+    assert lib.pauli_workspace_bytes(2, 10, 1) == 12 * 4 ** 10
+    assert lib.pauli_workspace_bytes(1, 10, 3) == 3 * 8 * 4 ** 10
+    assert lib.pauli_workspace_bytes(0, 10, 1) == 0
+    assert lib.pauli_workspace_bytes(2, 3, 1) == 12 * 32 * 32
+    assert lib.pauli_workspace_bytes(2, 17, 1) == 0
+    assert lib.pauli_workspace_bytes(5, 4, 1) == 0
+
+
+def test_tiles(lib):
+    n = lib.pauli_tile_count(2)
+    assert n >= 6 and lib.pauli_tile_count(1) == n and lib.pauli_tile_count(0) == 1
+    assert lib.pauli_tile_count(7) == 0
+    for N in range(0, 17):
+        t = lib.pauli_tile_selected(2, N)
+        assert 1 <= t <= n
+    assert lib.pauli_batched_tile_count() >= 1
+
+
+def test_batched_validation(lib, pauli):
+    vp = ctypes.c_void_p
+    G = (vp * 2)(FAKE_IN, FAKE_IN + (1 << 20))
+    O = (vp * 2)(FAKE_OUT, FAKE_OUT + (1 << 20))
+    Ns = (ctypes.c_int * 2)(3, 5)
+    o = opts(pauli)
+    assert lib.pauli_decompose_batched(0, G, Ns, O, ctypes.byref(o)) == EINVAL
+    assert lib.pauli_decompose_batched(2, None, Ns, O, ctypes.byref(o)) == EINVAL
+    bad = (ctypes.c_int * 2)(3, 13)
+    assert lib.pauli_decompose_batched(2, G, bad, O, ctypes.byref(o)) == EINVAL
+    assert lib.pauli_decompose_batched(2, G, Ns, O, ctypes.byref(opts(pauli, algo="fp64_gray"))) == EUNSUPPORTED
+    assert lib.pauli_decompose_batched(2, G, Ns, O, ctypes.byref(opts(pauli, in_dt=1))) == EUNSUPPORTED
+    # no workspace
+    assert lib.pauli_decompose_batched(2, G, Ns, O, ctypes.byref(o)) == ENOMEM
+    need = lib.pauli_batched_workspace_bytes(2, Ns, 2)
+    assert need > 12 * (32 * 32 + 32 * 32)
+    small = opts(pauli, ws=0x40000000, ws_bytes=need - 1)
+    assert lib.pauli_decompose_batched(2, G, Ns, O, ctypes.byref(small)) == ENOMEM
+    assert lib.pauli_batched_workspace_bytes(2, bad, 2) == 0
+    assert lib.pauli_batched_tile_selected(2, Ns, 2) >= 1
+
+
+def test_pass_entry_points_validation(lib, pauli):
+    o = opts(pauli)
+    assert lib.pauli_pack(FAKE_IN, 10, 1, 0, ctypes.byref(o)) == ENOMEM
+    assert lib.pauli_contract(10, 1, 0, FAKE_OUT, ctypes.byref(o)) == ENOMEM
+    assert lib.pauli_pack(FAKE_IN, 10, 1, 5, ctypes.byref(o)) == EINVAL
+    g = opts(pauli, algo="fp64_gray")
+    assert lib.pauli_pack(FAKE_IN, 10, 1, 0, ctypes.byref(g)) == EUNSUPPORTED
+    ws = opts(pauli, ws=0x30000000, ws_bytes=12 * 4 ** 10)
+    assert lib.pauli_pack(None, 10, 1, 0, ctypes.byref(ws)) == EINVAL
+    assert lib.pauli_contract(10, 1, 0, 0x30000000 + 4096, ctypes.byref(ws)) == EINVAL   # overlaps workspace
+
+
+def test_autotune_validation(lib, pauli):
+    o = opts(pauli)
+    assert lib.pauli_autotune(5, 3, ctypes.byref(o)) == EINVAL
+    assert lib.pauli_autotune(0, 3, ctypes.byref(o)) == EINVAL
+    assert lib.pauli_autotune(3, 5, ctypes.byref(opts(pauli, algo="fp64_gray"))) == EUNSUPPORTED
