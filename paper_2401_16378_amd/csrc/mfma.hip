@@ -37,6 +37,33 @@ __global__ __launch_bounds__(WAVES * 64) void contract_kernel(Params prm) {
     contract_tile<PLANES, RB, WAVES, DIR, PF>(wsm, dst, prm.N, L / nMB, L % nMB, prm.scale, prm.out128, lds);
 }
 
+template <int PLANES, int RB, int DIR, int AHEAD>
+__global__ __launch_bounds__(256) void contract_lds_kernel(Params prm) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    constexpr int MT = 4 * RB * 32;
+    const uint32_t D = 1u << prm.N, Dp = padded_dim(prm.N);
+    const uint32_t nMB = Dp / MT;
+    const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const unsigned char* wsm = (const unsigned char*)prm.ws + (size_t)blockIdx.y * Dp * Dp * Pack<PLANES>::EB;
+    unsigned char* dst = (unsigned char*)prm.out + (size_t)blockIdx.y * D * D * (prm.out128 ? 16 : 8);
+    contract_tile_lds<PLANES, RB, DIR, AHEAD>(wsm, dst, prm.N, L / nMB, L % nMB, prm.scale, prm.out128, lds);
+}
+
+template <int PLANES, int RB, int AHEAD, int DIR>
+hipError_t launch_contract_lds(const Params& p, int batch, hipStream_t s) {
+    constexpr int MT = 4 * RB * 32;
+    const uint32_t Dp = padded_dim(p.N);
+    const uint32_t nMB = Dp / MT, nXB = Dp / XT;
+    auto kern = contract_lds_kernel<PLANES, RB, DIR, AHEAD>;
+    const int ring = (AHEAD + 1) * 2 * Pack<PLANES>::NPL * FRAG;
+    const int stage = 4 * 1024 * (p.out128 ? 16 : 8);
+    const int lds = ring > stage ? ring : stage;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(256), lds, s, p);
+    return hipGetLastError();
+}
+
 // ---- tile table: (rows per wave / 32, waves per workgroup, ring depth) ----
 struct TileDesc {
     int rb, waves, pf;
@@ -54,6 +81,9 @@ constexpr TileDesc TILES[] = {
     {4, 4, 8},  // 10: 512 rows, deeper ring
     {4, 2, 8},  // 11: 256 rows, deeper ring
     {2, 4, 8},  // 12: 256 rows, deeper ring
+    {4, 4, 3},  // 13: 512 rows, LDS-staged, copies 3 slice pairs ahead
+    {4, 4, 7},  // 14: 512 rows, LDS-staged, copies 7 slice pairs ahead
+    {2, 4, 3},  // 15: 256 rows, LDS-staged, copies 3 slice pairs ahead
 };
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
@@ -85,6 +115,9 @@ hipError_t launch_tile(int tile, const Params& p, int batch, hipStream_t s) {
         case 10: return launch_contract<PLANES, 4, 4, 8, DIR>(p, batch, s);
         case 11: return launch_contract<PLANES, 4, 2, 8, DIR>(p, batch, s);
         case 12: return launch_contract<PLANES, 2, 4, 8, DIR>(p, batch, s);
+        case 13: return launch_contract_lds<PLANES, 4, 3, DIR>(p, batch, s);
+        case 14: return launch_contract_lds<PLANES, 4, 7, DIR>(p, batch, s);
+        case 15: return launch_contract_lds<PLANES, 2, 3, DIR>(p, batch, s);
         default: return hipErrorInvalidValue;
     }
 }

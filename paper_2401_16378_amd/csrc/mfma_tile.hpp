@@ -250,6 +250,78 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
     }
 }
 
+// Epilogue shared by the contraction variants: binary64 recombination of the
+// accumulators, phase, scale, and an LDS-staged store of each 32x32 block as
+// one contiguous coefficient run (forward) or one aligned square of G
+// (adjoint).  lds holds WAVES * 1024 * esz bytes; all waves of the
+// workgroup must call it (it contains barriers).
+template <int PLANES, int RB, int DIR>
+__device__ inline void store_tile(const f32x16 (&acc)[PLANES == 3 ? 2 : 1][RB][2], unsigned char* __restrict__ dst,
+                                  int N, uint32_t X0, uint32_t Pw, double scale, int out128, unsigned char* lds) {
+    constexpr int ACC = PLANES == 3 ? 2 : 1;
+    const uint32_t D = 1u << N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, h = lane >> 5;
+    const int esz = out128 ? 16 : 8;
+    unsigned char* stage = lds + wave * 1024 * esz;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const uint32_t pb = Pw + 32 * rb;   // first row of this 32x32 block
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t pl = 8 * (r >> 2) + 4 * h + (r & 3);
+            double re = (double)acc[0][rb][0][r];
+            double im = (double)acc[0][rb][1][r];
+            if constexpr (ACC == 2) {
+                re += (double)acc[ACC - 1][rb][0][r];
+                im += (double)acc[ACC - 1][rb][1][r];
+            }
+            re *= scale;
+            im *= scale;
+            uint32_t slot;
+            if constexpr (DIR == FORWARD) {
+                rotate_minus_i(re, im, (uint32_t)__popc((X0 + l32) & (pb + pl)));
+                slot = pauli_index((uint32_t)l32, pl);           // offset inside the 1024-run
+            } else {
+                slot = ((pl ^ (uint32_t)l32) << 5) | pl;        // (row, col) inside the 32x32 square
+            }
+            if (out128) *(double2*)(stage + slot * 16) = make_double2(re, im);
+            else *(float2*)(stage + slot * 8) = make_float2((float)re, (float)im);
+        }
+        __syncthreads();
+        if constexpr (DIR == FORWARD) {
+            // contiguous run of min(1024, 4^N) coefficients starting at n(X0, pb)
+            const uint32_t run = D < 32u ? D * D : 1024u;
+            unsigned char* o = dst + (size_t)pauli_index(X0, pb) * esz;
+            if (pb < D) {
+                if (run * esz >= 16) {
+                    for (uint32_t b = lane * 16; b < run * esz; b += 64 * 16)
+                        *(u32x4*)(o + b) = *(const u32x4*)(stage + b);
+                } else if (lane == 0) {
+                    *(u32x2*)o = *(const u32x2*)stage;   // N = 0, binary32 output
+                }
+            }
+        } else {
+            // 32x32 square of G: rows (pb ^ X0) + rl, columns pb + cl
+            const uint32_t w = D < 32u ? D : 32u;
+            const uint32_t rowbytes = w * esz;
+            const uint32_t r0 = (pb ^ X0) & ~31u;
+            if (pb < D) {
+                if (rowbytes >= 16) {
+                    for (uint32_t b = lane * 16; b < w * rowbytes; b += 64 * 16) {
+                        const uint32_t rl = b / rowbytes, cb = b % rowbytes;
+                        *(u32x4*)(dst + ((size_t)(r0 + rl) * D + pb) * esz + cb) =
+                            *(const u32x4*)(stage + rl * 32 * esz + cb);
+                    }
+                } else if (lane == 0) {
+                    *(u32x2*)dst = *(const u32x2*)stage;     // N = 0, binary32 output
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // One output tile: flip masks xb*32.., rows mb*MT.. (MT = WAVES*RB*32) of a
 // matrix with padded order Dp.  Waves whose rows lie beyond Dp (only when
 // Dp < MT) skip the contraction but take part in the epilogue barriers.
@@ -414,65 +486,173 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
         }
     }
 
-    // ---- epilogue: binary64 recombination, phase, scale, staged store ----
-    const int esz = out128 ? 16 : 8;
-    unsigned char* stage = lds + wave * 1024 * esz;
+    store_tile<PLANES, RB, DIR>(acc, dst, N, X0, Pw, scale, out128, lds);
+}
+
+// s_waitcnt with vmcnt <= NV and the other counters unconstrained (gfx9
+// encoding: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8], vmcnt[15:14]).
+// Wait until at most NV vector-memory operations of this wave are outstanding
+// and every LDS read it issued has returned (lgkmcnt 0), so that a following
+// barrier also orders this wave's LDS reads before other waves' ring refills.
+template <int NV>
+__device__ inline void wait_vmcnt() {
+    static_assert(NV >= 0 && NV < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((NV & 15) | (7 << 4) | (0 << 8) | ((NV >> 4) << 14));
+}
+
+// Variant of contract_tile for 4-wave workgroups that stages the packed
+// operand once per workgroup: slices are handled in pairs, each pair's
+// fragments are copied HBM/L2 -> LDS by direct loads (each wave copies a
+// quarter, AHEAD pairs ahead of use, into a ring of AHEAD+1 pair slots), and
+// all four waves read the B fragments from LDS.  Per pair: wait for this
+// wave's own copies of the pair, one workgroup barrier (the pair is complete
+// and the slot refilled next held a pair every wave has finished), refill,
+// then the MFMAs.  lds must hold max(ring, epilogue staging) bytes.
+template <int PLANES, int RB, int DIR, int AHEAD>
+__device__ inline void contract_tile_lds(const unsigned char* __restrict__ wsm, unsigned char* __restrict__ dst,
+                                         int N, uint32_t xb, uint32_t mb, double scale, int out128,
+                                         unsigned char* lds) {
+    using P = Pack<PLANES>;
+    constexpr int WAVES = 4;
+    constexpr int ACC = PLANES == 3 ? 2 : 1;
+    constexpr int MT = WAVES * RB * 32;
+    constexpr int PAIR_FR = 2 * P::NPL;                    // fragments per slice pair
+    constexpr int LPW = PAIR_FR / WAVES;                   // copies per wave per pair
+    static_assert(PAIR_FR % WAVES == 0, "pair must split evenly over the waves");
+    constexpr int PAIR_BYTES = PAIR_FR * FRAG;
+    constexpr int NSL = AHEAD + 1;                         // ring slots
+    constexpr int U = 32 * RB / P::SK;                     // slices per sign group
+    constexpr int GP = U / 2;                              // pairs per sign group
+    static_assert(U % 2 == 0, "sign group holds whole pairs");
+
+    const uint32_t Dp = padded_dim(N);
+    const uint32_t nS = Dp / P::SK, nP = nS / 2;
+    const uint32_t X0 = xb * XT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, h = lane >> 5;
+    const uint32_t Pw = mb * MT + wave * RB * 32;
+    const unsigned char* slab = wsm + (size_t)xb * nS * P::SLICE_BYTES;   // pairs are contiguous
+
+    uint32_t fA[2][4];
+    float fF[4][4];
+    if constexpr (PLANES == 3) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        const uint32_t pb = Pw + 32 * rb;   // first row of this 32x32 block
+        for (int e = 0; e < 2; ++e)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const uint32_t pl = 8 * (r >> 2) + 4 * h + (r & 3);
-            double re = (double)acc[0][rb][0][r];
-            double im = (double)acc[0][rb][1][r];
-            if constexpr (ACC == 2) {
-                re += (double)acc[ACC - 1][rb][0][r];
-                im += (double)acc[ACC - 1][rb][1][r];
+            for (int jj = 0; jj < 4; ++jj) {
+                const uint32_t q0 = 16 * e + 8 * h + 2 * jj;
+                const uint32_t s0 = (__popc(l32 & q0) & 1) ? 0xBF80u : 0x3F80u;
+                const uint32_t s1 = (__popc(l32 & (q0 + 1)) & 1) ? 0xBF80u : 0x3F80u;
+                fA[e][jj] = s0 | (s1 << 16);
             }
-            re *= scale;
-            im *= scale;
-            uint32_t slot;
-            if constexpr (DIR == FORWARD) {
-                rotate_minus_i(re, im, (uint32_t)__popc((X0 + l32) & (pb + pl)));
-                slot = pauli_index((uint32_t)l32, pl);           // offset inside the 1024-run
-            } else {
-                slot = ((pl ^ (uint32_t)l32) << 5) | pl;        // (row, col) inside the 32x32 square
-            }
-            if (out128) *(double2*)(stage + slot * 16) = make_double2(re, im);
-            else *(float2*)(stage + slot * 8) = make_float2((float)re, (float)im);
-        }
-        __syncthreads();
-        if constexpr (DIR == FORWARD) {
-            // contiguous run of min(1024, 4^N) coefficients starting at n(X0, pb)
-            const uint32_t run = D < 32u ? D * D : 1024u;
-            unsigned char* o = dst + (size_t)pauli_index(X0, pb) * esz;
-            if (pb < D) {
-                if (run * esz >= 16) {
-                    for (uint32_t b = lane * 16; b < run * esz; b += 64 * 16)
-                        *(u32x4*)(o + b) = *(const u32x4*)(stage + b);
-                } else if (lane == 0) {
-                    *(u32x2*)o = *(const u32x2*)stage;   // N = 0, binary32 output
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                fF[e][t] = (__popc(l32 & (8 * e + 4 * h + t)) & 1) ? -1.f : 1.f;
+    }
+    f32x16 acc[ACC][RB][2];
+#pragma unroll
+    for (int a = 0; a < ACC; ++a)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][rb][cb][r] = 0.f;
+
+    // copy this wave's quarter of pair p (clamped to the last pair) into its slot
+    auto copy_pair = [&](uint32_t p, uint32_t slot) {
+        const uint32_t ps = p < nP ? p : nP - 1;
+        const unsigned char* g = slab + (size_t)ps * PAIR_BYTES + (wave * LPW) * FRAG + lane * 16;
+        unsigned char* l = lds + slot * PAIR_BYTES + (wave * LPW) * FRAG;
+#pragma unroll
+        for (int j = 0; j < LPW; ++j)
+            __builtin_amdgcn_global_load_lds(g + j * FRAG, (__attribute__((address_space(3))) void*)(l + j * FRAG),
+                                             16, 0, 0);
+    };
+    // B fragments of one pair (two slices) as read from LDS, ping-ponged so the
+    // next pair's reads go out half-way through the current pair's MFMAs.
+    u32x4 Bb[2][2][P::NPL];
+    auto read_pair = [&](uint32_t p, int buf) {
+        const unsigned char* base = lds + (p % NSL) * PAIR_BYTES + lane * 16;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int f = 0; f < P::NPL; ++f) Bb[buf][k][f] = *(const u32x4*)(base + (k * P::NPL + f) * FRAG);
+    };
+    bf16x8 Ap[2], An[2];
+    float ts = 1.f;
+    auto slice_mfma = [&](int buf, int k, int u) {
+        if constexpr (PLANES == 3) {
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const bool neg = popc_const((uint32_t)rb & (uint32_t)(u >> 1)) & 1;
+                    const bf16x8 A = neg ? An[u & 1] : Ap[u & 1];
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        acc[pl == 0 ? 0 : ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            A, __builtin_bit_cast(bf16x8, Bb[buf][k][pl * 2 + cb]), acc[pl == 0 ? 0 : ACC - 1][rb][cb],
+                            0, 0, 0);
                 }
+        } else {
+            const f32x4 B0 = __builtin_bit_cast(f32x4, Bb[buf][k][0]), B1 = __builtin_bit_cast(f32x4, Bb[buf][k][1]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const bool neg = popc_const((uint32_t)rb & (uint32_t)(u >> 2)) & 1;
+                    const float A = (neg ? -ts : ts) * fF[u & 3][t];
+                    acc[0][rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, B0[t], acc[0][rb][0], 0, 0, 0);
+                    acc[0][rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, B1[t], acc[0][rb][1], 0, 0, 0);
+                }
+        }
+    };
+
+    // Prologue: copies of pairs 0..AHEAD in flight, pair 0 complete and read.
+#pragma unroll
+    for (int k = 0; k <= AHEAD; ++k) copy_pair(k, k);
+    wait_vmcnt<LPW * AHEAD>();
+    __builtin_amdgcn_s_barrier();
+    read_pair(0, 0);
+
+    static_assert(GP % 2 == 0 || GP == 1, "ping-pong over the pairs of a sign group");
+    for (uint32_t p0 = 0; p0 < nP; p0 += GP) {
+        const bool neg_grp = __popc((Pw >> 5) & ((2 * p0 * P::SK) >> 5)) & 1;
+        if constexpr (PLANES == 3) {
+            const uint32_t tm = neg_grp ? 0x80008000u : 0u;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const u32x4 q = {fA[e][0] ^ tm, fA[e][1] ^ tm, fA[e][2] ^ tm, fA[e][3] ^ tm};
+                Ap[e] = __builtin_bit_cast(bf16x8, q);
+                An[e] = __builtin_bit_cast(bf16x8, q ^ 0x80008000u);
             }
         } else {
-            // 32x32 square of G: rows (pb ^ X0) + rl, columns pb + cl
-            const uint32_t w = D < 32u ? D : 32u;
-            const uint32_t rowbytes = w * esz;
-            const uint32_t r0 = (pb ^ X0) & ~31u;
-            if (pb < D) {
-                if (rowbytes >= 16) {
-                    for (uint32_t b = lane * 16; b < w * rowbytes; b += 64 * 16) {
-                        const uint32_t rl = b / rowbytes, cb = b % rowbytes;
-                        *(u32x4*)(dst + ((size_t)(r0 + rl) * D + pb) * esz + cb) =
-                            *(const u32x4*)(stage + rl * 32 * esz + cb);
-                    }
-                } else if (lane == 0) {
-                    *(u32x2*)dst = *(const u32x2*)stage;     // N = 0, binary32 output
-                }
-            }
+            ts = neg_grp ? -1.f : 1.f;
         }
-        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < GP; ++j) {
+            const uint32_t p = p0 + j;
+            const int cur = (GP == 1) ? (int)(p & 1) : (j & 1);
+            __builtin_amdgcn_sched_barrier(0);
+            slice_mfma(cur, 0, 2 * j);
+            __builtin_amdgcn_sched_barrier(0);
+            // mid-pair: pair p+1 complete everywhere; refill the slot pair p
+            // used (its fragments are in registers); read pair p+1.
+            wait_vmcnt<LPW * (AHEAD - 1)>();
+            __builtin_amdgcn_s_barrier();
+            copy_pair(p + 1 + AHEAD, (p + 1 + AHEAD) % NSL);
+            read_pair(p + 1, cur ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+            slice_mfma(cur, 1, 2 * j + 1);
+        }
     }
+    wait_vmcnt<0>();                    // the ring's last (unused) copies land before the
+    __builtin_amdgcn_s_barrier();       // epilogue reuses the LDS
+    store_tile<PLANES, RB, DIR>(acc, dst, N, X0, Pw, scale, out128, lds);
 }
 
 }  // namespace mfma

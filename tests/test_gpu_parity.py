@@ -64,7 +64,7 @@ def test_mfma_small(algo, N):
 
 
 @pytest.mark.parametrize("algo", ["fp32", "split_bf16"])
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", list(range(1, 16)))
 def test_mfma_every_tile_n9(algo, tile):
     p = lib()
     N = 9
@@ -72,6 +72,23 @@ def test_mfma_every_tile_n9(algo, tile):
     c = p.decompose(dev(G), algo=algo, tile=tile).cpu().numpy()
     ref = oracle.decompose(G, threads=8)
     assert rel_err(c, ref) <= TOL[algo] * 1.5  # c64 output rounding included
+
+
+@pytest.mark.parametrize("algo", ["fp32", "split_bf16"])
+def test_tiles_bitexact_n10(algo):
+    """Every tile shape sums the K slices of an output element in the same
+    order, so all of them (register-ring and LDS-staged alike) must agree bit
+    for bit, in both directions."""
+    p = lib()
+    N = 10
+    assert p.tile_count(algo) == 15
+    G = dev(workloads.iid_complex(N, 710, np.complex64))
+    c = dev(workloads.iid_complex(N, 711, np.complex64).reshape(-1))
+    ref_f = p.decompose(G, algo=algo, tile=1)
+    ref_a = p.reconstruct(c, algo=algo, tile=1)
+    for tile in range(2, 16):
+        assert torch.equal(p.decompose(G, algo=algo, tile=tile), ref_f), tile
+        assert torch.equal(p.reconstruct(c, algo=algo, tile=tile), ref_a), tile
 
 
 @pytest.mark.parametrize("algo", ALGOS)
