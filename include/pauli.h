@@ -74,7 +74,7 @@ typedef struct pauli_opts {
     int algo;               /* pauli_algo */
     int in_dtype;           /* pauli_dtype of the input */
     int out_dtype;          /* pauli_dtype of the output */
-    int tile;               /* 0 = tuned/default tile; >0 forces a tile id (pauli_tile_count) */
+    int tile;               /* 0 = tuned/default tile; >0 forces a tile id (pauli_tile_valid) */
     void* stream;           /* hipStream_t, NULL = null stream */
     void* workspace;        /* optional device scratch, see pauli_workspace_bytes */
     size_t workspace_bytes; /* its size in bytes */
@@ -139,6 +139,9 @@ size_t pauli_batched_workspace_bytes(int count, const int* N, int algo);
 /* Number of persistent-kernel tile shapes for the uneven batch. */
 int pauli_batched_tile_count(void);
 
+/* 1 if batched tile shape `tile` can run `algo` (FP32 excludes shape 3). */
+int pauli_batched_tile_valid(int algo, int tile);
+
 /*
  * Run pauli_decompose_batched with every tile shape on the given buffers
  * (outputs are overwritten with the same correct result), time each and keep
@@ -168,8 +171,16 @@ size_t pauli_workspace_bytes(int algo, int N, int batch);
  */
 int pauli_autotune(int N_min, int N_max, const pauli_opts* opts);
 
-/* Number of selectable tile configurations for `algo` (ids 1..count). */
+/* Number of tile configurations for `algo` (ids 1..count). */
 int pauli_tile_count(int algo);
+
+/*
+ * 1 if tile id `tile` can run `algo` at order N, else 0.  A tile needs at
+ * least as many (padded) matrix rows as one workgroup covers, and FP32 does
+ * not offer the register-ring tiles of 4 x 32 rows per wave (ids 1, 2, 7, 10,
+ * 11); a forced invalid tile fails with PAULI_EINVAL.
+ */
+int pauli_tile_valid(int algo, int tile, int N);
 
 /* Tile id pauli_decompose would use for (algo, N) right now. */
 int pauli_tile_selected(int algo, int N);

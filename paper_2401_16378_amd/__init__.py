@@ -48,9 +48,9 @@ _lock = threading.Lock()
 
 EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward",
            "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_workspace_bytes",
-           "pauli_batched_tile_count", "pauli_autotune_batched", "pauli_batched_tile_selected", "pauli_autotune",
-           "pauli_tile_count", "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_last_error",
-           "pauli_version"]
+           "pauli_batched_tile_count", "pauli_batched_tile_valid", "pauli_autotune_batched",
+           "pauli_batched_tile_selected", "pauli_autotune", "pauli_tile_count", "pauli_tile_valid",
+           "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_last_error", "pauli_version"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_autotune_batched.restype = ci
         lib.pauli_batched_tile_count.argtypes = []
         lib.pauli_batched_tile_count.restype = ci
+        lib.pauli_batched_tile_valid.argtypes = [ci, ci]
+        lib.pauli_batched_tile_valid.restype = ci
         lib.pauli_batched_tile_selected.argtypes = [ci, ip, ci]
         lib.pauli_batched_tile_selected.restype = ci
         lib.pauli_workspace_bytes.argtypes = [ci, ci, ci]
@@ -86,6 +88,8 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_autotune.restype = ci
         lib.pauli_tile_count.argtypes = [ci]
         lib.pauli_tile_count.restype = ci
+        lib.pauli_tile_valid.argtypes = [ci, ci, ci]
+        lib.pauli_tile_valid.restype = ci
         lib.pauli_tile_selected.argtypes = [ci, ci]
         lib.pauli_tile_selected.restype = ci
         lib.pauli_pack.argtypes = [vp, ci, ci, ci, op]
@@ -267,6 +271,14 @@ def autotune(n_min: int, n_max: int, algo: str = "split_bf16", device=None) -> d
 
 def tile_count(algo: str = "split_bf16") -> int:
     return load_library().pauli_tile_count(ALGOS[algo])
+
+
+def tile_valid(tile: int, N: int, algo: str = "split_bf16") -> bool:
+    return bool(load_library().pauli_tile_valid(ALGOS[algo], tile, N))
+
+
+def batched_tile_valid(tile: int, algo: str = "split_bf16") -> bool:
+    return bool(load_library().pauli_batched_tile_valid(ALGOS[algo], tile))
 
 
 def tile_selected(N: int, algo: str = "split_bf16") -> int:

@@ -286,6 +286,12 @@ int pauli_tile_count(int algo) {
     return mfma_tile_count(planes_of(algo));
 }
 
+int pauli_tile_valid(int algo, int tile, int N) {
+    if (algo == PAULI_ALGO_FP64_GRAY) return tile == 1 && N >= 0 && N <= N_MAX ? 1 : 0;
+    if (!valid_algo(algo) || N < 0 || N > N_MAX) return 0;
+    return mfma_tile_valid(planes_of(algo), tile, N) ? 1 : 0;
+}
+
 int pauli_tile_selected(int algo, int N) {
     if (!valid_algo(algo) || N < 0 || N > N_MAX) return 0;
     return pick_tile(algo, N, 0);
@@ -367,6 +373,8 @@ int validate_batch(int count, const void* const* G, const int* N, void* const* o
         return fail(PAULI_EUNSUPPORTED, "%s: only C64 input and output", fn);
     if (o.tile < 0 || o.tile > batched_tile_count())
         return fail(PAULI_EINVAL, "%s: tile %d outside [0, %d]", fn, o.tile, batched_tile_count());
+    if (o.tile > 0 && !batched_tile_valid(planes_of(o.algo), o.tile))
+        return fail(PAULI_EINVAL, "%s: tile %d is not available for algo %d", fn, o.tile, o.algo);
     for (int k = 0; k < count; ++k) {
         if (N[k] < 1 || N[k] > N_MAX_BATCHED)
             return fail(PAULI_EINVAL, "%s: N[%d]=%d outside [1, %d]", fn, k, N[k], N_MAX_BATCHED);
@@ -494,6 +502,7 @@ extern "C" int pauli_autotune_batched(int count, const void* const* G, const int
     int best = 1;
     float best_ms = 1e30f;
     for (int t = 1; t <= batched_tile_count() && e == hipSuccess; ++t) {
+        if (!batched_tile_valid(planes, t)) continue;
         if ((st = run_batched(count, G, N, out, o, t, fn)) != PAULI_OK) break;   // warm-up + capture
         if ((e = hipEventRecord(a, s)) != hipSuccess) break;
         for (int r = 0; r < 5 && st == PAULI_OK; ++r) st = run_batched(count, G, N, out, o, t, fn);
@@ -522,6 +531,11 @@ extern "C" int pauli_autotune_batched(int count, const void* const* G, const int
 }
 
 extern "C" int pauli_batched_tile_count(void) { return batched_tile_count(); }
+
+extern "C" int pauli_batched_tile_valid(int algo, int tile) {
+    if (algo != PAULI_ALGO_SPLIT_BF16 && algo != PAULI_ALGO_FP32) return 0;
+    return batched_tile_valid(planes_of(algo), tile) ? 1 : 0;
+}
 
 extern "C" int pauli_batched_tile_selected(int count, const int* N, int algo) {
     if (count < 1 || !N || (algo != PAULI_ALGO_SPLIT_BF16 && algo != PAULI_ALGO_FP32)) return 0;

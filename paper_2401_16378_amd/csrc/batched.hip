@@ -85,21 +85,25 @@ constexpr int NBTILES = sizeof(BTILES) / sizeof(BTILES[0]);
 template <int PLANES, int RB, int WAVES, int PF>
 hipError_t launch_contract_batched(const BatchItem* items, int count, uint32_t total, const unsigned char* ws,
                                    unsigned int* counter, hipStream_t s) {
-    auto kern = contract_batched_kernel<PLANES, RB, WAVES, PF>;
-    const int lds = WAVES * 1024 * 8;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    int dev = 0, cus = 0, per_cu = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WAVES * 64, lds)) !=
-        hipSuccess)
-        return e;
-    if (per_cu < 1) per_cu = 1;
-    uint32_t grid = (uint32_t)cus * (uint32_t)per_cu;
-    if (grid > total) grid = total;   // never more workgroups than tiles
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES * 64), lds, s, items, count, total, ws, counter);
-    return hipGetLastError();
+    if constexpr (!ring_tile_ok(PLANES, RB)) {
+        return hipErrorInvalidValue;
+    } else {
+        auto kern = contract_batched_kernel<PLANES, RB, WAVES, PF>;
+        const int lds = WAVES * 1024 * 8;
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        int dev = 0, cus = 0, per_cu = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WAVES * 64, lds)) !=
+            hipSuccess)
+            return e;
+        if (per_cu < 1) per_cu = 1;
+        uint32_t grid = (uint32_t)cus * (uint32_t)per_cu;
+        if (grid > total) grid = total;   // never more workgroups than tiles
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES * 64), lds, s, items, count, total, ws, counter);
+        return hipGetLastError();
+    }
 }
 
 template <int PLANES>
@@ -118,6 +122,10 @@ hipError_t launch_contract_btile(int btile, const BatchItem* items, int count, u
 
 int batched_tile_count() { return NBTILES; }
 
+bool batched_tile_valid(int planes, int btile) {
+    return btile >= 1 && btile <= NBTILES && ring_tile_ok(planes, BTILES[btile - 1].rb);
+}
+
 uint32_t batched_output_tiles(int btile, int n) {
     const BTile t = BTILES[btile - 1];
     const uint32_t MT = t.rb * t.waves * 32;
@@ -135,7 +143,7 @@ size_t batched_packed_bytes(int planes, int n) {
 hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, int count, uint32_t pack_total,
                           uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
                           hipStream_t stream) {
-    if (btile < 1 || btile > NBTILES) return hipErrorInvalidValue;
+    if (!batched_tile_valid(planes, btile)) return hipErrorInvalidValue;
     if (planes == 3)
         hipLaunchKernelGGL((pack_batched_kernel<3>), dim3(pack_total), dim3(256), 0, stream, items_dev, count, packed);
     else

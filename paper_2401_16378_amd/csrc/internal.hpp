@@ -42,6 +42,7 @@ struct BatchItem {
     uint32_t tile0;   // first output tile of this matrix in the batch numbering
 };
 int batched_tile_count();
+bool batched_tile_valid(int planes, int btile);
 uint32_t batched_output_tiles(int btile, int n);
 uint32_t batched_pack_tiles(int n);
 size_t batched_packed_bytes(int planes, int n);

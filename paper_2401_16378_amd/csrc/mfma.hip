@@ -67,6 +67,7 @@ hipError_t launch_contract_lds(const Params& p, int batch, hipStream_t s) {
 // ---- tile table: (rows per wave / 32, waves per workgroup, ring depth) ----
 struct TileDesc {
     int rb, waves, pf;
+    bool lds = false;   // LDS-staged variant (pf = pairs copied ahead)
 };
 constexpr TileDesc TILES[] = {
     {4, 4, 4},  // 1: 512 rows
@@ -81,23 +82,27 @@ constexpr TileDesc TILES[] = {
     {4, 4, 8},  // 10: 512 rows, deeper ring
     {4, 2, 8},  // 11: 256 rows, deeper ring
     {2, 4, 8},  // 12: 256 rows, deeper ring
-    {4, 4, 3},  // 13: 512 rows, LDS-staged, copies 3 slice pairs ahead
-    {4, 4, 7},  // 14: 512 rows, LDS-staged, copies 7 slice pairs ahead
-    {2, 4, 3},  // 15: 256 rows, LDS-staged, copies 3 slice pairs ahead
+    {4, 4, 3, true},  // 13: 512 rows, LDS-staged, copies 3 slice pairs ahead
+    {4, 4, 7, true},  // 14: 512 rows, LDS-staged, copies 7 slice pairs ahead
+    {2, 4, 3, true},  // 15: 256 rows, LDS-staged, copies 3 slice pairs ahead
 };
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
 template <int PLANES, int RB, int WAVES, int PF, int DIR>
 hipError_t launch_contract(const Params& p, int batch, hipStream_t s) {
-    constexpr int MT = WAVES * RB * 32;
-    const uint32_t Dp = padded_dim(p.N);
-    const uint32_t nMB = Dp / MT, nXB = Dp / XT;
-    auto kern = contract_kernel<PLANES, RB, WAVES, DIR, PF>;
-    const int lds = WAVES * 1024 * (p.out128 ? 16 : 8);
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(WAVES * 64), lds, s, p);
-    return hipGetLastError();
+    if constexpr (!ring_tile_ok(PLANES, RB)) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int MT = WAVES * RB * 32;
+        const uint32_t Dp = padded_dim(p.N);
+        const uint32_t nMB = Dp / MT, nXB = Dp / XT;
+        auto kern = contract_kernel<PLANES, RB, WAVES, DIR, PF>;
+        const int lds = WAVES * 1024 * (p.out128 ? 16 : 8);
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(WAVES * 64), lds, s, p);
+        return hipGetLastError();
+    }
 }
 
 template <int PLANES, int DIR>
@@ -134,14 +139,15 @@ hipError_t launch_pack(const void* in, bool in128, void* ws, int N, int batch, h
 
 int mfma_tile_count(int /*planes*/) { return NTILES; }
 
-bool mfma_tile_valid(int /*planes*/, int tile, int N) {
+bool mfma_tile_valid(int planes, int tile, int N) {
     if (tile < 1 || tile > NTILES) return false;
     const TileDesc t = TILES[tile - 1];
+    if (!t.lds && !ring_tile_ok(planes, t.rb)) return false;
     return padded_dim(N) >= (uint32_t)(t.rb * t.waves * 32);
 }
 
 int mfma_default_tile(int planes, int N) {
-    (void)planes;
+    if (planes == 1 && N >= 8) return 15;   // LDS-staged, 256 rows: fastest binary32 shape
     if (N >= 9) return 1;
     if (N == 8) return 3;
     if (N == 7) return 6;

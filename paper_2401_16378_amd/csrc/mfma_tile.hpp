@@ -250,6 +250,33 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
     }
 }
 
+// Binary32 plane: an MFMA accumulator chain adds at most FLUSH_SLICES slices
+// (256 K values) before it is added into a running binary32 total and
+// restarted from zero.  The boundary is a fixed K offset, the same for every
+// tile shape, so all tiles still sum each output in one order; a chain of 256
+// terms instead of 2^N cuts the accumulated rounding by about sqrt(2^N / 256).
+constexpr uint32_t FLUSH_SLICES = 256 / Pack<1>::SK;
+
+// Register-ring tiles of 4 x 32 rows per wave need the 128 accumulators plus
+// the 128-register binary32 total next to the fragment ring, more than the
+// register file holds; compiled that way they spill and the adjoint direction
+// returned wrong values, so the binary32 plane does not offer them (its
+// LDS-staged and 2 x 32-row tiles run at the same speed).
+constexpr bool ring_tile_ok(int planes, int rb) { return !(planes == 1 && rb == 4); }
+
+template <int RB>
+__device__ inline void flush_into(f32x16 (&tot)[1][RB][2], f32x16 (&acc)[1][RB][2]) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                tot[0][rb][cb][r] += acc[0][rb][cb][r];
+                acc[0][rb][cb][r] = 0.f;
+            }
+}
+
 // Epilogue shared by the contraction variants: binary64 recombination of the
 // accumulators, phase, scale, and an LDS-staged store of each 32x32 block as
 // one contiguous coefficient run (forward) or one aligned square of G
@@ -338,7 +365,7 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
     constexpr int GS = 2 * (U > PF ? U : PF);              // slices per unrolled step
     static_assert(GS % U == 0 && GS % PF == 0, "ring depth and sign group must nest");
 
-    const uint32_t D = 1u << N, Dp = padded_dim(N);
+    const uint32_t Dp = padded_dim(N);
     const uint32_t nS = Dp / P::SK;
     const uint32_t X0 = xb * XT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -370,7 +397,7 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
                 fF[e][t] = (__popc(l32 & (8 * e + 4 * h + t)) & 1) ? -1.f : 1.f;
     }
 
-    f32x16 acc[ACC][RB][2];
+    f32x16 acc[ACC][RB][2], tot[1][RB][2];   // tot: binary32 plane's flushed total
 #pragma unroll
     for (int a = 0; a < ACC; ++a)
 #pragma unroll
@@ -378,7 +405,7 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc[a][rb][cb][r] = 0.f;
+                for (int r = 0; r < 16; ++r) acc[a][rb][cb][r] = tot[0][rb][cb][r] = 0.f;
 
     // ---- B fragment ring ----
     u32x4 ring[PF][P::NPL];
@@ -441,6 +468,13 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
                             acc[0][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, Bv[cb][t], acc[0][rb][cb], 0, 0, 0);
                     }
             }
+            if constexpr (PLANES == 1) {
+                if constexpr (GS % FLUSH_SLICES == 0) {
+                    if (uu % FLUSH_SLICES == FLUSH_SLICES - 1) flush_into<RB>(tot, acc);
+                } else {
+                    if ((s0 + uu + 1) % FLUSH_SLICES == 0) flush_into<RB>(tot, acc);
+                }
+            }
             // Refill this slot with slice s+PF.  The fences keep the loads
             // here, PF slices ahead of their use, instead of letting the
             // scheduler sink them next to the MFMAs that consume them.
@@ -483,15 +517,22 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
                     }
                 }
             }
+            if constexpr (PLANES == 1) {
+                if ((s + 1) % FLUSH_SLICES == 0) flush_into<RB>(tot, acc);
+            }
         }
     }
 
-    store_tile<PLANES, RB, DIR>(acc, dst, N, X0, Pw, scale, out128, lds);
+    if constexpr (PLANES == 1) {
+        flush_into<RB>(tot, acc);
+        store_tile<PLANES, RB, DIR>(tot, dst, N, X0, Pw, scale, out128, lds);
+    } else {
+        store_tile<PLANES, RB, DIR>(acc, dst, N, X0, Pw, scale, out128, lds);
+    }
 }
 
-// s_waitcnt with vmcnt <= NV and the other counters unconstrained (gfx9
-// encoding: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8], vmcnt[15:14]).
-// Wait until at most NV vector-memory operations of this wave are outstanding
+// s_waitcnt (gfx9 encoding: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8],
+// vmcnt[15:14]).  Wait until at most NV vector-memory operations of this wave are outstanding
 // and every LDS read it issued has returned (lgkmcnt 0), so that a following
 // barrier also orders this wave's LDS reads before other waves' ring refills.
 template <int NV>
@@ -552,7 +593,7 @@ __device__ inline void contract_tile_lds(const unsigned char* __restrict__ wsm, 
             for (int t = 0; t < 4; ++t)
                 fF[e][t] = (__popc(l32 & (8 * e + 4 * h + t)) & 1) ? -1.f : 1.f;
     }
-    f32x16 acc[ACC][RB][2];
+    f32x16 acc[ACC][RB][2], tot[1][RB][2];   // tot: binary32 plane's flushed total
 #pragma unroll
     for (int a = 0; a < ACC; ++a)
 #pragma unroll
@@ -560,7 +601,7 @@ __device__ inline void contract_tile_lds(const unsigned char* __restrict__ wsm, 
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc[a][rb][cb][r] = 0.f;
+                for (int r = 0; r < 16; ++r) acc[a][rb][cb][r] = tot[0][rb][cb][r] = 0.f;
 
     // copy this wave's quarter of pair p (clamped to the last pair) into its slot
     auto copy_pair = [&](uint32_t p, uint32_t slot) {
@@ -648,11 +689,19 @@ __device__ inline void contract_tile_lds(const unsigned char* __restrict__ wsm, 
             read_pair(p + 1, cur ^ 1);
             __builtin_amdgcn_sched_barrier(0);
             slice_mfma(cur, 1, 2 * j + 1);
+            if constexpr (PLANES == 1) {
+                if ((2 * (p + 1)) % FLUSH_SLICES == 0) flush_into<RB>(tot, acc);
+            }
         }
     }
     wait_vmcnt<0>();                    // the ring's last (unused) copies land before the
     __builtin_amdgcn_s_barrier();       // epilogue reuses the LDS
-    store_tile<PLANES, RB, DIR>(acc, dst, N, X0, Pw, scale, out128, lds);
+    if constexpr (PLANES == 1) {
+        flush_into<RB>(tot, acc);
+        store_tile<PLANES, RB, DIR>(tot, dst, N, X0, Pw, scale, out128, lds);
+    } else {
+        store_tile<PLANES, RB, DIR>(acc, dst, N, X0, Pw, scale, out128, lds);
+    }
 }
 
 }  // namespace mfma

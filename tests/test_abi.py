@@ -78,6 +78,7 @@ def test_validation_errors(lib, pauli, fn):
         (FAKE_IN, 4, 1, FAKE_OUT, opts(pauli, in_dt=7), EINVAL),
         (FAKE_IN, 4, 1, FAKE_OUT, opts(pauli, tile=99), EINVAL),
         (FAKE_IN, 4, 1, FAKE_OUT, opts(pauli, tile=1), EINVAL),    # 512-row tile at N = 4
+        (FAKE_IN, 12, 1, FAKE_OUT, opts(pauli, algo="fp32", tile=1), EINVAL),   # not offered for binary32
         (FAKE_IN, 10, 1, FAKE_OUT, opts(pauli, ws=0x30000008, ws_bytes=1 << 30), EINVAL),  # misaligned ws
         (FAKE_IN, 10, 1, FAKE_OUT, opts(pauli, ws=0x30000000, ws_bytes=1024), ENOMEM),
     ]
@@ -103,10 +104,21 @@ def test_tiles(lib):
     n = lib.pauli_tile_count(2)
     assert n >= 6 and lib.pauli_tile_count(1) == n and lib.pauli_tile_count(0) == 1
     assert lib.pauli_tile_count(7) == 0
-    for N in range(0, 17):
-        t = lib.pauli_tile_selected(2, N)
-        assert 1 <= t <= n
+    for algo in (1, 2):
+        for N in range(0, 17):
+            t = lib.pauli_tile_selected(algo, N)
+            assert 1 <= t <= n and lib.pauli_tile_valid(algo, t, N) == 1, (algo, N, t)
+    # 512-row tiles need N >= 9; binary32 has no 4 x 32-row register-ring tiles
+    assert lib.pauli_tile_valid(2, 1, 9) == 1 and lib.pauli_tile_valid(2, 1, 8) == 0
+    for t in (1, 2, 7, 10, 11):
+        assert lib.pauli_tile_valid(1, t, 12) == 0
+    for t in (3, 4, 5, 6, 8, 9, 12, 13, 14, 15):
+        assert lib.pauli_tile_valid(1, t, 12) == 1
+    assert lib.pauli_tile_valid(0, 1, 10) == 1 and lib.pauli_tile_valid(0, 2, 10) == 0
+    assert lib.pauli_tile_valid(2, 0, 10) == 0 and lib.pauli_tile_valid(2, n + 1, 10) == 0
     assert lib.pauli_batched_tile_count() >= 1
+    assert lib.pauli_batched_tile_valid(2, 3) == 1 and lib.pauli_batched_tile_valid(1, 3) == 0
+    assert lib.pauli_batched_tile_valid(1, 1) == 1 and lib.pauli_batched_tile_valid(0, 1) == 0
 
 
 def test_batched_validation(lib, pauli):
@@ -129,6 +141,8 @@ def test_batched_validation(lib, pauli):
     assert lib.pauli_decompose_batched(2, G, Ns, O, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_batched_workspace_bytes(2, bad, 2) == 0
     assert lib.pauli_batched_tile_selected(2, Ns, 2) >= 1
+    ws = opts(pauli, algo="fp32", tile=3, ws=0x40000000, ws_bytes=need)
+    assert lib.pauli_decompose_batched(2, G, Ns, O, ctypes.byref(ws)) == EINVAL
 
 
 def test_pass_entry_points_validation(lib, pauli):

@@ -116,9 +116,14 @@ def test_autotune_batched(batch):
 
 def test_small_mixed_batch_fp32():
     p = lib()
-    Ns = [1, 2, 5, 3, 7, 4, 6]
+    Ns = [1, 2, 5, 3, 7, 4, 6, 9]
     mats = [workloads.iid_complex(n, 40 + n, np.complex64) for n in Ns]
-    outs = p.decompose_batched([torch.from_numpy(m).to("cuda") for m in mats], algo="fp32")
-    for m, o in zip(mats, outs):
-        ref = oracle.decompose(m)
-        assert np.abs(o.cpu().numpy() - ref).max() / np.abs(ref).max() <= 1e-5
+    dev_m = [torch.from_numpy(m).to("cuda") for m in mats]
+    tiles = [t for t in range(1, p.load_library().pauli_batched_tile_count() + 1) if p.batched_tile_valid(t, "fp32")]
+    assert 3 not in tiles and len(tiles) >= 3
+    for tile in tiles:
+        outs = p.decompose_batched(dev_m, algo="fp32", tile=tile)
+        for m, o in zip(mats, outs):
+            ref = oracle.decompose(m)
+            assert np.abs(o.cpu().numpy() - ref).max() / np.abs(ref).max() <= 1e-5, tile
+    assert 1 <= p.autotune_batched(dev_m, algo="fp32") in tiles
