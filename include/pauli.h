@@ -185,6 +185,34 @@ int pauli_tile_valid(int algo, int tile, int N);
 /* Tile id pauli_decompose would use for (algo, N) right now. */
 int pauli_tile_selected(int algo, int N);
 
+/*
+ * Coefficients of a caller-chosen list of Pauli strings (the paper's inner
+ * product of a matrix with a single Pauli string, O(2^N) each; sections 3
+ * and 4):
+ *     out[k] = 2^-N Tr(P_{strings[k]} G),   k = 0 .. count-1,
+ * the same value pauli_decompose gives for that n (section 2,
+ * Eq. (c_def_in_terms_of_fn)), summed in binary64 whatever the dtypes.
+ * G: DEVICE, one 2^N x 2^N matrix (opts->in_dtype).  strings: HOST array of
+ * count string indices, each below 4^N (else PAULI_EINVAL); repeats allowed.
+ * out: DEVICE, count coefficients (opts->out_dtype), in the order of strings.
+ * 0 <= N <= 16, count >= 1.  opts->algo and opts->tile are ignored.
+ * The library sorts the list by flip mask on the host (strings whose flip
+ * masks agree above bit 3 share one pass over their 16 XOR-diagonals of G)
+ * and copies that plan into opts->workspace (at least
+ * pauli_coeffs_at_workspace_bytes(count) bytes) or, when it is NULL, into
+ * memory from the library's pool.  The strings array may be reused as soon
+ * as the call returns.
+ */
+int pauli_coeffs_at(const void* G, int N, const unsigned int* strings, int count, void* out,
+                    const pauli_opts* opts);
+
+/*
+ * Workspace bytes that suffice for pauli_coeffs_at with any list of `count`
+ * strings at order N (the plan plus, for short lists whose columns are split
+ * over several workgroups, binary64 partial sums); 0 for invalid arguments.
+ */
+size_t pauli_coeffs_at_workspace_bytes(int N, int count);
+
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char* pauli_last_error(void);
 

@@ -50,7 +50,8 @@ EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_
            "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_workspace_bytes",
            "pauli_batched_tile_count", "pauli_batched_tile_valid", "pauli_autotune_batched",
            "pauli_batched_tile_selected", "pauli_autotune", "pauli_tile_count", "pauli_tile_valid",
-           "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_last_error", "pauli_version"]
+           "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_coeffs_at",
+           "pauli_coeffs_at_workspace_bytes", "pauli_last_error", "pauli_version"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -96,6 +97,10 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_pack.restype = ci
         lib.pauli_contract.argtypes = [ci, ci, ci, vp, op]
         lib.pauli_contract.restype = ci
+        lib.pauli_coeffs_at.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_uint), ci, vp, op]
+        lib.pauli_coeffs_at.restype = ci
+        lib.pauli_coeffs_at_workspace_bytes.argtypes = [ci, ci]
+        lib.pauli_coeffs_at_workspace_bytes.restype = ctypes.c_size_t
         lib.pauli_last_error.argtypes = []
         lib.pauli_last_error.restype = ctypes.c_char_p
         lib.pauli_version.argtypes = []
@@ -214,6 +219,31 @@ def decompose_backward(grad_c: torch.Tensor, algo: str = "split_bf16", out_dtype
 _batch_ws = {}
 
 
+def coeffs_at(G: torch.Tensor, strings, out_dtype=None, workspace_tensor=None) -> torch.Tensor:
+    """c_k = 2^-N Tr(P_{strings[k]} G) for one complex matrix G [2^N, 2^N] and a
+    host list of string indices, O(2^N) each, summed in binary64."""
+    import numpy as np
+    G = _prep(G)
+    N = _qubits_of_matrix(G)
+    if G.dim() != 2:
+        raise ValueError("coeffs_at takes one matrix, got shape %s" % (tuple(G.shape),))
+    ns = np.ascontiguousarray(np.asarray(strings, dtype=np.uint64).reshape(-1))
+    if ns.size and int(ns.max()) >= 1 << (2 * N):
+        raise ValueError("string index %d is not below 4^%d" % (int(ns.max()), N))
+    ns = ns.astype(np.uint32)
+    out_dtype = out_dtype or G.dtype
+    out = torch.empty(ns.shape[0], dtype=out_dtype, device=G.device)
+    if ns.shape[0] == 0:
+        return out
+    o = _opts("fp64_gray", _DT[G.dtype], _DT[out_dtype], 0, _stream(G))
+    if workspace_tensor is not None:
+        o.workspace = workspace_tensor.data_ptr()
+        o.workspace_bytes = workspace_tensor.numel() * workspace_tensor.element_size()
+    _check(load_library().pauli_coeffs_at(G.data_ptr(), N, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint)),
+                                          ns.shape[0], out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
 def _batch_args(mats, algo, outs):
     mats = [_prep(m) for m in mats]
     for m in mats:
@@ -287,6 +317,6 @@ def tile_selected(N: int, algo: str = "split_bf16") -> int:
 
 from .autograd import PauliDecompose  # noqa: E402
 
-__all__ = ["decompose", "reconstruct", "decompose_backward", "decompose_batched", "autotune",
-           "autotune_batched", "workspace",
+__all__ = ["decompose", "reconstruct", "decompose_backward", "decompose_batched", "coeffs_at", "autotune",
+           "autotune_batched", "workspace", "tile_valid", "batched_tile_valid", "tile_count", "tile_selected",
            "PauliDecompose", "PauliError", "load_library", "last_error", "ALGOS", "EXPORTS"]

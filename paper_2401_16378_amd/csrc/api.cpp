@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/pauli.h"
+#include "common.hpp"
 #include "internal.hpp"
 
 using namespace pauli;
@@ -615,6 +616,153 @@ extern "C" int pauli_autotune(int N_min, int N_max, const pauli_opts* opts) {
         for (auto& kv : g_tune) fprintf(f, "%d %d %d\n", kv.first.first, kv.first.second, kv.second);
         fclose(f);
     }
+    g_last_error.clear();
+    return PAULI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Coefficients of a list of Pauli strings.  Host plan: sort the strings by
+// line group (x >> 4) and low mask bits, cut each group into chunks of at most
+// STRINGS_PER_CHUNK, copy [chunks | entries] into the workspace from pinned
+// staging, launch one workgroup per chunk.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct StringsPlan {
+    std::vector<StringChunk> chunks;
+    std::vector<StringEntry> entries;
+    int parts = 1;   // workgroups per chunk (column split), see strings_parts
+};
+
+// Split the columns of each chunk over several workgroups when there are too
+// few chunks to fill the device: about STRINGS_MAX_BLOCKS workgroups in all.
+int strings_parts(int N, size_t nchunks) {
+    const size_t want = (size_t)STRINGS_MAX_BLOCKS / nchunks;
+    const size_t cap = strings_batches(N);
+    const size_t p = want < cap ? want : cap;
+    return p < 1 ? 1 : (int)p;
+}
+
+size_t strings_ws_bytes(size_t nchunks, size_t count, int parts) {
+    return round256(sizeof(StringChunk) * nchunks) + round256(sizeof(StringEntry) * count) +
+           (parts > 1 ? round256(sizeof(double) * 2 * count * (size_t)parts) : 0);
+}
+
+// Counting sort of the list by flip mask (stable, O(count + 2^N)), then cut
+// every line group into chunks.
+StringsPlan plan_strings(int N, const uint32_t* strings, int count) {
+    StringsPlan P;
+    const uint32_t nx = 1u << N;
+    std::vector<uint32_t> start(nx + 1, 0u), xs(count);
+    for (int k = 0; k < count; ++k) {
+        xs[k] = flip_of_index(strings[k]);
+        ++start[xs[k] + 1];
+    }
+    for (uint32_t x = 0; x < nx; ++x) start[x + 1] += start[x];
+    std::vector<uint32_t> order(count);
+    {
+        std::vector<uint32_t> fill(start.begin(), start.end() - 1);
+        for (int k = 0; k < count; ++k) order[fill[xs[k]]++] = (uint32_t)k;
+    }
+    P.entries.resize(count);
+    for (int a = 0; a < count; ++a) P.entries[a] = {strings[order[a]], order[a]};
+    const uint32_t W = N < 4 ? nx : 16u;           // masks per line group
+    for (uint32_t g0 = 0; g0 < nx; g0 += W) {
+        const uint32_t a0 = start[g0], a1 = start[g0 + W];
+        for (uint32_t a = a0; a < a1; a += STRINGS_PER_CHUNK) {
+            const uint32_t b = std::min(a1, a + (uint32_t)STRINGS_PER_CHUNK);
+            P.chunks.push_back({g0, a, b - a, 0u});
+        }
+    }
+    P.parts = strings_parts(N, P.chunks.size());
+    return P;
+}
+
+// Pinned host staging for the plan, reused across calls once the copy that
+// last read it has completed.
+std::mutex g_stage_mu;
+void* g_stage = nullptr;
+size_t g_stage_bytes = 0;
+hipEvent_t g_stage_done = nullptr;
+
+}  // namespace
+
+extern "C" size_t pauli_coeffs_at_workspace_bytes(int N, int count) {
+    if (count < 1 || N < 0 || N > N_MAX) return 0;
+    // chunks <= count; the column split gives chunks x parts <= STRINGS_MAX_BLOCKS
+    // with chunks >= count / STRINGS_PER_CHUNK, so parts x count stays below
+    // STRINGS_MAX_BLOCKS x STRINGS_PER_CHUNK + count, and parts <= strings_batches(N).
+    const size_t c = (size_t)count;
+    size_t pc = std::min(c * strings_batches(N), (size_t)STRINGS_MAX_BLOCKS * STRINGS_PER_CHUNK + c);
+    return round256(sizeof(StringChunk) * c) + round256(sizeof(StringEntry) * c) + round256(sizeof(double) * 2 * pc);
+}
+
+extern "C" int pauli_coeffs_at(const void* G, int N, const unsigned int* strings, int count, void* out,
+                               const pauli_opts* opts) {
+    const char* fn = "pauli_coeffs_at";
+    const pauli_opts o = resolve(opts);
+    if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
+    if (count < 1) return fail(PAULI_EINVAL, "%s: count=%d must be >= 1", fn, count);
+    if (!G || !out || !strings) return fail(PAULI_EINVAL, "%s: NULL pointer", fn);
+    if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
+        return fail(PAULI_EINVAL, "%s: unknown dtype (in %d, out %d)", fn, o.in_dtype, o.out_dtype);
+    if ((uintptr_t)G % 16 || (uintptr_t)out % 16) return fail(PAULI_EINVAL, "%s: G or out not 16-byte aligned", fn);
+    const uint64_t nmax = (uint64_t)1 << (2 * N);
+    for (int k = 0; k < count; ++k)
+        if ((uint64_t)strings[k] >= nmax)
+            return fail(PAULI_EINVAL, "%s: strings[%d]=%u is not below 4^%d", fn, k, strings[k], N);
+    const size_t gbytes = (size_t)nmax * elem_bytes(o.in_dtype), obytes = (size_t)count * elem_bytes(o.out_dtype);
+    if (overlaps(G, gbytes, out, obytes)) return fail(PAULI_EINVAL, "%s: input and output overlap", fn);
+    const StringsPlan P = plan_strings(N, strings, count);
+    const size_t need = strings_ws_bytes(P.chunks.size(), P.entries.size(), P.parts);
+    if (o.workspace) {
+        if ((uintptr_t)o.workspace % 256) return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+        if (o.workspace_bytes < need)
+            return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, o.workspace_bytes);
+        if (overlaps(o.workspace, need, G, gbytes) || overlaps(o.workspace, need, out, obytes))
+            return fail(PAULI_EINVAL, "%s: workspace overlaps input or output", fn);
+    }
+    hipStream_t s = (hipStream_t)o.stream;
+    hipError_t e;
+    void* ws = o.workspace;
+    hipMemPool_t pool = nullptr;
+    if (!ws) {
+        if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
+        if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
+    }
+    const size_t chunk_bytes = round256(sizeof(StringChunk) * P.chunks.size());
+    const size_t plan_bytes = chunk_bytes + round256(sizeof(StringEntry) * P.entries.size());
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        if (!g_stage_done && (e = hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming)) != hipSuccess) {
+            g_stage_done = nullptr;
+            goto fail_free;
+        }
+        if ((e = hipEventSynchronize(g_stage_done)) != hipSuccess) goto fail_free;
+        if (g_stage_bytes < plan_bytes) {
+            if (g_stage) (void)hipHostFree(g_stage);
+            g_stage = nullptr;
+            g_stage_bytes = 0;
+            if ((e = hipHostMalloc(&g_stage, plan_bytes)) != hipSuccess) {
+                g_stage = nullptr;
+                goto fail_free;
+            }
+            g_stage_bytes = plan_bytes;
+        }
+        memcpy(g_stage, P.chunks.data(), sizeof(StringChunk) * P.chunks.size());
+        memcpy((char*)g_stage + chunk_bytes, P.entries.data(), sizeof(StringEntry) * P.entries.size());
+        if ((e = hipMemcpyAsync(ws, g_stage, plan_bytes, hipMemcpyHostToDevice, s)) != hipSuccess) goto fail_free;
+        if ((e = hipEventRecord(g_stage_done, s)) != hipSuccess) goto fail_free;
+    }
+    e = launch_strings(G, o.in_dtype == PAULI_C128, N, (const StringChunk*)ws, (int)P.chunks.size(),
+                       (const StringEntry*)((char*)ws + chunk_bytes), count, P.parts,
+                       (double2*)((char*)ws + plan_bytes), out, o.out_dtype == PAULI_C128, s);
+fail_free:
+    if (pool) {
+        const hipError_t ef = hipFreeAsync(ws, s);
+        if (e == hipSuccess) e = ef;
+    }
+    if (e != hipSuccess) return hip_fail(e, fn);
     g_last_error.clear();
     return PAULI_OK;
 }

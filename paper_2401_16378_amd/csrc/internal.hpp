@@ -50,4 +50,25 @@ hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, int
                           uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
                           hipStream_t stream);
 
+// Pauli-string list: the host sorts the strings into chunks of at most 256
+// strings sharing a line group (flip masks equal above bit 3); chunk k covers
+// entries[first, first + count) and the masks x0 .. x0 + 15 (x0 = 0 for N < 4).
+struct StringChunk {
+    uint32_t x0, first, count, pad;
+};
+struct StringEntry {
+    uint32_t n;      // Pauli string index (< 4^N)
+    uint32_t slot;   // position of its coefficient in the output
+};
+constexpr int STRINGS_PER_CHUNK = 256;
+constexpr int STRINGS_MAX_BLOCKS = 2048;   // chunks x parts aimed for when the list is short
+// Column batches of one line-group pass at order N (the most parts a chunk can split into).
+uint32_t strings_batches(int N);
+// parts > 1 splits every chunk's columns over `parts` workgroups whose binary64
+// partial sums (parts x count double2 in `partial`, indexed by entry) are then
+// added in order by a second kernel.
+hipError_t launch_strings(const void* G, bool in_c128, int N, const StringChunk* chunks, int nchunks,
+                          const StringEntry* entries, int count, int parts, double2* partial, void* out,
+                          bool out_c128, hipStream_t stream);
+
 }  // namespace pauli

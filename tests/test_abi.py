@@ -162,3 +162,34 @@ def test_autotune_validation(lib, pauli):
     assert lib.pauli_autotune(5, 3, ctypes.byref(o)) == EINVAL
     assert lib.pauli_autotune(0, 3, ctypes.byref(o)) == EINVAL
     assert lib.pauli_autotune(3, 5, ctypes.byref(opts(pauli, algo="fp64_gray"))) == EUNSUPPORTED
+
+
+def test_coeffs_at_validation(lib, pauli):
+    u32 = ctypes.c_uint
+    ns = (u32 * 3)(0, 5, 15)
+    o = opts(pauli)
+    f = lib.pauli_coeffs_at
+    cases = [
+        (FAKE_IN, -1, ns, 3, FAKE_OUT, EINVAL),
+        (FAKE_IN, 17, ns, 3, FAKE_OUT, EINVAL),
+        (FAKE_IN, 2, ns, 0, FAKE_OUT, EINVAL),
+        (None, 2, ns, 3, FAKE_OUT, EINVAL),
+        (FAKE_IN, 2, None, 3, FAKE_OUT, EINVAL),
+        (FAKE_IN, 2, ns, 3, None, EINVAL),
+        (FAKE_IN + 8, 2, ns, 3, FAKE_OUT, EINVAL),
+        (FAKE_IN, 1, ns, 3, FAKE_OUT, EINVAL),        # 5 and 15 are not below 4^1
+        (FAKE_IN, 2, ns, 3, FAKE_IN + 64, EINVAL),    # output inside G
+    ]
+    for G, N, s, c, out, want in cases:
+        assert f(G, N, s, c, out, ctypes.byref(o)) == want, (N, c, pauli.last_error())
+        assert pauli.last_error() != ""
+    small = opts(pauli, ws=0x30000000, ws_bytes=64)
+    assert f(FAKE_IN, 2, ns, 3, FAKE_OUT, ctypes.byref(small)) == ENOMEM
+    mis = opts(pauli, ws=0x30000010, ws_bytes=1 << 20)
+    assert f(FAKE_IN, 2, ns, 3, FAKE_OUT, ctypes.byref(mis)) == EINVAL
+    assert lib.pauli_coeffs_at_workspace_bytes(2, 0) == 0
+    assert lib.pauli_coeffs_at_workspace_bytes(17, 5) == 0
+    assert lib.pauli_coeffs_at_workspace_bytes(2, 1) == 768          # chunk + entry + one partial
+    assert lib.pauli_coeffs_at_workspace_bytes(14, 1) >= 16 * 128     # a single string split 128 ways
+    big = lib.pauli_coeffs_at_workspace_bytes(14, 1 << 20)
+    assert 24 * (1 << 20) <= big <= 24 * (1 << 20) + 16 * (2048 * 256 + (1 << 20)) + 1024
