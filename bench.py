@@ -38,25 +38,27 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2401_16378_amd/csrc/mfma_tile.hpp", "paper_2401_16378_amd/csrc/mfma.hip",
                   "paper_2401_16378_amd/csrc/common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_bf16_n14.json")
+STRINGS_SOURCES = ["paper_2401_16378_amd/csrc/strings.hip", "paper_2401_16378_amd/csrc/common.hpp"]
+STRINGS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_strings_n14.json")
 
 
-def source_hash() -> str:
+def source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+def measured_traffic(path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the kernel as it stands now."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != source_hash():
+    if t.get("source_hash") != source_hash(sources):
         return None
     return t.get("bytes_per_launch")
 
@@ -170,10 +172,67 @@ def bench_backward(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_strings(a):
+    """Coefficients of a list of 65,536 Pauli strings (seeded uniform sample
+    without replacement) of the N=14 complex64 Hermitian matrix: one
+    pauli_coeffs_at call per step, binary64 sums."""
+    import torch
+    import paper_2401_16378_amd as pauli
+    import workloads
+    dev = torch.device("cuda:0")
+    N, L = a.N, a.strings
+    log("[bench] generating N=%d Hermitian complex64 input (seed %d)" % (N, workloads.SEED_N14))
+    G = workloads.hermitian(N, workloads.SEED_N14)
+    Gd = torch.from_numpy(G).to(dev)
+    ns = workloads.sample_indices(4 ** N, L, seed=workloads.SEED_SAMPLE).astype(np.uint32)
+    lib = pauli.load_library()
+    ws = torch.empty(lib.pauli_coeffs_at_workspace_bytes(N, L), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    ms = timed(lambda: pauli.coeffs_at(Gd, ns, workspace_tensor=ws), a.steps, a.warmup, stream)
+    got = pauli.coeffs_at(Gd, ns, out_dtype=torch.complex128, workspace_tensor=ws).cpu().numpy()
+    # HBM bytes the method must move: the 16 XOR diagonals (16 x 2^N elements)
+    # of every line group the list touches, read once, plus the coefficients.
+    flips = np.bitwise_xor(ns & 0x55555555, (ns >> 1) & 0x55555555)
+    x = np.zeros_like(ns)
+    for t in range(N):
+        x |= ((flips >> (2 * t)) & 1) << t
+    groups = len(np.unique(x >> 4)) if N >= 4 else 1
+    width = 16 if N >= 4 else 1 << N
+    alg_bytes = groups * width * (1 << N) * 8 + L * 8
+    achieved = alg_bytes / (ms / 1e3) / 1e9
+    line = {"metric": "Pauli string coefficients/sec, list of %d strings at N=%d" % (L, N),
+            "value": L / (ms / 1e3), "unit": "strings/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "coefficients of %d Pauli strings (uniform sample without replacement, "
+                                   "seed %d) of one %dx%d complex64 Hermitian matrix (seed %d), binary64 sums, "
+                                   "host list, one pauli_coeffs_at call per step"
+                                   % (L, workloads.SEED_SAMPLE, 1 << N, 1 << N, workloads.SEED_N14),
+                       "N": N, "strings": L, "line_groups": groups},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(STRINGS_TRAFFIC_FILE, STRINGS_SOURCES)
+                         if (N, L) == (14, 65536) else None,
+                         "note": "whole call (plan copy, strings_kernel, strings_finish) on the stream, "
+                                 "so a lower bound on the kernel's own rate"}}
+    if not a.no_cpu:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        ref = oracle.coeffs_at(G.astype(np.complex128), ns, threads=cores)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": L / dt, "unit": "strings/s", "cores": cores, "kind": "oracle",
+                                "sample": "the same %d strings, binary64 Gray-code oracle, %d threads over "
+                                          "disjoint ranges, %.1f s" % (L, cores, dt)}
+        line["max_err_vs_oracle"] = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["n14", "batch", "backward"], default="n14")
+    ap.add_argument("--workload", choices=["n14", "batch", "backward", "strings"], default="n14")
+    ap.add_argument("--strings", type=int, default=65536, help="list length of the strings workload")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--N", type=int, default=14)
@@ -197,10 +256,20 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.copy_probe_gib > 0:
+        # a device copy of known size, the calibration for HBM byte counters
+        nb = int(a.copy_probe_gib * (1 << 30))
+        src = torch.empty(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if a.workload == "batch":
         return bench_batch(a)
     if a.workload == "backward":
         return bench_backward(a)
+    if a.workload == "strings":
+        return bench_strings(a)
     N = a.N
     log("[bench] generating N=%d Hermitian complex64 input (seed %d)" % (N, workloads.SEED_N14))
     t0 = time.perf_counter()
@@ -223,14 +292,6 @@ def main():
         st = st or lib.pauli_contract(N, 1, 0, out.data_ptr(), ctypes.byref(o))
         if st != 0:
             raise RuntimeError(pauli.last_error())
-
-    if a.copy_probe_gib > 0:
-        nb = int(a.copy_probe_gib * (1 << 30))
-        src = torch.empty(nb, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     for _ in range(a.warmup):
         step()
