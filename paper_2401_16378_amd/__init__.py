@@ -150,6 +150,14 @@ def workspace(algo: str, N: int, batch: int, device) -> torch.Tensor:
     return ws
 
 
+def release_workspace(device=None) -> None:
+    """Drop the cached scratch buffer of `device` (all devices if None)."""
+    if device is None:
+        _scratch.clear()
+    else:
+        _scratch.pop(torch.device(device), None)
+
+
 def _stream(t: torch.Tensor):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
@@ -318,5 +326,5 @@ def tile_selected(N: int, algo: str = "split_bf16") -> int:
 from .autograd import PauliDecompose  # noqa: E402
 
 __all__ = ["decompose", "reconstruct", "decompose_backward", "decompose_batched", "coeffs_at", "autotune",
-           "autotune_batched", "workspace", "tile_valid", "batched_tile_valid", "tile_count", "tile_selected",
+           "autotune_batched", "workspace", "release_workspace", "tile_valid", "batched_tile_valid", "tile_count", "tile_selected",
            "PauliDecompose", "PauliError", "load_library", "last_error", "ALGOS", "EXPORTS"]

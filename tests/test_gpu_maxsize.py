@@ -1,0 +1,85 @@
+"""Largest order the library accepts, N = 16 (65536 x 65536, 2^32
+coefficients, 32 GiB per complex64 operand): every offset into G, the packed
+operand and the output passes 2^32 here.
+
+G = A (x) B for two seeded 256 x 256 matrices with small integer parts, so
+G is exact in complex64, c(G)_n = c(A)_{n >> 16} c(B)_{n & 0xFFFF} exactly
+(the oracle's Kronecker pin), and every path computes these dyadic values
+without rounding: split-bf16 (the integers sit on the hi grid, FP32 sums
+stay below 2^24), binary32, and the binary64 string list.  Sampled outputs
+are therefore compared for equality.  Needs about 150 GiB of device memory.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+N = 16
+
+
+def small_int_matrix(seed):
+    rng = np.random.default_rng(seed)
+    re = rng.integers(-2, 3, (256, 256))
+    im = rng.integers(-2, 3, (256, 256))
+    return (re + 1j * im).astype(np.complex64)
+
+
+@pytest.fixture(scope="module")
+def kron_case():
+    import paper_2401_16378_amd as p
+    p.load_library()
+    A, B = small_int_matrix(16001), small_int_matrix(16002)
+    cA, cB = oracle.decompose(A), oracle.decompose(B)
+    rng = np.random.default_rng(16003)
+    ns = rng.integers(0, 4 ** N, 65536, dtype=np.uint64)
+    ns[:4] = [0, 4 ** N - 1, 4 ** 8 - 1, (4 ** N - 1) ^ 0x5555]
+    ref = cA[(ns >> 16).astype(np.int64)] * cB[(ns & 0xFFFF).astype(np.int64)]
+    print("N=16 case: building G = A (x) B on the device", flush=True)
+    G = torch.kron(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+    assert G.shape == (1 << N, 1 << N) and G.dtype == torch.complex64
+    yield p, G, ns, ref
+    del G
+    p.release_workspace()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+def test_n16_decompose_exact(kron_case, algo):
+    p, G, ns, ref = kron_case
+    print("N=16 decompose", algo, flush=True)
+    c = p.decompose(G, algo=algo)
+    assert c.shape == (4 ** N,)
+    got = c[torch.from_numpy(ns.astype(np.int64)).cuda()].cpu().numpy()
+    assert np.array_equal(got, ref.astype(np.complex64)), np.abs(got - ref).max()
+    del c
+    p.release_workspace()
+
+
+def test_n16_coeffs_at_exact(kron_case):
+    p, G, ns, ref = kron_case
+    print("N=16 coeffs_at", flush=True)
+    got = p.coeffs_at(G, ns.astype(np.uint32), out_dtype=torch.complex128).cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+def test_n16_reconstruct(kron_case):
+    """The adjoint at full size: reconstruct from the exact coefficients and
+    compare sampled entries of G (mid/lo planes carry the low bits, so this
+    one is checked to the split-bf16 tolerance, not bit for bit)."""
+    p, G, ns, ref = kron_case
+    print("N=16 reconstruct", flush=True)
+    c = p.decompose(G, algo="split_bf16")
+    G2 = p.reconstruct(c, algo="split_bf16")
+    del c
+    rng = np.random.default_rng(16004)
+    rows = torch.from_numpy(rng.integers(0, 1 << N, 4096)).cuda()
+    cols = torch.from_numpy(rng.integers(0, 1 << N, 4096)).cuda()
+    a, b = G[rows, cols], G2[rows, cols]
+    err = ((a - b).abs().max() / G.abs().max()).item()
+    assert err <= 1e-6, err
+    assert torch.equal(G2[0, :64], G[0, :64]) or ((G2[0, :64] - G[0, :64]).abs().max() / G.abs().max()).item() <= 1e-6
+    del G2
+    p.release_workspace()
