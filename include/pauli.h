@@ -67,7 +67,15 @@ typedef enum pauli_algo {
     /* Each binary32 input component split exactly into three bfloat16 parts
      * (hi, mid, lo); bf16 MFMA with two FP32 accumulators (hi; mid+lo),
      * recombined in binary64 before the phase and 2^-N scaling. */
-    PAULI_ALGO_SPLIT_BF16 = 2
+    PAULI_ALGO_SPLIT_BF16 = 2,
+    /* Not the paper's O(8^N) evaluation: for every flip mask the coefficients
+     * are a Sylvester-Hadamard transform of the gathered XOR diagonal
+     * (section 2, Eq. (c_def_in_terms_of_fn)), done by fast Walsh-Hadamard
+     * butterflies in O(N 4^N), binary64 throughout: two passes over HBM
+     * through a workspace of 16 bytes per matrix element.  Forward only
+     * (pauli_decompose); 9 <= N <= 14, other N and the adjoint entry points
+     * return PAULI_EUNSUPPORTED. */
+    PAULI_ALGO_FWHT = 3
 } pauli_algo;
 
 typedef struct pauli_opts {

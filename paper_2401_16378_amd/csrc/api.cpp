@@ -47,8 +47,11 @@ size_t elem_bytes(int dtype) { return dtype == PAULI_C128 ? 16 : 8; }
 
 bool valid_dtype(int d) { return d == PAULI_C64 || d == PAULI_C128; }
 bool valid_algo(int a) {
-    return a == PAULI_ALGO_FP64_GRAY || a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16;
+    return a == PAULI_ALGO_FP64_GRAY || a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16 || a == PAULI_ALGO_FWHT;
 }
+
+// Matrix-core algorithms (packed operand, tile shapes, separate passes).
+bool is_mfma(int a) { return a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16; }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     const char* pa = (const char*)a;
@@ -84,7 +87,7 @@ void load_tune_cache_locked() {
 int planes_of(int algo) { return algo == PAULI_ALGO_SPLIT_BF16 ? 3 : 1; }
 
 int pick_tile(int algo, int N, int forced) {
-    if (algo == PAULI_ALGO_FP64_GRAY) return 0;
+    if (!is_mfma(algo)) return 0;
     const int planes = planes_of(algo);
     if (forced > 0) return forced;
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -108,6 +111,9 @@ int check_common(const void* in, int N, int batch, const void* out, const pauli_
     if (overlaps(in, count * elem_bytes(o.in_dtype), out, count * elem_bytes(o.out_dtype)))
         return fail(PAULI_EINVAL, "%s: input and output overlap", fn);
     if (o.tile < 0) return fail(PAULI_EINVAL, "%s: tile=%d must be >= 0", fn, o.tile);
+    if (o.algo == PAULI_ALGO_FWHT && !fwht_supported(N))
+        return fail(PAULI_EUNSUPPORTED, "%s: the FWHT algorithm covers %d <= N <= %d, not N=%d", fn, FWHT_N_MIN,
+                    FWHT_N_MAX, N);
     if (o.workspace && o.algo != PAULI_ALGO_FP64_GRAY) {
         if ((uintptr_t)o.workspace % 256)
             return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
@@ -115,8 +121,7 @@ int check_common(const void* in, int N, int batch, const void* out, const pauli_
             overlaps(o.workspace, o.workspace_bytes, out, count * elem_bytes(o.out_dtype)))
             return fail(PAULI_EINVAL, "%s: workspace overlaps input or output", fn);
     }
-    if (o.tile > 0 && o.algo != PAULI_ALGO_FP64_GRAY &&
-        !mfma_tile_valid(planes_of(o.algo), o.tile, N))
+    if (o.tile > 0 && is_mfma(o.algo) && !mfma_tile_valid(planes_of(o.algo), o.tile, N))
         return fail(PAULI_EINVAL, "%s: tile %d not valid for algo %d at N=%d", fn, o.tile, o.algo, N);
     return PAULI_OK;
 }
@@ -158,6 +163,24 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
     const bool in128 = o.in_dtype == PAULI_C128, out128 = o.out_dtype == PAULI_C128;
     if (o.algo == PAULI_ALGO_FP64_GRAY) {
         e = launch_gray(dir, in, in128, out, out128, N, batch, scale, s);
+    } else if (o.algo == PAULI_ALGO_FWHT) {
+        if (dir != FORWARD)
+            return fail(PAULI_EUNSUPPORTED, "%s: the FWHT algorithm has no adjoint in this build", fn);
+        const size_t need = fwht_workspace_bytes(N, batch);
+        void* ws = o.workspace;
+        if (ws) {
+            if (o.workspace_bytes < need)
+                return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
+                            o.workspace_bytes);
+            e = launch_fwht(in, in128, out, out128, N, batch, ws, s);
+        } else {
+            hipMemPool_t pool;
+            if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
+            if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
+            e = launch_fwht(in, in128, out, out128, N, batch, ws, s);
+            const hipError_t ef = hipFreeAsync(ws, s);
+            if (e == hipSuccess) e = ef;
+        }
     } else {
         const int planes = planes_of(o.algo);
         const int tile = pick_tile(o.algo, N, o.tile);
@@ -278,17 +301,19 @@ int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts
 size_t pauli_workspace_bytes(int algo, int N, int batch) {
     if (!valid_algo(algo) || N < 0 || N > N_MAX || batch < 1) return 0;
     if (algo == PAULI_ALGO_FP64_GRAY) return 0;
+    if (algo == PAULI_ALGO_FWHT) return fwht_supported(N) ? fwht_workspace_bytes(N, batch) : 0;
     return mfma_workspace_bytes(planes_of(algo), N, batch);
 }
 
 int pauli_tile_count(int algo) {
-    if (algo == PAULI_ALGO_FP64_GRAY) return 1;
+    if (algo == PAULI_ALGO_FP64_GRAY || algo == PAULI_ALGO_FWHT) return 1;
     if (!valid_algo(algo)) return 0;
     return mfma_tile_count(planes_of(algo));
 }
 
 int pauli_tile_valid(int algo, int tile, int N) {
     if (algo == PAULI_ALGO_FP64_GRAY) return tile == 1 && N >= 0 && N <= N_MAX ? 1 : 0;
+    if (algo == PAULI_ALGO_FWHT) return tile == 1 && fwht_supported(N) ? 1 : 0;
     if (!valid_algo(algo) || N < 0 || N > N_MAX) return 0;
     return mfma_tile_valid(planes_of(algo), tile, N) ? 1 : 0;
 }

@@ -71,4 +71,12 @@ hipError_t launch_strings(const void* G, bool in_c128, int N, const StringChunk*
                           const StringEntry* entries, int count, int parts, double2* partial, void* out,
                           bool out_c128, hipStream_t stream);
 
+// All coefficients by two fast Walsh-Hadamard passes through a binary64
+// intermediate of fwht_workspace_bytes(N, batch) bytes (16 per element).
+constexpr int FWHT_N_MIN = 9, FWHT_N_MAX = 14;
+bool fwht_supported(int N);
+size_t fwht_workspace_bytes(int N, int batch);
+hipError_t launch_fwht(const void* G, bool in_c128, void* out, bool out_c128, int N, int batch, void* ws,
+                       hipStream_t stream);
+
 }  // namespace pauli

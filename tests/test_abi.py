@@ -193,3 +193,19 @@ def test_coeffs_at_validation(lib, pauli):
     assert lib.pauli_coeffs_at_workspace_bytes(14, 1) >= 16 * 128     # a single string split 128 ways
     big = lib.pauli_coeffs_at_workspace_bytes(14, 1 << 20)
     assert 24 * (1 << 20) <= big <= 24 * (1 << 20) + 16 * (2048 * 256 + (1 << 20)) + 1024
+
+
+def test_fwht_algo_queries(lib, pauli):
+    assert pauli.ALGOS["fwht"] == 3
+    assert lib.pauli_workspace_bytes(3, 14, 1) == 16 * 4 ** 14
+    assert lib.pauli_workspace_bytes(3, 14, 2) == 2 * 16 * 4 ** 14
+    assert lib.pauli_workspace_bytes(3, 8, 1) == 0 and lib.pauli_workspace_bytes(3, 15, 1) == 0
+    assert lib.pauli_tile_count(3) == 1
+    assert lib.pauli_tile_valid(3, 1, 9) == 1 and lib.pauli_tile_valid(3, 1, 8) == 0
+    o = opts(pauli, algo="fwht")
+    assert lib.pauli_decompose(FAKE_IN, 8, 1, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
+    assert lib.pauli_decompose(FAKE_IN, 15, 1, FAKE_IN + (1 << 40), ctypes.byref(o)) == EUNSUPPORTED
+    small = opts(pauli, algo="fwht", ws=0x30000000, ws_bytes=1024)
+    assert lib.pauli_decompose(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
+    assert lib.pauli_pack(FAKE_IN, 10, 1, 0, ctypes.byref(o)) == EUNSUPPORTED
+    assert lib.pauli_autotune(9, 10, ctypes.byref(o)) == EUNSUPPORTED
