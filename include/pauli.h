@@ -72,8 +72,8 @@ typedef enum pauli_algo {
      * are a Sylvester-Hadamard transform of the gathered XOR diagonal
      * (section 2, Eq. (c_def_in_terms_of_fn)), done by fast Walsh-Hadamard
      * butterflies in O(N 4^N), binary64 throughout: two passes over HBM
-     * through a workspace of 16 bytes per matrix element.  Forward only
-     * (pauli_decompose); 9 <= N <= 14, other N and the adjoint entry points
+     * through a workspace of 16 bytes per matrix element.  All three
+     * directions (decompose, reconstruct, backward); 9 <= N <= 14, other N
      * return PAULI_EUNSUPPORTED. */
     PAULI_ALGO_FWHT = 3
 } pauli_algo;

@@ -164,20 +164,18 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
     if (o.algo == PAULI_ALGO_FP64_GRAY) {
         e = launch_gray(dir, in, in128, out, out128, N, batch, scale, s);
     } else if (o.algo == PAULI_ALGO_FWHT) {
-        if (dir != FORWARD)
-            return fail(PAULI_EUNSUPPORTED, "%s: the FWHT algorithm has no adjoint in this build", fn);
         const size_t need = fwht_workspace_bytes(N, batch);
         void* ws = o.workspace;
         if (ws) {
             if (o.workspace_bytes < need)
                 return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
                             o.workspace_bytes);
-            e = launch_fwht(in, in128, out, out128, N, batch, ws, s);
+            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, ws, s);
         } else {
             hipMemPool_t pool;
             if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
             if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
-            e = launch_fwht(in, in128, out, out128, N, batch, ws, s);
+            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, ws, s);
             const hipError_t ef = hipFreeAsync(ws, s);
             if (e == hipSuccess) e = ef;
         }

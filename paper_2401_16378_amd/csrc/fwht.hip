@@ -8,26 +8,32 @@
 // With i = 32 i_h + i_l and z = 32 z_h + z_l the sign (-1)^{popc(i&z)}
 // factors into (-1)^{popc(i_l&z_l)} (-1)^{popc(i_h&z_h)}, so the transform
 // splits into two HBM passes through a binary64 intermediate
-//   U[x][z_l][i_h] = sum_{i_l} (-1)^{popc(i_l&z_l)} G[(32 i_h + i_l)^x][32 i_h + i_l]
-//   c(x, 32 z_h + z_l) = 2^-N (-i)^{popc(x&z)} sum_{i_h} (-1)^{popc(i_h&z_h)} U[x][z_l][i_h]
-// (U holds 4^N complex binary64 values, 16 bytes each, in the workspace).
+//   U(x, z_l, i_h) = sum_{i_l} (-1)^{popc(i_l&z_l)} G[(32 i_h + i_l)^x][32 i_h + i_l]
+//   c(x, 32 z_h + z_l) = 2^-N (-i)^{popc(x&z)} sum_{i_h} (-1)^{popc(i_h&z_h)} U(x, z_l, i_h)
+// (U holds 4^N complex binary64 values, 16 bytes each, in the workspace,
+// stored as U[x][i_h / 8][z_l][i_h % 8] so that both passes move long
+// contiguous runs).
 //
-// Pass 1: a workgroup owns 32 flip masks x0..x0+31 and 8 consecutive i_h.
+// Pass 1: a workgroup owns 32 flip masks x0..x0+31 and 8 consecutive i_h,
+// whose eight tiles it requests together (four at a time for complex128).
 // For each i_h the 32 x 32 block of G at rows (32 i_h ^ x0) .. +31, columns
 // 32 i_h .. +31 holds exactly the 32 diagonals' entries for those i (entry
 // (r, c) belongs to x_l = r ^ c, i_l = c), so it is loaded whole, widened to
 // binary64 in LDS, and read back transposed: thread t takes x_l = t >> 3 and
 // i_l = 4 (t & 7) + k, k < 4.  The 32-point butterflies run over k inside the
-// thread and over lanes t ^ 1, t ^ 2, t ^ 4 (i_l bits 2..4).  The 8 values
-// of each (x, z_l) for the workgroup's 8 i_h are one 128-byte run of U.
+// thread and over lanes t ^ 1, t ^ 2, t ^ 4 (i_l bits 2..4).  The workgroup's
+// results for one flip mask (32 z_l x 8 i_h) are one contiguous 4 KiB block
+// of U.
 //
-// Pass 2: a workgroup owns 16 vectors U[x][z_l][.] -- 4 flip masks x_l =
+// Pass 2: a workgroup owns 16 vectors U(x, z_l, .) -- 4 flip masks x_l =
 // 4a..4a+3 and 4 phase values z_l = 4b..4b+3 of one 32-mask block -- with
-// 16 threads per vector holding i_h = q + 16 k.  Butterflies run over k in
-// the thread and over lanes q ^ 1, 2, 4, 8.  For each z_h the 16 results are
+// TPV (up to 64) threads per vector holding i_h = q + TPV k.  Butterflies run
+// over k in the thread and over lanes q ^ 1, 2, ..., TPV / 2.  For each z_h the 16 results are
 // the 16 consecutive coefficients n with fixed high bits (n's low four bits
 // are (x^z)_0, z_0, (x^z)_1, z_1), so they are staged in LDS and stored as one
 // contiguous 128-byte (complex64) or 256-byte (complex128) run.
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -35,6 +41,7 @@ namespace pauli {
 namespace {
 
 constexpr int HB = 8;                   // i_h values per pass-1 workgroup
+
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
@@ -64,11 +71,13 @@ __device__ inline double2 load_g(const void* G, size_t idx) {
 
 template <bool IN128>
 __global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall, double2* __restrict__ Uall, int N) {
+    using InT = typename std::conditional<IN128, double2, float2>::type;
+    constexpr int PF = IN128 ? 4 : 8;    // tiles whose loads are issued together (32 or 64 KiB per workgroup)
     __shared__ double2 tile[32 * 33];    // [row][column], padded row
     const uint32_t D = 1u << N, M = D >> 5;
-    const uint32_t x0 = blockIdx.x * 32u, h0 = blockIdx.y * HB;
+    const uint32_t x0 = blockIdx.y * 32u, h0 = blockIdx.x * HB;
     const size_t mat = (size_t)D * D;
-    const unsigned char* G = (const unsigned char*)Gall + (size_t)blockIdx.z * mat * (IN128 ? 16 : 8);
+    const InT* G = (const InT*)Gall + (size_t)blockIdx.z * mat;
     double2* U = Uall + (size_t)blockIdx.z * mat;
     const int t = threadIdx.x, lane = t & 63;
     const int lr = t >> 3, lc = (t & 7) * 4;       // load: row, first column of 4
@@ -76,73 +85,88 @@ __global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall,
 
     double2 acc[4][HB];
 #pragma unroll
-    for (int h = 0; h < HB; ++h) {
-        const uint32_t ih = h0 + h;
-        const uint32_t row = ((ih << 5) ^ x0) + lr, col = (ih << 5) + lc;
-        double2 g[4];
+    for (int h1 = 0; h1 < HB; h1 += PF) {
+        InT g[PF][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) g[k] = load_g<IN128>(G, (size_t)row * D + col + k);
-        if (h > 0) __syncthreads();              // previous tile fully read
+        for (int h = 0; h < PF; ++h) {
+            const uint32_t ih = h0 + h1 + h;
+            const uint32_t row = ((ih << 5) ^ x0) + lr, col = (ih << 5) + lc;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) tile[lr * 33 + lc + k] = g[k];
-        __syncthreads();
-        double2 v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int il = il0 + k;
-            v[k] = tile[(il ^ xl) * 33 + il];
+            for (int k = 0; k < 4; ++k) {
+                const InT e = G[(size_t)row * D + col + k];
+                g[h][k].x = e.x;
+                g[h][k].y = e.y;
+            }
         }
-        // i_l bits 0 and 1: inside the thread
-        {
-            const double2 a0 = add2(v[0], v[1]), a1 = sub2(v[0], v[1]);
-            const double2 a2 = add2(v[2], v[3]), a3 = sub2(v[2], v[3]);
-            v[0] = add2(a0, a2);
-            v[2] = sub2(a0, a2);
-            v[1] = add2(a1, a3);
-            v[3] = sub2(a1, a3);
+#pragma unroll
+        for (int h = 0; h < PF; ++h) {
+            if (h1 + h > 0) __syncthreads();     // previous tile fully read
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tile[lr * 33 + lc + k] = make_double2((double)g[h][k].x, (double)g[h][k].y);
+            __syncthreads();
+            double2 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int il = il0 + k;
+                v[k] = tile[(il ^ xl) * 33 + il];
+            }
+            // i_l bits 0 and 1: inside the thread
+            {
+                const double2 a0 = add2(v[0], v[1]), a1 = sub2(v[0], v[1]);
+                const double2 a2 = add2(v[2], v[3]), a3 = sub2(v[2], v[3]);
+                v[0] = add2(a0, a2);
+                v[2] = sub2(a0, a2);
+                v[1] = add2(a1, a3);
+                v[3] = sub2(a1, a3);
+            }
+            // i_l bits 2, 3, 4: lanes t ^ 1, t ^ 2, t ^ 4
+#pragma unroll
+            for (int m = 1; m <= 4; m <<= 1)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = lane_butterfly(v[k], lane, m);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k][h1 + h] = v[k];
         }
-        // i_l bits 2, 3, 4: lanes t ^ 1, t ^ 2, t ^ 4
-#pragma unroll
-        for (int m = 1; m <= 4; m <<= 1)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = lane_butterfly(v[k], lane, m);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k][h] = v[k];
     }
-    // U[x][z_l][h0 .. h0 + 7]: one contiguous 128-byte run per (x, z_l)
+    // U block (x, i_h / 8): [z_l][i_h % 8], 4 KiB contiguous per flip mask
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t zl = il0 + k;
-        double2* dst = U + ((size_t)(x0 + xl) * 32u + zl) * M + h0;
+        double2* dst = U + (((size_t)(x0 + xl) * (M / HB) + blockIdx.x) * 32u + zl) * HB;
 #pragma unroll
         for (int h = 0; h < HB; ++h) dst[h] = acc[k][h];
     }
 }
 
-// EPT = M / 16 elements per thread (M = 2^(N-5) values of i_h per vector).
-template <int EPT, bool OUT128>
-__global__ __launch_bounds__(256) void fwht_pass2(const double2* __restrict__ Uall, void* __restrict__ outall, int N,
-                                                  double scale) {
+// TPV threads per vector (16, 32 or 64), EPT = M / TPV elements per thread
+// (M = 2^(N-5) values of i_h per vector); the workgroup has 16 TPV threads.
+template <int TPV, int EPT, bool OUT128>
+__global__ __launch_bounds__(16 * TPV) void fwht_pass2(const double2* __restrict__ Uall, void* __restrict__ outall,
+                                                       int N, double scale) {
     extern __shared__ __attribute__((aligned(16))) unsigned char stage[];   // [z_h][16] coefficients
-    constexpr uint32_t M = 16u * EPT;
+    constexpr uint32_t M = (uint32_t)TPV * EPT;
     constexpr int ESZ = OUT128 ? 16 : 8;
+    constexpr uint32_t NT = 16u * TPV;
     const uint32_t D = 1u << N;
     const size_t mat = (size_t)D * D;
-    const uint32_t x0 = blockIdx.x * 32u;
-    const uint32_t a = blockIdx.y & 7u, b = blockIdx.y >> 3;      // x_l quad, z_l quad
+    const uint32_t x0 = blockIdx.y * 32u;
+    const uint32_t a = blockIdx.x & 7u, b = blockIdx.x >> 3;      // x_l quad, z_l quad
     const double2* U = Uall + (size_t)blockIdx.z * mat;
     unsigned char* out = (unsigned char*)outall + (size_t)blockIdx.z * mat * ESZ;
     const int t = threadIdx.x, lane = t & 63;
-    const int vec = t >> 4, q = t & 15;
+    const int vec = t / TPV, q = t % TPV;
     const uint32_t xl = 4u * a + (uint32_t)(vec & 3), zl = 4u * b + (uint32_t)(vec >> 2);
     const uint32_t x = x0 + xl;
 
     double2 v[EPT];
-    const double2* src = U + ((size_t)x * 32u + zl) * M + q;
+    const double2* src = U + (size_t)x * 32u * M + zl * HB;
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) v[k] = src[16 * k];
+    for (int k = 0; k < EPT; ++k) {
+        const uint32_t ih = (uint32_t)q + (uint32_t)TPV * k;
+        v[k] = src[(size_t)(ih / HB) * 32u * HB + ih % HB];
+    }
 
-    // i_h bits 4 .. log2(M)-1: over k inside the thread
+    // high i_h bits: over k inside the thread
 #pragma unroll
     for (int s = 1; s < EPT; s <<= 1)
 #pragma unroll
@@ -152,9 +176,9 @@ __global__ __launch_bounds__(256) void fwht_pass2(const double2* __restrict__ Ua
                 v[k] = add2(p, r);
                 v[k + s] = sub2(p, r);
             }
-    // i_h bits 0 .. 3: lanes q ^ 1, 2, 4, 8
+    // low i_h bits: lanes q ^ 1, 2, ..., TPV / 2 (a vector's threads are consecutive lanes of one wave)
 #pragma unroll
-    for (int m = 1; m <= 8; m <<= 1)
+    for (int m = 1; m < TPV; m <<= 1)
 #pragma unroll
         for (int k = 0; k < EPT; ++k) v[k] = lane_butterfly(v[k], lane, m);
 
@@ -162,7 +186,7 @@ __global__ __launch_bounds__(256) void fwht_pass2(const double2* __restrict__ Ua
     const uint32_t slot = ((xl ^ zl) & 1u) | ((zl & 1u) << 1) | (((xl ^ zl) & 2u) << 1) | ((zl & 2u) << 2);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const uint32_t zh = (uint32_t)q + 16u * k;
+        const uint32_t zh = (uint32_t)q + (uint32_t)TPV * k;
         const uint32_t z = (zh << 5) + zl;
         double re = v[k].x * scale, im = v[k].y * scale;
         rotate_minus_i(re, im, (uint32_t)__popc(x & z));
@@ -174,30 +198,179 @@ __global__ __launch_bounds__(256) void fwht_pass2(const double2* __restrict__ Ua
     // M runs of 16 coefficients (16 * ESZ bytes each), 16-byte stores
     constexpr uint32_t CH = (16u * ESZ) / 16u;    // 16-byte chunks per run
     const uint32_t xb4 = x0 + 4u * a, zb4 = 4u * b;
-    for (uint32_t j = (uint32_t)t; j < M * CH; j += 256u) {
+    for (uint32_t j = (uint32_t)t; j < M * CH; j += NT) {
         const uint32_t zh = j / CH, part = j % CH;
         const uint32_t base = pauli_index(xb4, (zh << 5) + zb4);   // low four bits are zero
         *(u32x4_t*)(out + (size_t)base * ESZ + part * 16u) = *(const u32x4_t*)(stage + ((size_t)zh * CH + part) * 16u);
     }
 }
 
-template <int EPT>
-hipError_t launch_pass2(const double2* U, void* out, bool out128, int N, int batch, hipStream_t s) {
+// ---- adjoint: G[i^x][i] = scale sum_z i^{popc(x&z)} (-1)^{popc(i&z)} c(x, z) ----
+// Pass A mirrors pass 2: the 16 coefficient runs of a workgroup's vectors are
+// read into LDS, phased by i^{popc(x&z)}, transformed over z_h (H is
+// symmetric, so the same butterflies map z_h to i_h) and stored as
+// W(x, z_l, i_h) in U's blocked layout.
+template <int TPV, int EPT, bool IN128>
+__global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ inall, double2* __restrict__ Wall,
+                                                       int N) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char stage[];   // [z_h][16] coefficients
+    constexpr uint32_t M = (uint32_t)TPV * EPT;
+    constexpr int ESZ = IN128 ? 16 : 8;
+    constexpr uint32_t NT = 16u * TPV;
     const uint32_t D = 1u << N;
-    const dim3 grid(D / 32u, 64u, (uint32_t)batch);
-    const size_t lds = (size_t)16u * EPT * 16u * (out128 ? 16u : 8u);
-    const double scale = 1.0 / (double)D;
+    const size_t mat = (size_t)D * D;
+    const uint32_t x0 = blockIdx.y * 32u;
+    const uint32_t a = blockIdx.x & 7u, b = blockIdx.x >> 3;
+    const unsigned char* in = (const unsigned char*)inall + (size_t)blockIdx.z * mat * ESZ;
+    double2* W = Wall + (size_t)blockIdx.z * mat;
+    const int t = threadIdx.x, lane = t & 63;
+    const int vec = t / TPV, q = t % TPV;
+    const uint32_t xl = 4u * a + (uint32_t)(vec & 3), zl = 4u * b + (uint32_t)(vec >> 2);
+    const uint32_t x = x0 + xl;
+
+    constexpr uint32_t CH = (16u * ESZ) / 16u;
+    const uint32_t xb4 = x0 + 4u * a, zb4 = 4u * b;
+    for (uint32_t j = (uint32_t)t; j < M * CH; j += NT) {
+        const uint32_t zh = j / CH, part = j % CH;
+        const uint32_t base = pauli_index(xb4, (zh << 5) + zb4);
+        *(u32x4_t*)(stage + ((size_t)zh * CH + part) * 16u) = *(const u32x4_t*)(in + (size_t)base * ESZ + part * 16u);
+    }
+    __syncthreads();
+    const uint32_t slot = ((xl ^ zl) & 1u) | ((zl & 1u) << 1) | (((xl ^ zl) & 2u) << 1) | ((zl & 2u) << 2);
+    double2 v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const uint32_t zh = (uint32_t)q + (uint32_t)TPV * k;
+        const uint32_t z = (zh << 5) + zl;
+        const unsigned char* src = stage + ((size_t)zh * 16u + slot) * ESZ;
+        double re, im;
+        if constexpr (IN128) {
+            const double2 c = *(const double2*)src;
+            re = c.x;
+            im = c.y;
+        } else {
+            const float2 c = *(const float2*)src;
+            re = (double)c.x;
+            im = (double)c.y;
+        }
+        rotate_minus_i(re, im, 3u * (uint32_t)__popc(x & z));   // i^{popc(x&z)}
+        v[k] = make_double2(re, im);
+    }
+#pragma unroll
+    for (int s = 1; s < EPT; s <<= 1)
+#pragma unroll
+        for (int k = 0; k < EPT; ++k)
+            if ((k & s) == 0) {
+                const double2 p = v[k], r = v[k + s];
+                v[k] = add2(p, r);
+                v[k + s] = sub2(p, r);
+            }
+#pragma unroll
+    for (int m = 1; m < TPV; m <<= 1)
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) v[k] = lane_butterfly(v[k], lane, m);
+    double2* dst = W + (size_t)x * 32u * M + zl * HB;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const uint32_t ih = (uint32_t)q + (uint32_t)TPV * k;
+        dst[(size_t)(ih / HB) * 32u * HB + ih % HB] = v[k];
+    }
+}
+
+// Pass B mirrors pass 1: for 32 flip masks and 8 consecutive i_h, the
+// 32-point transforms over z_l give the diagonal entries y(x, 32 i_h + i_l),
+// which an LDS tile turns back into the 32 x 32 block of G at rows
+// (32 i_h ^ x0) .. +31, columns 32 i_h .. +31 (entry (r, c) holds x_l = r ^ c,
+// i_l = c), written row by row.
+template <bool OUT128>
+__global__ __launch_bounds__(256) void fwht_adj_b(const double2* __restrict__ Wall, void* __restrict__ Gall, int N,
+                                                  double scale) {
+    __shared__ double2 tile[32 * 33];
+    const uint32_t D = 1u << N, M = D >> 5;
+    const uint32_t x0 = blockIdx.y * 32u, h0 = blockIdx.x * HB;
+    const size_t mat = (size_t)D * D;
+    const double2* W = Wall + (size_t)blockIdx.z * mat;
+    unsigned char* G = (unsigned char*)Gall + (size_t)blockIdx.z * mat * (OUT128 ? 16 : 8);
+    const int t = threadIdx.x, lane = t & 63;
+    const int xl = t >> 3, zl0 = (t & 7) * 4;      // transform: flip mask, first z_l of 4
+    const int lr = t >> 3, lc = (t & 7) * 4;       // store: row, first column of 4
+
+    double2 w[4][HB];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2* src = W + (((size_t)(x0 + xl) * (M / HB) + blockIdx.x) * 32u + zl0 + k) * HB;
+#pragma unroll
+        for (int h = 0; h < HB; ++h) w[k][h] = src[h];
+    }
+#pragma unroll
+    for (int h = 0; h < HB; ++h) {
+        double2 v[4] = {w[0][h], w[1][h], w[2][h], w[3][h]};
+        {
+            const double2 a0 = add2(v[0], v[1]), a1 = sub2(v[0], v[1]);
+            const double2 a2 = add2(v[2], v[3]), a3 = sub2(v[2], v[3]);
+            v[0] = add2(a0, a2);
+            v[2] = sub2(a0, a2);
+            v[1] = add2(a1, a3);
+            v[3] = sub2(a1, a3);
+        }
+#pragma unroll
+        for (int m = 1; m <= 4; m <<= 1)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = lane_butterfly(v[k], lane, m);
+        if (h > 0) __syncthreads();              // previous tile fully written out
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int il = zl0 + k;
+            tile[(il ^ xl) * 33 + il] = make_double2(v[k].x * scale, v[k].y * scale);
+        }
+        __syncthreads();
+        const uint32_t ih = h0 + h;
+        const uint32_t row = ((ih << 5) ^ x0) + lr, col = (ih << 5) + lc;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double2 g = tile[lr * 33 + lc + k];
+            if constexpr (OUT128) ((double2*)G)[(size_t)row * D + col + k] = g;
+            else ((float2*)G)[(size_t)row * D + col + k] = make_float2((float)g.x, (float)g.y);
+        }
+    }
+}
+
+template <int TPV, int EPT>
+hipError_t launch_adj_a(const void* in, bool in128, double2* W, int N, int batch, uint32_t nxb,
+                        hipStream_t s) {
+    const dim3 grid(64u, nxb, (uint32_t)batch);
+    const size_t lds = (size_t)TPV * EPT * 16u * (in128 ? 16u : 8u);
+    hipError_t e;
+    if (in128) {
+        e = hipFuncSetAttribute((const void*)fwht_adj_a<TPV, EPT, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((fwht_adj_a<TPV, EPT, true>), grid, dim3(16 * TPV), lds, s, in, W, N);
+    } else {
+        e = hipFuncSetAttribute((const void*)fwht_adj_a<TPV, EPT, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((fwht_adj_a<TPV, EPT, false>), grid, dim3(16 * TPV), lds, s, in, W, N);
+    }
+    return hipGetLastError();
+}
+
+template <int TPV, int EPT>
+hipError_t launch_pass2(const double2* U, void* out, bool out128, int N, int batch, double scale, uint32_t nxb,
+                        hipStream_t s) {
+    const dim3 grid(64u, nxb, (uint32_t)batch);   // the 64 quads of a mask block back to back
+    const size_t lds = (size_t)TPV * EPT * 16u * (out128 ? 16u : 8u);
     hipError_t e;
     if (out128) {
-        e = hipFuncSetAttribute((const void*)fwht_pass2<EPT, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
+        e = hipFuncSetAttribute((const void*)fwht_pass2<TPV, EPT, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fwht_pass2<EPT, true>), grid, dim3(256), lds, s, U, out, N, scale);
+        hipLaunchKernelGGL((fwht_pass2<TPV, EPT, true>), grid, dim3(16 * TPV), lds, s, U, out, N, scale);
     } else {
-        e = hipFuncSetAttribute((const void*)fwht_pass2<EPT, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
+        e = hipFuncSetAttribute((const void*)fwht_pass2<TPV, EPT, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fwht_pass2<EPT, false>), grid, dim3(256), lds, s, U, out, N, scale);
+        hipLaunchKernelGGL((fwht_pass2<TPV, EPT, false>), grid, dim3(16 * TPV), lds, s, U, out, N, scale);
     }
     return hipGetLastError();
 }
@@ -210,25 +383,40 @@ size_t fwht_workspace_bytes(int N, int batch) {
     return ((size_t)1 << (2 * N)) * 16u * (size_t)batch;
 }
 
-hipError_t launch_fwht(const void* G, bool in_c128, void* out, bool out_c128, int N, int batch, void* ws,
-                       hipStream_t s) {
+hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N, int batch,
+                       double scale, void* ws, hipStream_t s) {
     if (!fwht_supported(N)) return hipErrorInvalidValue;
-    const uint32_t D = 1u << N, M = D >> 5;
+    const uint32_t D = 1u << N, M = D >> 5, nxb = D / 32u;
     double2* U = (double2*)ws;
-    const dim3 g1(D / 32u, M / HB, (uint32_t)batch);
-    if (in_c128) hipLaunchKernelGGL(fwht_pass1<true>, g1, dim3(256), 0, s, G, U, N);
-    else hipLaunchKernelGGL(fwht_pass1<false>, g1, dim3(256), 0, s, G, U, N);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const dim3 gt(M / HB, nxb, (uint32_t)batch);   // consecutive i_h groups back to back
+    hipError_t e = hipSuccess;
+    if (dir == FORWARD) {
+        if (in_c128) hipLaunchKernelGGL(fwht_pass1<true>, gt, dim3(256), 0, s, in, U, N);
+        else hipLaunchKernelGGL(fwht_pass1<false>, gt, dim3(256), 0, s, in, U, N);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        switch (N) {   // (threads per vector, elements per thread)
+            case 9: return launch_pass2<16, 1>(U, out, out_c128, N, batch, scale, nxb, s);
+            case 10: return launch_pass2<32, 1>(U, out, out_c128, N, batch, scale, nxb, s);
+            case 11: return launch_pass2<32, 2>(U, out, out_c128, N, batch, scale, nxb, s);
+            case 12: return launch_pass2<32, 4>(U, out, out_c128, N, batch, scale, nxb, s);
+            case 13: return launch_pass2<32, 8>(U, out, out_c128, N, batch, scale, nxb, s);
+            case 14: return launch_pass2<32, 16>(U, out, out_c128, N, batch, scale, nxb, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (N) {
-        case 9: return launch_pass2<1>(U, out, out_c128, N, batch, s);
-        case 10: return launch_pass2<2>(U, out, out_c128, N, batch, s);
-        case 11: return launch_pass2<4>(U, out, out_c128, N, batch, s);
-        case 12: return launch_pass2<8>(U, out, out_c128, N, batch, s);
-        case 13: return launch_pass2<16>(U, out, out_c128, N, batch, s);
-        case 14: return launch_pass2<32>(U, out, out_c128, N, batch, s);
+        case 9: e = launch_adj_a<16, 1>(in, in_c128, U, N, batch, nxb, s); break;
+        case 10: e = launch_adj_a<32, 1>(in, in_c128, U, N, batch, nxb, s); break;
+        case 11: e = launch_adj_a<32, 2>(in, in_c128, U, N, batch, nxb, s); break;
+        case 12: e = launch_adj_a<32, 4>(in, in_c128, U, N, batch, nxb, s); break;
+        case 13: e = launch_adj_a<32, 8>(in, in_c128, U, N, batch, nxb, s); break;
+        case 14: e = launch_adj_a<32, 16>(in, in_c128, U, N, batch, nxb, s); break;
         default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
+    if (out_c128) hipLaunchKernelGGL(fwht_adj_b<true>, gt, dim3(256), 0, s, U, out, N, scale);
+    else hipLaunchKernelGGL(fwht_adj_b<false>, gt, dim3(256), 0, s, U, out, N, scale);
+    return hipGetLastError();
 }
 
 }  // namespace pauli

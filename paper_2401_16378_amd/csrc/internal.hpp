@@ -76,7 +76,9 @@ hipError_t launch_strings(const void* G, bool in_c128, int N, const StringChunk*
 constexpr int FWHT_N_MIN = 9, FWHT_N_MAX = 14;
 bool fwht_supported(int N);
 size_t fwht_workspace_bytes(int N, int batch);
-hipError_t launch_fwht(const void* G, bool in_c128, void* out, bool out_c128, int N, int batch, void* ws,
-                       hipStream_t stream);
+// FORWARD: in = matrices, out = coefficients; ADJOINT: in = coefficients,
+// out = matrices.  scale multiplies the result as for launch_gray.
+hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N, int batch,
+                       double scale, void* ws, hipStream_t stream);
 
 }  // namespace pauli

@@ -25,7 +25,7 @@ pytestmark = pytest.mark.gpu
 
 N = 11
 D = 1 << N
-TOL = {"split_bf16": 1e-5, "fp32": 1e-5, "fp64_gray": 1e-10}
+TOL = {"split_bf16": 1e-5, "fp32": 1e-5, "fp64_gray": 1e-10, "fwht": 1e-10}
 
 
 def threads():
@@ -64,7 +64,7 @@ def oracle_gradient(problem):
 def gpu_gradient(problem, algo):
     import paper_2401_16378_amd as pauli
     G, G2, w, (b, rows, cols), ref = problem
-    dt = torch.complex128 if algo == "fp64_gray" else torch.complex64
+    dt = torch.complex128 if algo in ("fp64_gray", "fwht") else torch.complex64   # binary64 algorithms
     Gd = torch.from_numpy(G).to("cuda").to(dt).requires_grad_(True)
     t = pauli.decompose(torch.from_numpy(G2).to("cuda").to(dt), algo=algo).detach()
     c = pauli.PauliDecompose.apply(Gd, algo)
@@ -98,7 +98,7 @@ def test_oracle_gradient_vs_finite_differences(problem):
         assert abs(grad[q] - fd) <= 1e-8 * np.abs(grad).max(), (q, grad[q], fd)
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray"])
+@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray", "fwht"])
 def test_adjoint_gradient_vs_oracle(problem, algo):
     ref = oracle_gradient(problem)
     got = gpu_gradient(problem, algo)

@@ -1,5 +1,6 @@
 """Fast Walsh-Hadamard algorithm (PAULI_ALGO_FWHT): all 4^N coefficients in
-O(N 4^N) through a binary64 intermediate.  It is not the paper's evaluation
+O(N 4^N) through a binary64 intermediate, and its adjoint (reconstruction,
+gradient).  It is not the paper's evaluation
 order, so it is held to the binary64 tolerance against the oracle (1e-12 of
 max|c|), plus the exact one-hots, the Hermitian and Parseval invariants at
 N = 14 and agreement with the binary64 Gray-code kernel."""
@@ -82,6 +83,48 @@ def test_n14_vs_gray_and_invariants():
     assert abs(lhs - rhs) <= 1e-12 * rhs
 
 
+def test_reconstruct_vs_oracle_full_n9():
+    p = lib()
+    N = 9
+    c = workloads.iid_complex(N, 1309, np.complex128).reshape(-1)
+    G = p.reconstruct(torch.from_numpy(c).cuda(), algo="fwht").cpu().numpy()
+    assert rel_err(G, oracle.recompose(c)) <= 1e-12
+
+
+@pytest.mark.parametrize("N", [10, 11, 12])
+def test_reconstruct_vs_oracle_sampled(N):
+    """Full recomposition by the oracle costs 8^N; 1,024 sampled entries
+    (O(2^N) each) stand in at larger N."""
+    p = lib()
+    c = workloads.iid_complex(N, 1300 + N, np.complex128).reshape(-1)
+    G = p.reconstruct(torch.from_numpy(c).cuda(), algo="fwht")
+    rows, cols = workloads.sample_entries(1 << N, 1024, seed=1350 + N)
+    r, q = torch.from_numpy(rows.astype(np.int64)).cuda(), torch.from_numpy(cols.astype(np.int64)).cuda()
+    got = G[r, q].cpu().numpy()
+    ref = oracle.recompose_entries(c, rows, cols)
+    assert rel_err(got, ref) <= 1e-12
+
+
+def test_backward_vs_oracle_entries():
+    p = lib()
+    N = 10
+    g = workloads.iid_complex(N, 1400, np.complex128).reshape(-1)
+    got = p.decompose_backward(torch.from_numpy(g).cuda(), algo="fwht").cpu().numpy()
+    rows, cols = workloads.sample_entries(1 << N, 512, seed=1401)
+    ref = oracle.grad_entries(g, rows, cols)
+    assert rel_err(got[rows.astype(np.int64), cols.astype(np.int64)], ref) <= 1e-12
+
+
+def test_round_trip_n14():
+    """decompose then reconstruct at N = 14 returns G to binary64 rounding."""
+    p = lib()
+    N = 14
+    Gd = torch.from_numpy(workloads.hermitian(N, workloads.SEED_N14)).cuda().to(torch.complex128)
+    c = p.decompose(Gd, algo="fwht")
+    G2 = p.reconstruct(c, algo="fwht")
+    assert ((G2 - Gd).abs().max() / Gd.abs().max()).item() <= 1e-12
+
+
 def test_unsupported_cases():
     p = lib()
     for N in (8, 15):
@@ -90,7 +133,7 @@ def test_unsupported_cases():
             p.decompose(G, algo="fwht")
         assert ei.value.status == 2
         del G
-    c = torch.zeros(4 ** 10, dtype=torch.complex64, device="cuda")
+    c = torch.zeros(4 ** 8, dtype=torch.complex64, device="cuda")
     with pytest.raises(p.PauliError) as ei:
         p.reconstruct(c, algo="fwht")
     assert ei.value.status == 2
