@@ -215,8 +215,22 @@ int pauli_coeffs_at(const void* G, int N, const unsigned int* strings, int count
                     const pauli_opts* opts);
 
 /*
- * Workspace bytes that suffice for pauli_coeffs_at with any list of `count`
- * strings at order N (the plan plus, for short lists whose columns are split
+ * Adjoint of pauli_coeffs_at, for reverse-mode differentiation: given
+ * grad_c[k] = dL/dRe(c_k) + i dL/dIm(c_k) for the listed strings (DEVICE,
+ * count values, opts->in_dtype), write the dense
+ *     grad_G = 2^-N sum_k grad_c[k] P_{strings[k]}
+ * (DEVICE, 2^N x 2^N, opts->out_dtype), zero away from the listed strings'
+ * XOR diagonals; repeated strings add.  This is the linear map's adjoint
+ * (Eq. (cn_compact) with Hermitian P_n), as for pauli_decompose_backward.
+ * strings is a HOST array as in pauli_coeffs_at; limits and workspace as
+ * there.  Summed in binary64.
+ */
+int pauli_coeffs_at_backward(const void* grad_c, int N, const unsigned int* strings, int count, void* grad_G,
+                             const pauli_opts* opts);
+
+/*
+ * Workspace bytes that suffice for pauli_coeffs_at and
+ * pauli_coeffs_at_backward with any list of `count` strings at order N (the plan plus, for short lists whose columns are split
  * over several workgroups, binary64 partial sums); 0 for invalid arguments.
  */
 size_t pauli_coeffs_at_workspace_bytes(int N, int count);

@@ -50,7 +50,7 @@ EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_
            "pauli_decompose_batched", "pauli_batched_workspace_bytes", "pauli_workspace_bytes",
            "pauli_batched_tile_count", "pauli_batched_tile_valid", "pauli_autotune_batched",
            "pauli_batched_tile_selected", "pauli_autotune", "pauli_tile_count", "pauli_tile_valid",
-           "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_coeffs_at",
+           "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_coeffs_at", "pauli_coeffs_at_backward",
            "pauli_coeffs_at_workspace_bytes", "pauli_last_error", "pauli_version"]
 
 
@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_contract.restype = ci
         lib.pauli_coeffs_at.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_uint), ci, vp, op]
         lib.pauli_coeffs_at.restype = ci
+        lib.pauli_coeffs_at_backward.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_uint), ci, vp, op]
+        lib.pauli_coeffs_at_backward.restype = ci
         lib.pauli_coeffs_at_workspace_bytes.argtypes = [ci, ci]
         lib.pauli_coeffs_at_workspace_bytes.restype = ctypes.c_size_t
         lib.pauli_last_error.argtypes = []
@@ -252,6 +254,30 @@ def coeffs_at(G: torch.Tensor, strings, out_dtype=None, workspace_tensor=None) -
     return out
 
 
+def coeffs_at_backward(grad_c: torch.Tensor, N: int, strings, out_dtype=None, workspace_tensor=None) -> torch.Tensor:
+    """Adjoint of coeffs_at: 2^-N sum_k grad_c[k] P_{strings[k]} as a dense
+    [2^N, 2^N] tensor (binary64 sums)."""
+    import numpy as np
+    g = _prep(grad_c)
+    ns = np.ascontiguousarray(np.asarray(strings, dtype=np.uint64).reshape(-1))
+    if g.dim() != 1 or g.shape[0] != ns.shape[0]:
+        raise ValueError("grad_c must be 1-D with one value per string")
+    if ns.size and int(ns.max()) >= 1 << (2 * N):
+        raise ValueError("string index %d is not below 4^%d" % (int(ns.max()), N))
+    ns = ns.astype(np.uint32)
+    out_dtype = out_dtype or g.dtype
+    out = torch.empty((1 << N, 1 << N), dtype=out_dtype, device=g.device)
+    if ns.shape[0] == 0:
+        return out.zero_()
+    o = _opts("fp64_gray", _DT[g.dtype], _DT[out_dtype], 0, _stream(g))
+    if workspace_tensor is not None:
+        o.workspace = workspace_tensor.data_ptr()
+        o.workspace_bytes = workspace_tensor.numel() * workspace_tensor.element_size()
+    _check(load_library().pauli_coeffs_at_backward(g.data_ptr(), N, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint)),
+                                                   ns.shape[0], out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
 def _batch_args(mats, algo, outs):
     mats = [_prep(m) for m in mats]
     for m in mats:
@@ -323,8 +349,9 @@ def tile_selected(N: int, algo: str = "split_bf16") -> int:
     return load_library().pauli_tile_selected(ALGOS[algo], N)
 
 
-from .autograd import PauliDecompose  # noqa: E402
+from .autograd import PauliCoeffsAt, PauliDecompose  # noqa: E402
 
-__all__ = ["decompose", "reconstruct", "decompose_backward", "decompose_batched", "coeffs_at", "autotune",
+__all__ = ["decompose", "reconstruct", "decompose_backward", "decompose_batched", "coeffs_at",
+           "coeffs_at_backward", "PauliCoeffsAt", "autotune",
            "autotune_batched", "workspace", "release_workspace", "tile_valid", "batched_tile_valid", "tile_count", "tile_selected",
            "PauliDecompose", "PauliError", "load_library", "last_error", "ALGOS", "EXPORTS"]

@@ -654,6 +654,7 @@ namespace {
 struct StringsPlan {
     std::vector<StringChunk> chunks;
     std::vector<StringEntry> entries;
+    std::vector<uint32_t> first;   // 2^N + 1 offsets: the strings of flip mask x are entries[first[x] .. first[x+1])
     int parts = 1;   // workgroups per chunk (column split), see strings_parts
 };
 
@@ -689,6 +690,7 @@ StringsPlan plan_strings(int N, const uint32_t* strings, int count) {
     }
     P.entries.resize(count);
     for (int a = 0; a < count; ++a) P.entries[a] = {strings[order[a]], order[a]};
+    P.first = start;
     const uint32_t W = N < 4 ? nx : 16u;           // masks per line group
     for (uint32_t g0 = 0; g0 < nx; g0 += W) {
         const uint32_t a0 = start[g0], a1 = start[g0 + W];
@@ -710,14 +712,46 @@ hipEvent_t g_stage_done = nullptr;
 
 }  // namespace
 
+// Copy host bytes [a | b] (b at offset off_b) into device memory at dst on
+// stream s through the shared pinned staging buffer.
+static hipError_t stage_copy(void* dst, const void* a, size_t na, const void* b, size_t nb, size_t off_b, hipStream_t s) {
+    const size_t bytes = off_b + nb;
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    hipError_t e;
+    if (!g_stage_done) {
+        if ((e = hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming)) != hipSuccess) {
+            g_stage_done = nullptr;
+            return e;
+        }
+    }
+    if ((e = hipEventSynchronize(g_stage_done)) != hipSuccess) return e;
+    if (g_stage_bytes < bytes) {
+        if (g_stage) (void)hipHostFree(g_stage);
+        g_stage = nullptr;
+        g_stage_bytes = 0;
+        if ((e = hipHostMalloc(&g_stage, bytes)) != hipSuccess) {
+            g_stage = nullptr;
+            return e;
+        }
+        g_stage_bytes = bytes;
+    }
+    memcpy(g_stage, a, na);
+    memcpy((char*)g_stage + off_b, b, nb);
+    if ((e = hipMemcpyAsync(dst, g_stage, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    return hipEventRecord(g_stage_done, s);
+}
+
 extern "C" size_t pauli_coeffs_at_workspace_bytes(int N, int count) {
     if (count < 1 || N < 0 || N > N_MAX) return 0;
+    const size_t adjoint = round256(sizeof(StringEntry) * (size_t)count) + round256(sizeof(uint32_t) * (((size_t)1 << N) + 1));
     // chunks <= count; the column split gives chunks x parts <= STRINGS_MAX_BLOCKS
     // with chunks >= count / STRINGS_PER_CHUNK, so parts x count stays below
     // STRINGS_MAX_BLOCKS x STRINGS_PER_CHUNK + count, and parts <= strings_batches(N).
     const size_t c = (size_t)count;
     size_t pc = std::min(c * strings_batches(N), (size_t)STRINGS_MAX_BLOCKS * STRINGS_PER_CHUNK + c);
-    return round256(sizeof(StringChunk) * c) + round256(sizeof(StringEntry) * c) + round256(sizeof(double) * 2 * pc);
+    const size_t forward =
+        round256(sizeof(StringChunk) * c) + round256(sizeof(StringEntry) * c) + round256(sizeof(double) * 2 * pc);
+    return std::max(forward, adjoint);
 }
 
 extern "C" int pauli_coeffs_at(const void* G, int N, const unsigned int* strings, int count, void* out,
@@ -755,32 +789,62 @@ extern "C" int pauli_coeffs_at(const void* G, int N, const unsigned int* strings
     }
     const size_t chunk_bytes = round256(sizeof(StringChunk) * P.chunks.size());
     const size_t plan_bytes = chunk_bytes + round256(sizeof(StringEntry) * P.entries.size());
-    {
-        std::lock_guard<std::mutex> lk(g_stage_mu);
-        if (!g_stage_done && (e = hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming)) != hipSuccess) {
-            g_stage_done = nullptr;
-            goto fail_free;
-        }
-        if ((e = hipEventSynchronize(g_stage_done)) != hipSuccess) goto fail_free;
-        if (g_stage_bytes < plan_bytes) {
-            if (g_stage) (void)hipHostFree(g_stage);
-            g_stage = nullptr;
-            g_stage_bytes = 0;
-            if ((e = hipHostMalloc(&g_stage, plan_bytes)) != hipSuccess) {
-                g_stage = nullptr;
-                goto fail_free;
-            }
-            g_stage_bytes = plan_bytes;
-        }
-        memcpy(g_stage, P.chunks.data(), sizeof(StringChunk) * P.chunks.size());
-        memcpy((char*)g_stage + chunk_bytes, P.entries.data(), sizeof(StringEntry) * P.entries.size());
-        if ((e = hipMemcpyAsync(ws, g_stage, plan_bytes, hipMemcpyHostToDevice, s)) != hipSuccess) goto fail_free;
-        if ((e = hipEventRecord(g_stage_done, s)) != hipSuccess) goto fail_free;
-    }
+    if ((e = stage_copy(ws, P.chunks.data(), sizeof(StringChunk) * P.chunks.size(), P.entries.data(),
+                        sizeof(StringEntry) * P.entries.size(), chunk_bytes, s)) != hipSuccess)
+        goto fail_free;
     e = launch_strings(G, o.in_dtype == PAULI_C128, N, (const StringChunk*)ws, (int)P.chunks.size(),
                        (const StringEntry*)((char*)ws + chunk_bytes), count, P.parts,
                        (double2*)((char*)ws + plan_bytes), out, o.out_dtype == PAULI_C128, s);
 fail_free:
+    if (pool) {
+        const hipError_t ef = hipFreeAsync(ws, s);
+        if (e == hipSuccess) e = ef;
+    }
+    if (e != hipSuccess) return hip_fail(e, fn);
+    g_last_error.clear();
+    return PAULI_OK;
+}
+
+extern "C" int pauli_coeffs_at_backward(const void* grad_c, int N, const unsigned int* strings, int count,
+                                        void* grad_G, const pauli_opts* opts) {
+    const char* fn = "pauli_coeffs_at_backward";
+    const pauli_opts o = resolve(opts);
+    if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
+    if (count < 1) return fail(PAULI_EINVAL, "%s: count=%d must be >= 1", fn, count);
+    if (!grad_c || !grad_G || !strings) return fail(PAULI_EINVAL, "%s: NULL pointer", fn);
+    if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
+        return fail(PAULI_EINVAL, "%s: unknown dtype (in %d, out %d)", fn, o.in_dtype, o.out_dtype);
+    if ((uintptr_t)grad_c % 16 || (uintptr_t)grad_G % 16)
+        return fail(PAULI_EINVAL, "%s: grad_c or grad_G not 16-byte aligned", fn);
+    const uint64_t nmax = (uint64_t)1 << (2 * N);
+    for (int k = 0; k < count; ++k)
+        if ((uint64_t)strings[k] >= nmax)
+            return fail(PAULI_EINVAL, "%s: strings[%d]=%u is not below 4^%d", fn, k, strings[k], N);
+    const size_t cbytes = (size_t)count * elem_bytes(o.in_dtype), gbytes = (size_t)nmax * elem_bytes(o.out_dtype);
+    if (overlaps(grad_c, cbytes, grad_G, gbytes)) return fail(PAULI_EINVAL, "%s: input and output overlap", fn);
+    const StringsPlan P = plan_strings(N, strings, count);
+    const size_t ent_bytes = round256(sizeof(StringEntry) * P.entries.size());
+    const size_t need = ent_bytes + round256(sizeof(uint32_t) * P.first.size());
+    if (o.workspace) {
+        if ((uintptr_t)o.workspace % 256) return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+        if (o.workspace_bytes < need)
+            return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, o.workspace_bytes);
+        if (overlaps(o.workspace, need, grad_c, cbytes) || overlaps(o.workspace, need, grad_G, gbytes))
+            return fail(PAULI_EINVAL, "%s: workspace overlaps input or output", fn);
+    }
+    hipStream_t s = (hipStream_t)o.stream;
+    hipError_t e;
+    void* ws = o.workspace;
+    hipMemPool_t pool = nullptr;
+    if (!ws) {
+        if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
+        if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
+    }
+    e = stage_copy(ws, P.entries.data(), sizeof(StringEntry) * P.entries.size(), P.first.data(),
+                   sizeof(uint32_t) * P.first.size(), ent_bytes, s);
+    if (e == hipSuccess)
+        e = launch_strings_adjoint(grad_c, o.in_dtype == PAULI_C128, (const StringEntry*)ws,
+                                   (const uint32_t*)((char*)ws + ent_bytes), grad_G, o.out_dtype == PAULI_C128, N, s);
     if (pool) {
         const hipError_t ef = hipFreeAsync(ws, s);
         if (e == hipSuccess) e = ef;

@@ -70,6 +70,10 @@ uint32_t strings_batches(int N);
 hipError_t launch_strings(const void* G, bool in_c128, int N, const StringChunk* chunks, int nchunks,
                           const StringEntry* entries, int count, int parts, double2* partial, void* out,
                           bool out_c128, hipStream_t stream);
+// Adjoint of the list (dense 2^N x 2^N output): entries sorted by flip mask,
+// first[x] .. first[x + 1] (2^N + 1 offsets) the strings of mask x.
+hipError_t launch_strings_adjoint(const void* grad, bool grad_c128, const StringEntry* entries,
+                                  const uint32_t* first, void* out, bool out_c128, int N, hipStream_t stream);
 
 // All coefficients by two fast Walsh-Hadamard passes through a binary64
 // intermediate of fwht_workspace_bytes(N, batch) bytes (16 per element).

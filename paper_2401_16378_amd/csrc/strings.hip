@@ -287,3 +287,81 @@ hipError_t launch_strings(const void* G, bool in_c128, int N, const StringChunk*
 }
 
 }  // namespace pauli
+
+// ---- adjoint of the list: grad_G = 2^-N sum_k g_k P_{n_k} ----
+namespace pauli {
+namespace {
+
+// One workgroup per (line group of 16 flip masks, batch of 128 columns):
+// every entry G[i ^ x][i] of the 16 x 128 block gets
+//   2^-N sum over listed strings k with flip mask x of
+//        i^{popc(x&z_k)} (-1)^{popc(i&z_k)} g_k,
+// zero when no listed string has flip mask x.  Element e = t + 256 j is
+// (column block c_b = e >> 8, row r, column c of its 16 x 16 tile), x_l =
+// r ^ c; sixteen consecutive threads write one 128-byte row segment.
+// first[x] .. first[x + 1] are the positions of mask x's strings in entries.
+template <bool GRAD128, bool OUT128>
+__global__ __launch_bounds__(256) void strings_adjoint(const void* __restrict__ grad, const StringEntry* __restrict__ entries,
+                                                       const uint32_t* __restrict__ first, void* __restrict__ out,
+                                                       int N, double scale) {
+    const uint32_t D = 1u << N;
+    const uint32_t W = D < 16u ? D : 16u, lw = D < 16u ? (uint32_t)N : 4u;
+    const uint32_t ib = D < 128u ? D : 128u;
+    const uint32_t x0 = blockIdx.y * W, i0 = blockIdx.x * ib;
+    const uint32_t total = ib * W;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t e = threadIdx.x + 256u * j;
+        if (e >= total) break;
+        const uint32_t c = e & (W - 1u), r = (e >> lw) & (W - 1u), b = e >> (2 * lw);
+        const uint32_t col = i0 + (b << lw) + c;
+        const uint32_t x = x0 + (r ^ c);
+        const uint32_t row = col ^ x;
+        double re = 0.0, im = 0.0;
+        for (uint32_t k = first[x]; k < first[x + 1]; ++k) {
+            const StringEntry s = entries[k];
+            const uint32_t z = phase_of_index(s.n);
+            double gr, gi;
+            if constexpr (GRAD128) {
+                const double2 g = ((const double2*)grad)[s.slot];
+                gr = g.x;
+                gi = g.y;
+            } else {
+                const float2 g = ((const float2*)grad)[s.slot];
+                gr = (double)g.x;
+                gi = (double)g.y;
+            }
+            rotate_minus_i(gr, gi, 3u * (uint32_t)__popc(x & z) + 2u * (uint32_t)__popc(col & z));
+            re += gr;
+            im += gi;
+        }
+        re *= scale;
+        im *= scale;
+        if constexpr (OUT128) ((double2*)out)[(size_t)row * D + col] = make_double2(re, im);
+        else ((float2*)out)[(size_t)row * D + col] = make_float2((float)re, (float)im);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_strings_adjoint(const void* grad, bool grad_c128, const StringEntry* entries,
+                                  const uint32_t* first, void* out, bool out_c128, int N, hipStream_t stream) {
+    const uint32_t D = 1u << N;
+    const uint32_t W = D < 16u ? D : 16u, ib = D < 128u ? D : 128u;
+    const dim3 grid(D / ib, D / W);
+    const double scale = 1.0 / (double)D;
+    if (grad_c128) {
+        if (out_c128)
+            hipLaunchKernelGGL((strings_adjoint<true, true>), grid, dim3(256), 0, stream, grad, entries, first, out, N, scale);
+        else
+            hipLaunchKernelGGL((strings_adjoint<true, false>), grid, dim3(256), 0, stream, grad, entries, first, out, N, scale);
+    } else {
+        if (out_c128)
+            hipLaunchKernelGGL((strings_adjoint<false, true>), grid, dim3(256), 0, stream, grad, entries, first, out, N, scale);
+        else
+            hipLaunchKernelGGL((strings_adjoint<false, false>), grid, dim3(256), 0, stream, grad, entries, first, out, N, scale);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pauli

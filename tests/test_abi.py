@@ -209,3 +209,18 @@ def test_fwht_algo_queries(lib, pauli):
     assert lib.pauli_decompose(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_pack(FAKE_IN, 10, 1, 0, ctypes.byref(o)) == EUNSUPPORTED
     assert lib.pauli_autotune(9, 10, ctypes.byref(o)) == EUNSUPPORTED
+
+
+def test_coeffs_at_backward_validation(lib, pauli):
+    u32 = ctypes.c_uint
+    ns = (u32 * 3)(0, 5, 15)
+    o = opts(pauli)
+    f = lib.pauli_coeffs_at_backward
+    assert f(FAKE_IN, 2, ns, 0, FAKE_OUT, ctypes.byref(o)) == EINVAL
+    assert f(FAKE_IN, 1, ns, 3, FAKE_OUT, ctypes.byref(o)) == EINVAL      # 5 and 15 are not below 4^1
+    assert f(FAKE_IN, 2, None, 3, FAKE_OUT, ctypes.byref(o)) == EINVAL
+    assert f(FAKE_IN, 2, ns, 3, FAKE_IN + 16, ctypes.byref(o)) == EINVAL   # overlap
+    small = opts(pauli, ws=0x30000000, ws_bytes=64)
+    assert f(FAKE_IN, 2, ns, 3, FAKE_OUT, ctypes.byref(small)) == ENOMEM
+    # the workspace bound covers the adjoint's plan (entries + 2^N + 1 offsets)
+    assert lib.pauli_coeffs_at_workspace_bytes(14, 1) >= 4 * (2 ** 14 + 1)

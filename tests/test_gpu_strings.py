@@ -118,3 +118,59 @@ def test_workspace_argument():
     assert torch.equal(a, b)
     with pytest.raises(p.PauliError):
         p.coeffs_at(G, ns, workspace_tensor=ws[:256])
+
+
+def dense_list_gradient(N, strings, g):
+    """The oracle's 2^-N sum_k g_k P_{n_k} at every entry (repeats add)."""
+    gc = np.zeros(4 ** N, np.complex128)
+    np.add.at(gc, np.asarray(strings, dtype=np.int64), g)
+    D = 1 << N
+    rows, cols = np.divmod(np.arange(D * D, dtype=np.uint64), D)
+    return oracle.grad_entries(gc, rows, cols).reshape(D, D)
+
+
+@pytest.mark.parametrize("N", [0, 1, 3, 5, 8])
+def test_backward_vs_oracle(N):
+    p = lib()
+    rng = np.random.default_rng(930 + N)
+    L = min(4 ** N, 40) + 3
+    ns = rng.integers(0, 4 ** N, L).astype(np.uint32)
+    ns[-1] = ns[0]                                   # a repeat adds
+    g = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    got = p.coeffs_at_backward(torch.from_numpy(g).cuda(), N, ns).cpu().numpy()
+    ref = dense_list_gradient(N, ns, g)
+    assert rel_err(got, ref) <= 1e-12
+
+
+def test_backward_equals_full_adjoint_n10():
+    """Scattering the list gradient into a 4^N vector and running the binary64
+    full adjoint must give the same matrix."""
+    p = lib()
+    N = 10
+    rng = np.random.default_rng(940)
+    ns = rng.integers(0, 4 ** N, 5000).astype(np.uint32)
+    g = rng.standard_normal(5000) + 1j * rng.standard_normal(5000)
+    got = p.coeffs_at_backward(torch.from_numpy(g).cuda(), N, ns)
+    gc = torch.zeros(4 ** N, dtype=torch.complex128, device="cuda")
+    gc.index_add_(0, torch.from_numpy(ns.astype(np.int64)).cuda(), torch.from_numpy(g).cuda())
+    full = p.decompose_backward(gc, algo="fp64_gray")
+    assert ((got - full).abs().max() / full.abs().max()).item() <= 1e-12
+
+
+def test_autograd_list_loss():
+    """L = sum_k w_k |c_k - t_k|^2 over a list of strings, through
+    PauliCoeffsAt: the gradient equals the oracle's adjoint of 2 w (c - t)."""
+    p = lib()
+    N = 7
+    G = workloads.iid_complex(N, 950, np.complex128)
+    rng = np.random.default_rng(951)
+    ns = rng.integers(0, 4 ** N, 300).astype(np.uint32)
+    t = rng.standard_normal(300) + 1j * rng.standard_normal(300)
+    w = rng.uniform(0, 1, 300)
+    Gd = torch.from_numpy(G).cuda().requires_grad_(True)
+    c = p.PauliCoeffsAt.apply(Gd, ns)
+    loss = (torch.from_numpy(w).cuda() * (c - torch.from_numpy(t).cuda()).abs() ** 2).sum()
+    loss.backward()
+    cref = oracle.coeffs_at(G, ns)
+    ref = dense_list_gradient(N, ns, 2.0 * w * (cref - t))
+    assert rel_err(Gd.grad.cpu().numpy(), ref) <= 1e-12
