@@ -40,6 +40,8 @@ KERNEL_SOURCES = ["paper_2401_16378_amd/csrc/mfma_tile.hpp", "paper_2401_16378_a
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_bf16_n14.json")
 STRINGS_SOURCES = ["paper_2401_16378_amd/csrc/strings.hip", "paper_2401_16378_amd/csrc/common.hpp"]
 STRINGS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_strings_n14.json")
+FWHT_SOURCES = ["paper_2401_16378_amd/csrc/fwht.hip", "paper_2401_16378_amd/csrc/common.hpp"]
+FWHT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwht_n14.json")
 
 
 def source_hash(sources=KERNEL_SOURCES) -> str:
@@ -263,9 +265,11 @@ def bench_fwht(a):
                                    "coefficients, algo fwht (two binary64 passes through a 16 B/element "
                                    "intermediate)" % (N, 1 << N, 1 << N, workloads.SEED_N14, N), "N": N, "algo": "fwht"},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(FWHT_TRAFFIC_FILE, FWHT_SOURCES) if N == 14 else None,
                          "note": "achieved counts 16 B per element (G read once, coefficients written once); the "
-                                 "two-pass design also writes and reads a 16 B/element intermediate"},
+                                 "two-pass design also writes and reads a 16 B/element intermediate, and traffic "
+                                 "is the measured HBM bytes of both passes of one decomposition"},
             "max_err_vs_fp64_gray": err}
     if not a.no_cpu:
         line["cpu_baseline"], line["max_err_vs_oracle_sample"] = cpu_baseline(
