@@ -44,6 +44,8 @@
 // accumulator, where the sums stay exact, and mid + lo into a second, and the
 // two are added in binary64 in the epilogue before the phase and scale.
 // PLANES = 1: binary32 MFMA on the binary32 components.
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -415,15 +417,22 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
         for (int f = 0; f < P::NPL; ++f) ring[slot][f] = *(const u32x4*)(p + f * FRAG);
     };
     const bool active = Pw < Dp;                 // idle waves skip the contraction
-    if (active && nS % GS == 0) {
+    // Main loop: GSX slices per unrolled step (the ring and the sign groups
+    // both nest in it).  The forward bf16 tiles of 4 x 32 rows per wave also
+    // get a step four times longer when the K length allows it: the compiler waits
+    // for every outstanding fragment load at the top of each step, and a
+    // longer step does that less often (measured 1.7% at N = 14); the sum
+    // order, and so the result, is the same for both step lengths.
+    auto main_loop = [&](auto gs_tag) {
+    constexpr int GSX = decltype(gs_tag)::value;
 #pragma unroll
     for (int k = 0; k < PF; ++k) fetch(k, (uint32_t)k < nS ? k : nS - 1);
 
     bf16x8 Ap[2], An[2];
     float ts = 1.f;
-    for (uint32_t s0 = 0; s0 < nS; s0 += GS) {
+    for (uint32_t s0 = 0; s0 < nS; s0 += GSX) {
 #pragma unroll
-        for (int uu = 0; uu < GS; ++uu) {
+        for (int uu = 0; uu < GSX; ++uu) {
             const int u = uu % U, slot = uu % PF;
             if (u == 0) {
                 // sign of this wave's rows against this group of 32*RB K values
@@ -469,7 +478,7 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
                     }
             }
             if constexpr (PLANES == 1) {
-                if constexpr (GS % FLUSH_SLICES == 0) {
+                if constexpr (GSX % FLUSH_SLICES == 0) {
                     if (uu % FLUSH_SLICES == FLUSH_SLICES - 1) flush_into<RB>(tot, acc);
                 } else {
                     if ((s0 + uu + 1) % FLUSH_SLICES == 0) flush_into<RB>(tot, acc);
@@ -484,6 +493,12 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
             __builtin_amdgcn_sched_barrier(0);
         }
     }
+    };
+    constexpr int GSL = (PLANES == 3 && RB == 4 && DIR == FORWARD) ? 4 * GS : GS;
+    if (active && nS % GSL == 0) {
+        main_loop(std::integral_constant<int, GSL>{});
+    } else if (active && nS % GS == 0) {
+        main_loop(std::integral_constant<int, GS>{});
     } else if (active) {
         // Fewer K slices than one unrolled group (small matrices in a batch
         // whose tile shape was chosen for larger ones): one slice at a time,
