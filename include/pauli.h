@@ -29,7 +29,11 @@
  * Execution: work is enqueued on opts->stream (a hipStream_t passed as
  * void*, NULL = the null stream) and the call returns without waiting.  The
  * caller synchronises before reading results.  No C++ exception crosses this
- * interface.
+ * interface.  With opts->workspace set, pauli_decompose, pauli_reconstruct,
+ * pauli_decompose_backward, pauli_pack and pauli_contract enqueue kernels
+ * only, so they may be captured in a HIP graph and replayed; the list and
+ * batched entry points copy a host-built plan on every call and must not be
+ * captured by the caller (the batched one replays a graph of its own).
  *
  * Errors: every function returns a pauli_status.  On failure nothing has been
  * enqueued and pauli_last_error() returns a message for the calling thread.
