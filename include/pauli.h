@@ -76,9 +76,9 @@ typedef enum pauli_algo {
      * are a Sylvester-Hadamard transform of the gathered XOR diagonal
      * (section 2, Eq. (c_def_in_terms_of_fn)), done by fast Walsh-Hadamard
      * butterflies in O(N 4^N), binary64 throughout: two passes over HBM
-     * through a workspace of 16 bytes per matrix element.  All three
-     * directions (decompose, reconstruct, backward); 9 <= N <= 14, other N
-     * return PAULI_EUNSUPPORTED. */
+     * through a workspace of 16 bytes per matrix element (N >= 9; up to
+     * N = 8 one kernel works in LDS and needs none).  All three directions
+     * (decompose, reconstruct, backward), 0 <= N <= 16. */
     PAULI_ALGO_FWHT = 3
 } pauli_algo;
 

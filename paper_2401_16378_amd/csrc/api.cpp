@@ -166,7 +166,9 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
     } else if (o.algo == PAULI_ALGO_FWHT) {
         const size_t need = fwht_workspace_bytes(N, batch);
         void* ws = o.workspace;
-        if (ws) {
+        if (need == 0) {
+            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, nullptr, s);
+        } else if (ws) {
             if (o.workspace_bytes < need)
                 return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
                             o.workspace_bytes);

@@ -138,19 +138,23 @@ __global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall,
     }
 }
 
-// TPV threads per vector (16, 32 or 64), EPT = M / TPV elements per thread
-// (M = 2^(N-5) values of i_h per vector); the workgroup has 16 TPV threads.
+// TPV threads per vector (16, 32 or 64), EPT elements per thread: the
+// workgroup transforms ML = TPV EPT values of i_h per vector (all 2^(N-5)
+// of them up to N = 14; above, each of the 2^(N-14) blocks of 512 whose top
+// bits fwht_top has already transformed, selected by blockIdx.x >> 6); the
+// workgroup has 16 TPV threads.
 template <int TPV, int EPT, bool OUT128>
 __global__ __launch_bounds__(16 * TPV) void fwht_pass2(const double2* __restrict__ Uall, void* __restrict__ outall,
                                                        int N, double scale) {
     extern __shared__ __attribute__((aligned(16))) unsigned char stage[];   // [z_h][16] coefficients
-    constexpr uint32_t M = (uint32_t)TPV * EPT;
+    constexpr uint32_t ML = (uint32_t)TPV * EPT;
     constexpr int ESZ = OUT128 ? 16 : 8;
     constexpr uint32_t NT = 16u * TPV;
-    const uint32_t D = 1u << N;
+    const uint32_t D = 1u << N, M = D >> 5;
     const size_t mat = (size_t)D * D;
     const uint32_t x0 = blockIdx.y * 32u;
-    const uint32_t a = blockIdx.x & 7u, b = blockIdx.x >> 3;      // x_l quad, z_l quad
+    const uint32_t a = blockIdx.x & 7u, b = (blockIdx.x >> 3) & 7u;   // x_l quad, z_l quad
+    const uint32_t h0 = (blockIdx.x >> 6) * ML;                       // first i_h (and z_h) of this block
     const double2* U = Uall + (size_t)blockIdx.z * mat;
     unsigned char* out = (unsigned char*)outall + (size_t)blockIdx.z * mat * ESZ;
     const int t = threadIdx.x, lane = t & 63;
@@ -162,7 +166,7 @@ __global__ __launch_bounds__(16 * TPV) void fwht_pass2(const double2* __restrict
     const double2* src = U + (size_t)x * 32u * M + zl * HB;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const uint32_t ih = (uint32_t)q + (uint32_t)TPV * k;
+        const uint32_t ih = h0 + (uint32_t)q + (uint32_t)TPV * k;
         v[k] = src[(size_t)(ih / HB) * 32u * HB + ih % HB];
     }
 
@@ -186,8 +190,8 @@ __global__ __launch_bounds__(16 * TPV) void fwht_pass2(const double2* __restrict
     const uint32_t slot = ((xl ^ zl) & 1u) | ((zl & 1u) << 1) | (((xl ^ zl) & 2u) << 1) | ((zl & 2u) << 2);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const uint32_t zh = (uint32_t)q + (uint32_t)TPV * k;
-        const uint32_t z = (zh << 5) + zl;
+        const uint32_t zh = (uint32_t)q + (uint32_t)TPV * k;      // row of the stage
+        const uint32_t z = ((h0 + zh) << 5) + zl;
         double re = v[k].x * scale, im = v[k].y * scale;
         rotate_minus_i(re, im, (uint32_t)__popc(x & z));
         unsigned char* dstl = stage + ((size_t)zh * 16u + slot) * ESZ;
@@ -195,12 +199,12 @@ __global__ __launch_bounds__(16 * TPV) void fwht_pass2(const double2* __restrict
         else *(float2*)dstl = make_float2((float)re, (float)im);
     }
     __syncthreads();
-    // M runs of 16 coefficients (16 * ESZ bytes each), 16-byte stores
+    // ML runs of 16 coefficients (16 * ESZ bytes each), 16-byte stores
     constexpr uint32_t CH = (16u * ESZ) / 16u;    // 16-byte chunks per run
     const uint32_t xb4 = x0 + 4u * a, zb4 = 4u * b;
-    for (uint32_t j = (uint32_t)t; j < M * CH; j += NT) {
+    for (uint32_t j = (uint32_t)t; j < ML * CH; j += NT) {
         const uint32_t zh = j / CH, part = j % CH;
-        const uint32_t base = pauli_index(xb4, (zh << 5) + zb4);   // low four bits are zero
+        const uint32_t base = pauli_index(xb4, ((h0 + zh) << 5) + zb4);   // low four bits are zero
         *(u32x4_t*)(out + (size_t)base * ESZ + part * 16u) = *(const u32x4_t*)(stage + ((size_t)zh * CH + part) * 16u);
     }
 }
@@ -214,13 +218,14 @@ template <int TPV, int EPT, bool IN128>
 __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ inall, double2* __restrict__ Wall,
                                                        int N) {
     extern __shared__ __attribute__((aligned(16))) unsigned char stage[];   // [z_h][16] coefficients
-    constexpr uint32_t M = (uint32_t)TPV * EPT;
+    constexpr uint32_t ML = (uint32_t)TPV * EPT;
     constexpr int ESZ = IN128 ? 16 : 8;
     constexpr uint32_t NT = 16u * TPV;
-    const uint32_t D = 1u << N;
+    const uint32_t D = 1u << N, M = D >> 5;
     const size_t mat = (size_t)D * D;
     const uint32_t x0 = blockIdx.y * 32u;
-    const uint32_t a = blockIdx.x & 7u, b = blockIdx.x >> 3;
+    const uint32_t a = blockIdx.x & 7u, b = (blockIdx.x >> 3) & 7u;
+    const uint32_t h0 = (blockIdx.x >> 6) * ML;
     const unsigned char* in = (const unsigned char*)inall + (size_t)blockIdx.z * mat * ESZ;
     double2* W = Wall + (size_t)blockIdx.z * mat;
     const int t = threadIdx.x, lane = t & 63;
@@ -230,9 +235,9 @@ __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ 
 
     constexpr uint32_t CH = (16u * ESZ) / 16u;
     const uint32_t xb4 = x0 + 4u * a, zb4 = 4u * b;
-    for (uint32_t j = (uint32_t)t; j < M * CH; j += NT) {
+    for (uint32_t j = (uint32_t)t; j < ML * CH; j += NT) {
         const uint32_t zh = j / CH, part = j % CH;
-        const uint32_t base = pauli_index(xb4, (zh << 5) + zb4);
+        const uint32_t base = pauli_index(xb4, ((h0 + zh) << 5) + zb4);
         *(u32x4_t*)(stage + ((size_t)zh * CH + part) * 16u) = *(const u32x4_t*)(in + (size_t)base * ESZ + part * 16u);
     }
     __syncthreads();
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ 
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
         const uint32_t zh = (uint32_t)q + (uint32_t)TPV * k;
-        const uint32_t z = (zh << 5) + zl;
+        const uint32_t z = ((h0 + zh) << 5) + zl;
         const unsigned char* src = stage + ((size_t)zh * 16u + slot) * ESZ;
         double re, im;
         if constexpr (IN128) {
@@ -272,7 +277,7 @@ __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ 
     double2* dst = W + (size_t)x * 32u * M + zl * HB;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const uint32_t ih = (uint32_t)q + (uint32_t)TPV * k;
+        const uint32_t ih = h0 + (uint32_t)q + (uint32_t)TPV * k;
         dst[(size_t)(ih / HB) * 32u * HB + ih % HB] = v[k];
     }
 }
@@ -338,7 +343,8 @@ __global__ __launch_bounds__(256) void fwht_adj_b(const double2* __restrict__ Wa
 template <int TPV, int EPT>
 hipError_t launch_adj_a(const void* in, bool in128, double2* W, int N, int batch, uint32_t nxb,
                         hipStream_t s) {
-    const dim3 grid(64u, nxb, (uint32_t)batch);
+    const uint32_t ntop = ((1u << N) >> 5) / (uint32_t)(TPV * EPT);
+    const dim3 grid(64u * ntop, nxb, (uint32_t)batch);
     const size_t lds = (size_t)TPV * EPT * 16u * (in128 ? 16u : 8u);
     hipError_t e;
     if (in128) {
@@ -358,7 +364,8 @@ hipError_t launch_adj_a(const void* in, bool in128, double2* W, int N, int batch
 template <int TPV, int EPT>
 hipError_t launch_pass2(const double2* U, void* out, bool out128, int N, int batch, double scale, uint32_t nxb,
                         hipStream_t s) {
-    const dim3 grid(64u, nxb, (uint32_t)batch);   // the 64 quads of a mask block back to back
+    const uint32_t ntop = ((1u << N) >> 5) / (uint32_t)(TPV * EPT);
+    const dim3 grid(64u * ntop, nxb, (uint32_t)batch);   // the 64 quads of a mask block back to back
     const size_t lds = (size_t)TPV * EPT * 16u * (out128 ? 16u : 8u);
     hipError_t e;
     if (out128) {
@@ -375,17 +382,168 @@ hipError_t launch_pass2(const double2* U, void* out, bool out128, int N, int bat
     return hipGetLastError();
 }
 
+// ---- orders 15 and 16: the top T = N - 14 bits of i_h ----
+// In U's blocked layout the D values of one flip mask are contiguous and
+// their i_h top bits select D / 2^T-element sub-blocks, so the 2^T partners
+// of an element lie D / 2^T apart; each thread does one 2^T-point
+// butterfly in place (a pure streaming pass).  Pass 2 (or adjoint pass A)
+// then handles the remaining 9 bits of each sub-block.
+template <int T>
+__global__ __launch_bounds__(256) void fwht_top(double2* __restrict__ Uall, int N) {
+    const uint32_t D = 1u << N;
+    const size_t mat = (size_t)D * D;
+    double2* U = Uall + (size_t)blockIdx.y * mat;
+    const uint32_t lgS = (uint32_t)N - T;                  // sub-block length 2^lgS
+    const size_t S = (size_t)1 << lgS, total = (size_t)D << lgS;
+    for (size_t f = (size_t)blockIdx.x * 256u + threadIdx.x; f < total; f += (size_t)gridDim.x * 256u) {
+        double2* p = U + ((f >> lgS) << N) + (f & (S - 1));
+        double2 v[1 << T];
+#pragma unroll
+        for (int k = 0; k < (1 << T); ++k) v[k] = p[(size_t)k << lgS];
+#pragma unroll
+        for (int m = 1; m < (1 << T); m <<= 1)
+#pragma unroll
+            for (int k = 0; k < (1 << T); ++k)
+                if ((k & m) == 0) {
+                    const double2 a = v[k], b = v[k + m];
+                    v[k] = add2(a, b);
+                    v[k + m] = sub2(a, b);
+                }
+#pragma unroll
+        for (int k = 0; k < (1 << T); ++k) p[(size_t)k << lgS] = v[k];
+    }
+}
+
+hipError_t launch_top(double2* U, int N, int batch, hipStream_t s) {
+    const dim3 grid(8192u, (uint32_t)batch);
+    if (N == 15) hipLaunchKernelGGL(fwht_top<1>, grid, dim3(256), 0, s, U, N);
+    else if (N == 16) hipLaunchKernelGGL(fwht_top<2>, grid, dim3(256), 0, s, U, N);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---- orders N <= 8: one kernel, everything in LDS ----
+// A workgroup owns W = min(32, D) flip masks x0 .. x0 + W - 1 and every
+// column: it gathers the D / W blocks of W x W entries (the same bijection:
+// entry (r, c) of the block at rows (i0 ^ x0) .., columns i0 .. belongs to
+// x_l = r ^ c, i = i0 + c) into v[x_l][i] in binary64 (forward), runs the
+// log2(D) butterfly stages over i in LDS, then writes each W x W (x_l, z_l)
+// block -- a contiguous run of W^2 coefficients -- phased and scaled.  The
+// adjoint reads those runs, phases by i^{popc(x&z)}, transforms over z and
+// scatters through the same blocks.
+template <bool IN128, bool OUT128, int DIR>
+__global__ __launch_bounds__(256) void fwht_small(const void* __restrict__ inall, void* __restrict__ outall, int N,
+                                                  double scale) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    double2* v = (double2*)lds_raw;               // [W][D]
+    const uint32_t D = 1u << N, W = D < 32u ? D : 32u;
+    const uint32_t lw = D < 32u ? (uint32_t)N : 5u;
+    const uint32_t x0 = blockIdx.x * W;
+    const size_t mat = (size_t)D * D;
+    const int t = threadIdx.x;
+    const uint32_t total = W * D;
+    const unsigned char* in = (const unsigned char*)inall + (size_t)blockIdx.y * mat * (IN128 ? 16 : 8);
+    unsigned char* out = (unsigned char*)outall + (size_t)blockIdx.y * mat * (OUT128 ? 16 : 8);
+    auto load = [&](size_t idx) {
+        if constexpr (IN128) return ((const double2*)in)[idx];
+        const float2 g = ((const float2*)in)[idx];
+        return make_double2((double)g.x, (double)g.y);
+    };
+    auto store = [&](size_t idx, double re, double im) {
+        if constexpr (OUT128) ((double2*)out)[idx] = make_double2(re * scale, im * scale);
+        else ((float2*)out)[idx] = make_float2((float)(re * scale), (float)(im * scale));
+    };
+    // run element o of block (x0, z_h): x_l and z_l from n's interleaved bits
+    auto run_xz = [&](uint32_t o, uint32_t& xl, uint32_t& zl) {
+        zl = compact_even(o >> 1);
+        xl = compact_even(o) ^ zl;
+    };
+    if constexpr (DIR == FORWARD) {
+        for (uint32_t e = t; e < total; e += 256) {
+            const uint32_t c = e & (W - 1u), r = (e >> lw) & (W - 1u), b = e >> (2 * lw);
+            const uint32_t i0 = b << lw;
+            v[(r ^ c) * D + i0 + c] = load((size_t)((i0 ^ x0) + r) * D + i0 + c);
+        }
+    } else {
+        for (uint32_t e = t; e < total; e += 256) {
+            const uint32_t zh = e >> (2 * lw), o = e & (W * W - 1u);
+            uint32_t xl, zl;
+            run_xz(o, xl, zl);
+            const uint32_t z = (zh << lw) + zl;
+            double2 c = load((size_t)pauli_index(x0, zh << lw) + o);
+            rotate_minus_i(c.x, c.y, 3u * (uint32_t)__popc((x0 + xl) & z));
+            v[xl * D + z] = c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t m = 1; m < D; m <<= 1) {        // butterflies over the column (or z) index
+        for (uint32_t e = t; e < total / 2; e += 256) {
+            const uint32_t row = e / (D / 2), k = e % (D / 2);
+            const uint32_t lo = ((k & ~(m - 1u)) << 1) | (k & (m - 1u));
+            double2* pa = v + row * D + lo;
+            const double2 a = pa[0], b = pa[m];
+            pa[0] = add2(a, b);
+            pa[m] = sub2(a, b);
+        }
+        __syncthreads();
+    }
+    if constexpr (DIR == FORWARD) {
+        for (uint32_t e = t; e < total; e += 256) {
+            const uint32_t zh = e >> (2 * lw), o = e & (W * W - 1u);
+            uint32_t xl, zl;
+            run_xz(o, xl, zl);
+            const uint32_t z = (zh << lw) + zl;
+            double2 c = v[xl * D + z];
+            rotate_minus_i(c.x, c.y, (uint32_t)__popc((x0 + xl) & z));
+            store((size_t)pauli_index(x0, zh << lw) + o, c.x, c.y);
+        }
+    } else {
+        for (uint32_t e = t; e < total; e += 256) {
+            const uint32_t c = e & (W - 1u), r = (e >> lw) & (W - 1u), b = e >> (2 * lw);
+            const uint32_t i0 = b << lw;
+            const double2 y = v[(r ^ c) * D + i0 + c];
+            store((size_t)((i0 ^ x0) + r) * D + i0 + c, y.x, y.y);
+        }
+    }
+}
+
+template <bool IN128, bool OUT128>
+hipError_t launch_small(Dir dir, const void* in, void* out, int N, int batch, double scale, hipStream_t s) {
+    const uint32_t D = 1u << N, W = D < 32u ? D : 32u;
+    const size_t lds = (size_t)W * D * 16u;
+    const dim3 grid(D / W, (uint32_t)batch);
+    hipError_t e;
+    if (dir == FORWARD) {
+        e = hipFuncSetAttribute((const void*)fwht_small<IN128, OUT128, FORWARD>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((fwht_small<IN128, OUT128, FORWARD>), grid, dim3(256), lds, s, in, out, N, scale);
+    } else {
+        e = hipFuncSetAttribute((const void*)fwht_small<IN128, OUT128, ADJOINT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((fwht_small<IN128, OUT128, ADJOINT>), grid, dim3(256), lds, s, in, out, N, scale);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool fwht_supported(int N) { return N >= FWHT_N_MIN && N <= FWHT_N_MAX; }
 
 size_t fwht_workspace_bytes(int N, int batch) {
-    return ((size_t)1 << (2 * N)) * 16u * (size_t)batch;
+    return N <= FWHT_SMALL_N_MAX ? 0 : ((size_t)1 << (2 * N)) * 16u * (size_t)batch;
 }
 
 hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N, int batch,
                        double scale, void* ws, hipStream_t s) {
     if (!fwht_supported(N)) return hipErrorInvalidValue;
+    if (N <= FWHT_SMALL_N_MAX) {
+        if (in_c128) return out_c128 ? launch_small<true, true>(dir, in, out, N, batch, scale, s)
+                                     : launch_small<true, false>(dir, in, out, N, batch, scale, s);
+        return out_c128 ? launch_small<false, true>(dir, in, out, N, batch, scale, s)
+                        : launch_small<false, false>(dir, in, out, N, batch, scale, s);
+    }
     const uint32_t D = 1u << N, M = D >> 5, nxb = D / 32u;
     double2* U = (double2*)ws;
     const dim3 gt(M / HB, nxb, (uint32_t)batch);   // consecutive i_h groups back to back
@@ -401,6 +559,10 @@ hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool ou
             case 12: return launch_pass2<32, 4>(U, out, out_c128, N, batch, scale, nxb, s);
             case 13: return launch_pass2<32, 8>(U, out, out_c128, N, batch, scale, nxb, s);
             case 14: return launch_pass2<32, 16>(U, out, out_c128, N, batch, scale, nxb, s);
+            case 15:
+            case 16:
+                if ((e = launch_top(U, N, batch, s)) != hipSuccess) return e;
+                return launch_pass2<32, 16>(U, out, out_c128, N, batch, scale, nxb, s);
             default: return hipErrorInvalidValue;
         }
     }
@@ -411,6 +573,11 @@ hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool ou
         case 12: e = launch_adj_a<32, 4>(in, in_c128, U, N, batch, nxb, s); break;
         case 13: e = launch_adj_a<32, 8>(in, in_c128, U, N, batch, nxb, s); break;
         case 14: e = launch_adj_a<32, 16>(in, in_c128, U, N, batch, nxb, s); break;
+        case 15:
+        case 16:
+            e = launch_adj_a<32, 16>(in, in_c128, U, N, batch, nxb, s);
+            if (e == hipSuccess) e = launch_top(U, N, batch, s);
+            break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;

@@ -77,7 +77,8 @@ hipError_t launch_strings_adjoint(const void* grad, bool grad_c128, const String
 
 // All coefficients by two fast Walsh-Hadamard passes through a binary64
 // intermediate of fwht_workspace_bytes(N, batch) bytes (16 per element).
-constexpr int FWHT_N_MIN = 9, FWHT_N_MAX = 14;
+constexpr int FWHT_N_MIN = 0, FWHT_N_MAX = 16;
+constexpr int FWHT_SMALL_N_MAX = 8;   // up to here one kernel works in LDS and needs no workspace
 bool fwht_supported(int N);
 size_t fwht_workspace_bytes(int N, int batch);
 // FORWARD: in = matrices, out = coefficients; ADJOINT: in = coefficients,

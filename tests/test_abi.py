@@ -199,12 +199,13 @@ def test_fwht_algo_queries(lib, pauli):
     assert pauli.ALGOS["fwht"] == 3
     assert lib.pauli_workspace_bytes(3, 14, 1) == 16 * 4 ** 14
     assert lib.pauli_workspace_bytes(3, 14, 2) == 2 * 16 * 4 ** 14
-    assert lib.pauli_workspace_bytes(3, 8, 1) == 0 and lib.pauli_workspace_bytes(3, 15, 1) == 0
+    assert lib.pauli_workspace_bytes(3, 8, 1) == 0                 # one kernel in LDS up to N = 8
+    assert lib.pauli_workspace_bytes(3, 16, 1) == 16 * 4 ** 16
     assert lib.pauli_tile_count(3) == 1
-    assert lib.pauli_tile_valid(3, 1, 9) == 1 and lib.pauli_tile_valid(3, 1, 8) == 0
+    assert all(lib.pauli_tile_valid(3, 1, N) == 1 for N in range(0, 17))
+    assert lib.pauli_tile_valid(3, 1, 17) == 0 and lib.pauli_tile_valid(3, 2, 10) == 0
     o = opts(pauli, algo="fwht")
-    assert lib.pauli_decompose(FAKE_IN, 8, 1, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
-    assert lib.pauli_decompose(FAKE_IN, 15, 1, FAKE_IN + (1 << 40), ctypes.byref(o)) == EUNSUPPORTED
+    assert lib.pauli_decompose(FAKE_IN, 17, 1, FAKE_OUT, ctypes.byref(o)) == EINVAL
     small = opts(pauli, algo="fwht", ws=0x30000000, ws_bytes=1024)
     assert lib.pauli_decompose(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_pack(FAKE_IN, 10, 1, 0, ctypes.byref(o)) == EUNSUPPORTED

@@ -125,15 +125,42 @@ def test_round_trip_n14():
     assert ((G2 - Gd).abs().max() / Gd.abs().max()).item() <= 1e-12
 
 
-def test_unsupported_cases():
+@pytest.mark.parametrize("N", list(range(0, 9)))
+def test_small_orders_vs_oracle(N):
+    """Up to N = 8 a single kernel works in LDS: forward and adjoint."""
     p = lib()
-    for N in (8, 15):
-        G = torch.zeros(1 << N, 1 << N, dtype=torch.complex64, device="cuda")
-        with pytest.raises(p.PauliError) as ei:
-            p.decompose(G, algo="fwht")
-        assert ei.value.status == 2
-        del G
-    c = torch.zeros(4 ** 8, dtype=torch.complex64, device="cuda")
-    with pytest.raises(p.PauliError) as ei:
-        p.reconstruct(c, algo="fwht")
-    assert ei.value.status == 2
+    G = workloads.iid_complex(N, 1600 + N, np.complex128)
+    c = p.decompose(torch.from_numpy(G).cuda(), algo="fwht").cpu().numpy()
+    assert rel_err(c, oracle.decompose(G)) <= 1e-12
+    cc = workloads.iid_complex(N, 1650 + N, np.complex128).reshape(-1)
+    R = p.reconstruct(torch.from_numpy(cc).cuda(), algo="fwht").cpu().numpy()
+    if N <= 7:
+        assert rel_err(R, oracle.recompose(cc)) <= 1e-12
+    else:
+        rows, cols = workloads.sample_entries(1 << N, 1024, seed=1660)
+        ref = oracle.recompose_entries(cc, rows, cols)
+        assert rel_err(R[rows.astype(np.int64), cols.astype(np.int64)], ref) <= 1e-12
+
+
+def test_n15_exact_kronecker():
+    """N = 15 adds a pass over the top bit of i_h (N = 16, two bits, is in the
+    maximum-size tests).  G = A (x) B with small integer parts (A 128 x 128,
+    B 256 x 256) is exact in complex64 and its coefficients c(A) c(B) are
+    dyadic, so binary64 butterflies must reproduce them exactly, and
+    reconstruct must return G exactly."""
+    p = lib()
+    rng = np.random.default_rng(1715)
+    A = (rng.integers(-2, 3, (128, 128)) + 1j * rng.integers(-2, 3, (128, 128))).astype(np.complex64)
+    B = (rng.integers(-2, 3, (256, 256)) + 1j * rng.integers(-2, 3, (256, 256))).astype(np.complex64)
+    cA, cB = oracle.decompose(A), oracle.decompose(B)
+    Gd = torch.kron(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+    c = p.decompose(Gd, algo="fwht", out_dtype=torch.complex128)
+    ns = rng.integers(0, 4 ** 15, 65536, dtype=np.uint64)
+    ns[:2] = [0, 4 ** 15 - 1]
+    ref = cA[(ns >> 16).astype(np.int64)] * cB[(ns & 0xFFFF).astype(np.int64)]
+    got = c[torch.from_numpy(ns.astype(np.int64)).cuda()].cpu().numpy()
+    assert np.array_equal(got, ref)
+    G2 = p.reconstruct(c, algo="fwht", out_dtype=torch.complex128)
+    assert torch.equal(G2, Gd.to(torch.complex128))
+    del c, G2, Gd
+    p.release_workspace()

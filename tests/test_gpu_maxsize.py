@@ -6,8 +6,10 @@ G = A (x) B for two seeded 256 x 256 matrices with small integer parts, so
 G is exact in complex64, c(G)_n = c(A)_{n >> 16} c(B)_{n & 0xFFFF} exactly
 (the oracle's Kronecker pin), and every path computes these dyadic values
 without rounding: split-bf16 (the integers sit on the hi grid, FP32 sums
-stay below 2^24), binary32, and the binary64 string list.  Sampled outputs
-are therefore compared for equality.  Needs about 150 GiB of device memory.
+stay below 2^24), binary32, the binary64 string list and the binary64 fast
+Walsh-Hadamard path (whose 64 GiB intermediate replaces split-bf16's 48 GiB
+workspace).  Sampled outputs are therefore compared for equality.  Needs
+about 150 GiB of device memory.
 """
 import numpy as np
 import pytest
@@ -46,7 +48,7 @@ def kron_case():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fwht"])
 def test_n16_decompose_exact(kron_case, algo):
     p, G, ns, ref = kron_case
     print("N=16 decompose", algo, flush=True)
