@@ -33,6 +33,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Pauli coeffs/sec + % MFMA peak at N=14, split-BF16 vs FP64 at err≤1e-6"
+METRIC_HERM = ("Pauli coeffs/sec at N=14, Hermitian-aware split-BF16 (not the paper's general method), "
+               "err<=1e-6")
 PEAK_BF16_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2401_16378_amd/csrc/mfma_tile.hpp", "paper_2401_16378_amd/csrc/mfma.hip",
@@ -280,7 +282,8 @@ def bench_fwht(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["n14", "batch", "backward", "strings", "fwht"], default="n14")
+    ap.add_argument("--workload", choices=["n14", "hermitian", "batch", "backward", "strings", "fwht"],
+                    default="n14")
     ap.add_argument("--strings", type=int, default=65536, help="list length of the strings workload")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -333,14 +336,18 @@ def main():
     stream = torch.cuda.current_stream(dev)
     ws = pauli.workspace(a.algo, N, 1, dev)
     o = pauli._opts(a.algo, 0, 0, a.tile, ctypes.c_void_p(stream.cuda_stream), ws)
+    herm = a.workload == "hermitian"
+    if herm and a.algo != "split_bf16":
+        raise SystemExit("bench.py: the hermitian workload times the split_bf16 algorithm")
+    mode = 3 if herm else 0   # 3: pauli_decompose_hermitian split at the kernel boundary
 
     def step(mid=None):
         # pauli_pack + pauli_contract is pauli_decompose split at the kernel
         # boundary, so the contraction kernel can be timed on its own.
-        st = lib.pauli_pack(Gd.data_ptr(), N, 1, 0, ctypes.byref(o))
+        st = lib.pauli_pack(Gd.data_ptr(), N, 1, mode, ctypes.byref(o))
         if mid is not None:
             mid.record(stream)
-        st = st or lib.pauli_contract(N, 1, 0, out.data_ptr(), ctypes.byref(o))
+        st = st or lib.pauli_contract(N, 1, mode, out.data_ptr(), ctypes.byref(o))
         if st != 0:
             raise RuntimeError(pauli.last_error())
 
@@ -367,6 +374,11 @@ def main():
     planes = 3 if a.algo == "split_bf16" else 1
     flops_exec = 2.0 * 2.0 * planes * float(8 ** N)   # 2 (re,im) x 2 flop/MAC x planes x D^3
     flops_useful = 4.0 * float(8 ** N)
+    if herm:
+        # the Hermitian variant's algorithmic work: half of K for every flip mask
+        # (the first few flip-mask tiles walk all of K, so this undercounts)
+        flops_exec /= 2.0
+        flops_useful /= 2.0
     achieved = flops_exec / (mean_launch / 1000.0) / 1e12
     peak = PEAK_BF16_TFLOPS if a.algo == "split_bf16" else 157.3
     log("[bench] %.3f ms/step, pack %.3f ms, contraction %.3f ms, %.1f TFLOP/s executed"
@@ -403,20 +415,25 @@ def main():
         res["max_err_vs_oracle_sample"] = err_cpu
         log("[bench] oracle %.0f coeffs/s on %d cores, sample err %.3g" % (cpu["value"], cpu["cores"], err_cpu))
 
-    traffic = measured_traffic()
+    traffic = None if herm else measured_traffic()
+    if herm:
+        res["imag_exactly_zero"] = bool(np.all(c_bf16.imag == 0))
     line = {
-        "metric": METRIC, "value": value, "unit": "coeffs/s", "n_gpus": 1, "steps": a.steps,
+        "metric": METRIC_HERM if herm else METRIC, "value": value, "unit": "coeffs/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16" if a.algo == "split_bf16" else "f32", "data": "synthetic",
         "config": {"workload": "dense Pauli decomposition, N=%d (%dx%d complex64 Hermitian, "
-                               "G=(A+A^H)/2, A iid N(0,1)), all 4^%d coefficients, %s"
-                               % (N, 1 << N, 1 << N, N, a.algo), "N": N, "batch": 1,
+                               "G=(A+A^H)/2, A iid N(0,1)), all 4^%d coefficients, %s%s"
+                               % (N, 1 << N, 1 << N, N, a.algo,
+                                  ", Hermitian variant (half of K per flip mask, pauli_decompose_hermitian)"
+                                  if herm else ""), "N": N, "batch": 1,
                    "algo": a.algo, "tile": pauli.tile_selected(N, a.algo) if a.tile == 0 else a.tile},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "useful_frac": flops_useful / (mean_launch / 1000.0) / 1e12 / peak,
                      "launch_ms": mean_launch, "flops_per_launch": flops_exec,
-                     "kernel": "contract_kernel (split-bf16, tile %d)" % (pauli.tile_selected(N, a.algo) if a.tile == 0 else a.tile),
+                     "kernel": "contract_kernel%s (%s, tile %d)" % (" <..., HERM=true>" if herm else "", a.algo,
+                                                                     pauli.tile_selected(N, a.algo) if a.tile == 0 else a.tile),
                      "pack_ms": pack_ms},
         "cpu_baseline": cpu,
     }

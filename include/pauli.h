@@ -109,6 +109,27 @@ void pauli_opts_default(pauli_opts* o);
 int pauli_decompose(const void* G, int N, int batch, void* out, const pauli_opts* opts);
 
 /*
+ * pauli_decompose for Hermitian G (G[j][i] = conj(G[i][j])), whose
+ * coefficients are real (every Pauli string is Hermitian, so Tr(P_n G) is
+ * real).  Not the paper's method: it uses what the paper sets aside (its
+ * algorithm is for arbitrary dense matrices, Abstract).  For a flip mask x,
+ * v_x[i xor x] = conj(v_x[i]) in Eq. (c_def_in_terms_of_fn), so the sum over
+ * half of the i, doubled, gives the sum over all: the matrix-core contraction
+ * walks half of its K range for every block of 32 flip masks whose common
+ * high bits are large enough (all blocks but the first few), and every
+ * coefficient's imaginary part is written as exactly zero.
+ * algo SPLIT_BF16 or FP32 (others: PAULI_EUNSUPPORTED); register-ring tiles
+ * only (pauli_tile_valid_hermitian; a forced LDS-staged tile fails with
+ * PAULI_EINVAL).  Limits, layouts, workspace and stream as pauli_decompose.
+ * The Hermitian property is the caller's promise and is not checked: the
+ * kernel reads only one entry of most pairs (G[i xor x][i], G[i][i xor x]),
+ * so for a non-Hermitian G the result is unspecified (finite input still
+ * gives finite output, and no memory outside G, out and the workspace is
+ * touched).
+ */
+int pauli_decompose_hermitian(const void* G, int N, int batch, void* out, const pauli_opts* opts);
+
+/*
  * Recompose matrices from coefficients, G = sum_n c_n P_n (Eq. (1)), for
  * `batch` coefficient vectors of length 4^N stored back to back.  Exact
  * inverse of pauli_decompose up to rounding.  Same limits as above.
@@ -194,6 +215,10 @@ int pauli_tile_count(int algo);
  */
 int pauli_tile_valid(int algo, int tile, int N);
 
+/* 1 if tile id `tile` can run pauli_decompose_hermitian for `algo` at order
+ * N: a valid tile of pauli_tile_valid that is not LDS-staged (ids 1..12). */
+int pauli_tile_valid_hermitian(int algo, int tile, int N);
+
 /* Tile id pauli_decompose would use for (algo, N) right now. */
 int pauli_tile_selected(int algo, int N);
 
@@ -246,14 +271,16 @@ const char* pauli_last_error(void);
  * The two passes of the matrix-core algorithms (SPLIT_BF16, FP32), for
  * callers that schedule or time them separately; opts->workspace is required
  * (pauli_workspace_bytes).  mode: 0 = decompose, 1 = reconstruct,
- * 2 = backward.
+ * 2 = backward, 3 = decompose a Hermitian matrix (pauli_decompose_hermitian;
+ * its pack is that of mode 0, its contraction takes the register-ring tiles
+ * of pauli_tile_valid_hermitian).
  *   pauli_pack: gather the input of the contraction (for mode 0 the XOR
  *     diagonals G[i ^ x][i] of section 2, Eq. (c_def_in_terms_of_fn); for
  *     modes 1 and 2 the coefficient blocks) and store it, converted to the
  *     matrix-core operand format, in the workspace.
  *   pauli_contract: contract the packed operand against the +-1 sign matrix
  *     and write the output of pauli_decompose / pauli_reconstruct /
- *     pauli_decompose_backward.
+ *     pauli_decompose_backward / pauli_decompose_hermitian.
  * pauli_pack followed by pauli_contract on the same stream, workspace and
  * arguments equals the one-call entry point bit for bit.
  */

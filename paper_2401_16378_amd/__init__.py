@@ -51,6 +51,7 @@ EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_
            "pauli_batched_tile_count", "pauli_batched_tile_valid", "pauli_autotune_batched",
            "pauli_batched_tile_selected", "pauli_autotune", "pauli_tile_count", "pauli_tile_valid",
            "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_coeffs_at", "pauli_coeffs_at_backward",
+           "pauli_decompose_hermitian", "pauli_tile_valid_hermitian",
            "pauli_coeffs_at_workspace_bytes", "pauli_last_error", "pauli_version"]
 
 
@@ -66,7 +67,8 @@ def load_library(path: str = LIB_PATH):
         vp, ci, op = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Opts)
         lib.pauli_opts_default.argtypes = [op]
         lib.pauli_opts_default.restype = None
-        for name in ("pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward"):
+        for name in ("pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward",
+                     "pauli_decompose_hermitian"):
             getattr(lib, name).argtypes = [vp, ci, ci, vp, op]
             getattr(lib, name).restype = ci
         lib.pauli_decompose_batched.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(ci),
@@ -91,6 +93,8 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_tile_count.restype = ci
         lib.pauli_tile_valid.argtypes = [ci, ci, ci]
         lib.pauli_tile_valid.restype = ci
+        lib.pauli_tile_valid_hermitian.argtypes = [ci, ci, ci]
+        lib.pauli_tile_valid_hermitian.restype = ci
         lib.pauli_tile_selected.argtypes = [ci, ci]
         lib.pauli_tile_selected.restype = ci
         lib.pauli_pack.argtypes = [vp, ci, ci, ci, op]
@@ -196,6 +200,23 @@ def decompose(G: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: i
     out = torch.empty(G.shape[:-2] + (1 << (2 * N),), dtype=out_dtype, device=G.device)
     o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G), workspace(algo, N, batch, G.device))
     _check(load_library().pauli_decompose(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def decompose_hermitian(G: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: int = 0) -> torch.Tensor:
+    """decompose() for Hermitian G: half the matrix-core work for most flip
+    masks, coefficients with imaginary part exactly zero.  G being Hermitian
+    is the caller's promise (not checked; otherwise the result is
+    unspecified).  Not differentiable: use PauliDecompose for gradients."""
+    if G.requires_grad:
+        raise ValueError("decompose_hermitian has no gradient; use PauliDecompose")
+    G = _prep(G)
+    N = _qubits_of_matrix(G)
+    out_dtype = out_dtype or G.dtype
+    batch = G.numel() // (1 << (2 * N))
+    out = torch.empty(G.shape[:-2] + (1 << (2 * N),), dtype=out_dtype, device=G.device)
+    o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G), workspace(algo, N, batch, G.device))
+    _check(load_library().pauli_decompose_hermitian(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
     return out
 
 
@@ -341,6 +362,10 @@ def tile_valid(tile: int, N: int, algo: str = "split_bf16") -> bool:
     return bool(load_library().pauli_tile_valid(ALGOS[algo], tile, N))
 
 
+def tile_valid_hermitian(tile: int, N: int, algo: str = "split_bf16") -> bool:
+    return bool(load_library().pauli_tile_valid_hermitian(ALGOS[algo], tile, N))
+
+
 def batched_tile_valid(tile: int, algo: str = "split_bf16") -> bool:
     return bool(load_library().pauli_batched_tile_valid(ALGOS[algo], tile))
 
@@ -351,7 +376,7 @@ def tile_selected(N: int, algo: str = "split_bf16") -> int:
 
 from .autograd import PauliCoeffsAt, PauliDecompose  # noqa: E402
 
-__all__ = ["decompose", "reconstruct", "decompose_backward", "decompose_batched", "coeffs_at",
+__all__ = ["decompose", "decompose_hermitian", "tile_valid_hermitian", "reconstruct", "decompose_backward", "decompose_batched", "coeffs_at",
            "coeffs_at_backward", "PauliCoeffsAt", "autotune",
            "autotune_batched", "workspace", "release_workspace", "tile_valid", "batched_tile_valid", "tile_count", "tile_selected",
            "PauliDecompose", "PauliError", "load_library", "last_error", "ALGOS", "EXPORTS"]

@@ -156,8 +156,20 @@ hipError_t pool_for_current_device(hipMemPool_t* pool) {
     return hipSuccess;
 }
 
+// Tile for the Hermitian forward contraction: forced, else the tuned tile of
+// the general path when it is a register-ring tile, else the default.
+int pick_tile_hermitian(int algo, int N, int forced) {
+    const int planes = planes_of(algo);
+    if (forced > 0) return forced;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
+    auto it = g_tune.find({algo, N});
+    if (it != g_tune.end() && mfma_tile_valid_hermitian(planes, it->second, N)) return it->second;
+    return mfma_default_tile_hermitian(planes, N);
+}
+
 int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& o, double scale,
-        const char* fn) {
+        const char* fn, bool herm = false) {
     hipError_t e;
     hipStream_t s = (hipStream_t)o.stream;
     const bool in128 = o.in_dtype == PAULI_C128, out128 = o.out_dtype == PAULI_C128;
@@ -183,19 +195,23 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
         }
     } else {
         const int planes = planes_of(o.algo);
-        const int tile = pick_tile(o.algo, N, o.tile);
+        const int tile = herm ? pick_tile_hermitian(o.algo, N, o.tile) : pick_tile(o.algo, N, o.tile);
         const size_t need = mfma_workspace_bytes(planes, N, batch);
+        auto launch = [&](void* w) {
+            return herm ? launch_mfma_hermitian(planes, in, in128, out, out128, N, batch, scale, tile, w, s)
+                        : launch_mfma(dir, planes, in, in128, out, out128, N, batch, scale, tile, w, s);
+        };
         void* ws = o.workspace;
         if (ws) {
             if (o.workspace_bytes < need)
                 return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
                             o.workspace_bytes);
-            e = launch_mfma(dir, planes, in, in128, out, out128, N, batch, scale, tile, ws, s);
+            e = launch(ws);
         } else {
             hipMemPool_t pool;
             if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
             if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
-            e = launch_mfma(dir, planes, in, in128, out, out128, N, batch, scale, tile, ws, s);
+            e = launch(ws);
             const hipError_t ef = hipFreeAsync(ws, s);
             if (e == hipSuccess) e = ef;
         }
@@ -227,6 +243,24 @@ int pauli_decompose(const void* G, int N, int batch, void* out, const pauli_opts
     return run(FORWARD, G, N, batch, out, o, 1.0 / (double)(1u << N), "pauli_decompose");
 }
 
+int pauli_decompose_hermitian(const void* G, int N, int batch, void* out, const pauli_opts* opts) {
+    const char* fn = "pauli_decompose_hermitian";
+    pauli_opts o = resolve(opts);
+    if (valid_algo(o.algo) && !is_mfma(o.algo))
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no Hermitian variant (split-bf16 and fp32 have)", fn,
+                    o.algo);
+    const int forced = o.tile;
+    o.tile = 0;   // the general tile check below does not apply; the Hermitian one does
+    int st = check_common(G, N, batch, out, o, fn);
+    if (st != PAULI_OK) return st;
+    if (forced < 0) return fail(PAULI_EINVAL, "%s: tile=%d must be >= 0", fn, forced);
+    if (forced > 0 && !mfma_tile_valid_hermitian(planes_of(o.algo), forced, N))
+        return fail(PAULI_EINVAL, "%s: tile %d not valid for the Hermitian variant of algo %d at N=%d", fn, forced,
+                    o.algo, N);
+    o.tile = forced;
+    return run(FORWARD, G, N, batch, out, o, 1.0 / (double)(1u << N), fn, true);
+}
+
 int pauli_reconstruct(const void* c, int N, int batch, void* G, const pauli_opts* opts) {
     const pauli_opts o = resolve(opts);
     int st = check_common(c, N, batch, G, o, "pauli_reconstruct");
@@ -246,7 +280,7 @@ int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
 static int stage_check(int N, int batch, int mode, const pauli_opts& o, const char* fn) {
     if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
     if (batch < 1) return fail(PAULI_EINVAL, "%s: batch=%d must be >= 1", fn, batch);
-    if (mode < 0 || mode > 2) return fail(PAULI_EINVAL, "%s: mode %d not in {0, 1, 2}", fn, mode);
+    if (mode < 0 || mode > 3) return fail(PAULI_EINVAL, "%s: mode %d not in {0, 1, 2, 3}", fn, mode);
     if (o.algo != PAULI_ALGO_SPLIT_BF16 && o.algo != PAULI_ALGO_FP32)
         return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes", fn, o.algo);
     if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
@@ -256,7 +290,8 @@ static int stage_check(int N, int batch, int mode, const pauli_opts& o, const ch
         return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
                     o.workspace ? o.workspace_bytes : (size_t)0);
     if ((uintptr_t)o.workspace % 256) return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
-    if (o.tile < 0 || (o.tile > 0 && !mfma_tile_valid(planes_of(o.algo), o.tile, N)))
+    if (o.tile < 0 || (o.tile > 0 && !(mode == 3 ? mfma_tile_valid_hermitian(planes_of(o.algo), o.tile, N)
+                                                 : mfma_tile_valid(planes_of(o.algo), o.tile, N))))
         return fail(PAULI_EINVAL, "%s: tile %d not valid at N=%d", fn, o.tile, N);
     return PAULI_OK;
 }
@@ -271,7 +306,7 @@ int pauli_pack(const void* in, int N, int batch, int mode, const pauli_opts* opt
     const size_t bytes = ((size_t)1 << (2 * N)) * (size_t)batch * elem_bytes(o.in_dtype);
     if (overlaps(in, bytes, o.workspace, o.workspace_bytes))
         return fail(PAULI_EINVAL, "%s: workspace overlaps the input", fn);
-    const hipError_t e = launch_mfma_pack(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), in,
+    const hipError_t e = launch_mfma_pack(mode == 0 || mode == 3 ? FORWARD : ADJOINT, planes_of(o.algo), in,
                                           o.in_dtype == PAULI_C128, N, batch, o.workspace, (hipStream_t)o.stream);
     if (e != hipSuccess) return hip_fail(e, fn);
     g_last_error.clear();
@@ -290,9 +325,12 @@ int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts
         return fail(PAULI_EINVAL, "%s: workspace overlaps the output", fn);
     const double scale = mode == 1 ? 1.0 : 1.0 / (double)(1u << N);
     const hipError_t e =
-        launch_mfma_contract(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), o.workspace, out,
-                             o.out_dtype == PAULI_C128, N, batch, scale, pick_tile(o.algo, N, o.tile),
-                             (hipStream_t)o.stream);
+        mode == 3 ? launch_mfma_contract_hermitian(planes_of(o.algo), o.workspace, out, o.out_dtype == PAULI_C128, N,
+                                                   batch, scale, pick_tile_hermitian(o.algo, N, o.tile),
+                                                   (hipStream_t)o.stream)
+                  : launch_mfma_contract(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), o.workspace, out,
+                                         o.out_dtype == PAULI_C128, N, batch, scale, pick_tile(o.algo, N, o.tile),
+                                         (hipStream_t)o.stream);
     if (e != hipSuccess) return hip_fail(e, fn);
     g_last_error.clear();
     return PAULI_OK;
@@ -316,6 +354,11 @@ int pauli_tile_valid(int algo, int tile, int N) {
     if (algo == PAULI_ALGO_FWHT) return tile == 1 && fwht_supported(N) ? 1 : 0;
     if (!valid_algo(algo) || N < 0 || N > N_MAX) return 0;
     return mfma_tile_valid(planes_of(algo), tile, N) ? 1 : 0;
+}
+
+int pauli_tile_valid_hermitian(int algo, int tile, int N) {
+    if (!is_mfma(algo) || N < 0 || N > N_MAX) return 0;
+    return mfma_tile_valid_hermitian(planes_of(algo), tile, N) ? 1 : 0;
 }
 
 int pauli_tile_selected(int algo, int N) {

@@ -25,7 +25,7 @@ struct Params {
     double scale;
 };
 
-template <int PLANES, int RB, int WAVES, int DIR, int PF>
+template <int PLANES, int RB, int WAVES, int DIR, int PF, bool HERM = false>
 __global__ __launch_bounds__(WAVES * 64) void contract_kernel(Params prm) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     constexpr int MT = WAVES * RB * 32;
@@ -34,7 +34,19 @@ __global__ __launch_bounds__(WAVES * 64) void contract_kernel(Params prm) {
     const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
     const unsigned char* wsm = (const unsigned char*)prm.ws + (size_t)blockIdx.y * Dp * Dp * Pack<PLANES>::EB;
     unsigned char* dst = (unsigned char*)prm.out + (size_t)blockIdx.y * D * D * (prm.out128 ? 16 : 8);
-    contract_tile<PLANES, RB, WAVES, DIR, PF>(wsm, dst, prm.N, L / nMB, L % nMB, prm.scale, prm.out128, lds);
+    uint32_t xb = L / nMB;
+    if constexpr (HERM) {
+        // The Hermitian walk halves K only for xb >= (step K) / 32, so the
+        // first slabs cost twice as much: deal slabs to the XCDs round-robin
+        // (XCD k, which owns the slab range [k S, k S + S), gets slabs
+        // k, k + 8, ...) instead of in ranges, one long slab per XCD, first.
+        const uint32_t nXB = Dp / XT;
+        if ((gridDim.x & 7u) == 0 && (nXB & 7u) == 0) {
+            const uint32_t S = nXB >> 3;
+            xb = (xb % S) * 8 + xb / S;
+        }
+    }
+    contract_tile<PLANES, RB, WAVES, DIR, PF, HERM>(wsm, dst, prm.N, xb, L % nMB, prm.scale, prm.out128, lds);
 }
 
 template <int PLANES, int RB, int DIR, int AHEAD>
@@ -88,7 +100,7 @@ constexpr TileDesc TILES[] = {
 };
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
-template <int PLANES, int RB, int WAVES, int PF, int DIR>
+template <int PLANES, int RB, int WAVES, int PF, int DIR, bool HERM = false>
 hipError_t launch_contract(const Params& p, int batch, hipStream_t s) {
     if constexpr (!ring_tile_ok(PLANES, RB)) {
         return hipErrorInvalidValue;
@@ -96,7 +108,7 @@ hipError_t launch_contract(const Params& p, int batch, hipStream_t s) {
         constexpr int MT = WAVES * RB * 32;
         const uint32_t Dp = padded_dim(p.N);
         const uint32_t nMB = Dp / MT, nXB = Dp / XT;
-        auto kern = contract_kernel<PLANES, RB, WAVES, DIR, PF>;
+        auto kern = contract_kernel<PLANES, RB, WAVES, DIR, PF, HERM>;
         const int lds = WAVES * 1024 * (p.out128 ? 16 : 8);
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
@@ -105,26 +117,33 @@ hipError_t launch_contract(const Params& p, int batch, hipStream_t s) {
     }
 }
 
-template <int PLANES, int DIR>
+// HERM: the Hermitian forward contraction, register-ring tiles only.
+template <int PLANES, int DIR, bool HERM = false>
 hipError_t launch_tile(int tile, const Params& p, int batch, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_contract<PLANES, 4, 4, 4, DIR>(p, batch, s);
-        case 2: return launch_contract<PLANES, 4, 2, 4, DIR>(p, batch, s);
-        case 3: return launch_contract<PLANES, 2, 4, 4, DIR>(p, batch, s);
-        case 4: return launch_contract<PLANES, 2, 8, 2, DIR>(p, batch, s);
-        case 5: return launch_contract<PLANES, 1, 1, 2, DIR>(p, batch, s);
-        case 6: return launch_contract<PLANES, 1, 4, 2, DIR>(p, batch, s);
-        case 7: return launch_contract<PLANES, 4, 1, 4, DIR>(p, batch, s);
-        case 8: return launch_contract<PLANES, 2, 2, 4, DIR>(p, batch, s);
-        case 9: return launch_contract<PLANES, 1, 2, 2, DIR>(p, batch, s);
-        case 10: return launch_contract<PLANES, 4, 4, 8, DIR>(p, batch, s);
-        case 11: return launch_contract<PLANES, 4, 2, 8, DIR>(p, batch, s);
-        case 12: return launch_contract<PLANES, 2, 4, 8, DIR>(p, batch, s);
-        case 13: return launch_contract_lds<PLANES, 4, 3, DIR>(p, batch, s);
-        case 14: return launch_contract_lds<PLANES, 4, 7, DIR>(p, batch, s);
-        case 15: return launch_contract_lds<PLANES, 2, 3, DIR>(p, batch, s);
-        default: return hipErrorInvalidValue;
+        case 1: return launch_contract<PLANES, 4, 4, 4, DIR, HERM>(p, batch, s);
+        case 2: return launch_contract<PLANES, 4, 2, 4, DIR, HERM>(p, batch, s);
+        case 3: return launch_contract<PLANES, 2, 4, 4, DIR, HERM>(p, batch, s);
+        case 4: return launch_contract<PLANES, 2, 8, 2, DIR, HERM>(p, batch, s);
+        case 5: return launch_contract<PLANES, 1, 1, 2, DIR, HERM>(p, batch, s);
+        case 6: return launch_contract<PLANES, 1, 4, 2, DIR, HERM>(p, batch, s);
+        case 7: return launch_contract<PLANES, 4, 1, 4, DIR, HERM>(p, batch, s);
+        case 8: return launch_contract<PLANES, 2, 2, 4, DIR, HERM>(p, batch, s);
+        case 9: return launch_contract<PLANES, 1, 2, 2, DIR, HERM>(p, batch, s);
+        case 10: return launch_contract<PLANES, 4, 4, 8, DIR, HERM>(p, batch, s);
+        case 11: return launch_contract<PLANES, 4, 2, 8, DIR, HERM>(p, batch, s);
+        case 12: return launch_contract<PLANES, 2, 4, 8, DIR, HERM>(p, batch, s);
+        default: break;
     }
+    if constexpr (!HERM) {
+        switch (tile) {
+            case 13: return launch_contract_lds<PLANES, 4, 3, DIR>(p, batch, s);
+            case 14: return launch_contract_lds<PLANES, 4, 7, DIR>(p, batch, s);
+            case 15: return launch_contract_lds<PLANES, 2, 3, DIR>(p, batch, s);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int PLANES, int DIR>
@@ -153,6 +172,15 @@ int mfma_default_tile(int planes, int N) {
     if (N == 7) return 6;
     if (N == 6) return 9;
     return 5;
+}
+
+bool mfma_tile_valid_hermitian(int planes, int tile, int N) {
+    return mfma_tile_valid(planes, tile, N) && !TILES[tile - 1].lds;
+}
+
+int mfma_default_tile_hermitian(int planes, int N) {
+    if (planes == 1 && N >= 8) return 3;    // 2 x 32 rows per wave, 4 waves (register ring)
+    return mfma_default_tile(planes, N);
 }
 
 size_t mfma_workspace_bytes(int planes, int N, int batch) {
@@ -189,6 +217,24 @@ hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* 
     const hipError_t e = launch_mfma_pack(dir, planes, in, in_c128, N, batch, ws, stream);
     if (e != hipSuccess) return e;
     return launch_mfma_contract(dir, planes, ws, out, out_c128, N, batch, scale, tile, stream);
+}
+
+hipError_t launch_mfma_contract_hermitian(int planes, const void* ws, void* out, bool out_c128, int N, int batch,
+                                          double scale, int tile, hipStream_t stream) {
+    if (tile == 0) tile = mfma_default_tile_hermitian(planes, N);
+    if (!mfma_tile_valid_hermitian(planes, tile, N)) return hipErrorInvalidValue;
+    Params p{ws, out, N, out_c128 ? 1 : 0, scale};
+    return planes == 3 ? launch_tile<3, FORWARD, true>(tile, p, batch, stream)
+                       : launch_tile<1, FORWARD, true>(tile, p, batch, stream);
+}
+
+hipError_t launch_mfma_hermitian(int planes, const void* in, bool in_c128, void* out, bool out_c128, int N,
+                                 int batch, double scale, int tile, void* ws, hipStream_t stream) {
+    if (tile == 0) tile = mfma_default_tile_hermitian(planes, N);
+    if (!mfma_tile_valid_hermitian(planes, tile, N)) return hipErrorInvalidValue;
+    const hipError_t e = launch_mfma_pack(FORWARD, planes, in, in_c128, N, batch, ws, stream);
+    if (e != hipSuccess) return e;
+    return launch_mfma_contract_hermitian(planes, ws, out, out_c128, N, batch, scale, tile, stream);
 }
 
 

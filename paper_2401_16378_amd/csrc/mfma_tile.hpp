@@ -283,8 +283,11 @@ __device__ inline void flush_into(f32x16 (&tot)[1][RB][2], f32x16 (&acc)[1][RB][
 // accumulators, phase, scale, and an LDS-staged store of each 32x32 block as
 // one contiguous coefficient run (forward) or one aligned square of G
 // (adjoint).  lds holds WAVES * 1024 * esz bytes; all waves of the
-// workgroup must call it (it contains barriers).
-template <int PLANES, int RB, int DIR>
+// workgroup must call it (it contains barriers).  HERM (forward only): the
+// input is Hermitian, so the sum is real when popc(x&z) is even and
+// imaginary when it is odd; the other component, zero in exact arithmetic,
+// is dropped before the phase, which leaves every coefficient exactly real.
+template <int PLANES, int RB, int DIR, bool HERM = false>
 __device__ inline void store_tile(const f32x16 (&acc)[PLANES == 3 ? 2 : 1][RB][2], unsigned char* __restrict__ dst,
                                   int N, uint32_t X0, uint32_t Pw, double scale, int out128, unsigned char* lds) {
     constexpr int ACC = PLANES == 3 ? 2 : 1;
@@ -309,7 +312,12 @@ __device__ inline void store_tile(const f32x16 (&acc)[PLANES == 3 ? 2 : 1][RB][2
             im *= scale;
             uint32_t slot;
             if constexpr (DIR == FORWARD) {
-                rotate_minus_i(re, im, (uint32_t)__popc((X0 + l32) & (pb + pl)));
+                const uint32_t ny = (uint32_t)__popc((X0 + l32) & (pb + pl));
+                if constexpr (HERM) {
+                    if (ny & 1) re = 0.0;
+                    else im = 0.0;
+                }
+                rotate_minus_i(re, im, ny);
                 slot = pauli_index((uint32_t)l32, pl);           // offset inside the 1024-run
             } else {
                 slot = ((pl ^ (uint32_t)l32) << 5) | pl;        // (row, col) inside the 32x32 square
@@ -356,7 +364,19 @@ __device__ inline void store_tile(const f32x16 (&acc)[PLANES == 3 ? 2 : 1][RB][2
 // Dp < MT) skip the contraction but take part in the epilogue barriers.
 // wsm = the matrix's packed operand, dst = its output; lds holds
 // WAVES * 1024 * esz bytes of staging.
-template <int PLANES, int RB, int WAVES, int DIR, int PF>
+//
+// HERM (forward, Hermitian G): v_x[i ^ x] = conj(v_x[i]) and
+// (-1)^{popc((i^x)&z)} = (-1)^{popc(i&z)} (-1)^{popc(x&z)}, so the sum over
+// the pair {i, i^x} is s_i (v + conj v) = 2 s_i Re v when popc(x&z) is even
+// and s_i (v - conj v) = 2i s_i Im v when it is odd: the sum over the i
+// with one bit b of i clear, doubled, gives the whole sum, provided every
+// flip mask of the tile has bit b set.  The tile's flip masks X0..X0+31
+// (X0 = 32 xb) share the bits of X0; with b the top bit of X0 and
+// X0 >= GS*SK, the skipped bit of the slice index lies above the unrolled
+// step, so each step still walks GS (or GSL) consecutive slices with the
+// same compile-time sign pattern, half as many steps.  Tiles with smaller X0
+// walk the whole K range (the same result without the shortcut).
+template <int PLANES, int RB, int WAVES, int DIR, int PF, bool HERM = false>
 __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsigned char* __restrict__ dst,
                                      int N, uint32_t xb, uint32_t mb, double scale, int out128,
                                      unsigned char* lds) {
@@ -366,10 +386,31 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
     constexpr int U = 32 * RB / P::SK;                     // slices per sign group (32*RB K)
     constexpr int GS = 2 * (U > PF ? U : PF);              // slices per unrolled step
     static_assert(GS % U == 0 && GS % PF == 0, "ring depth and sign group must nest");
+    static_assert(!HERM || DIR == FORWARD, "the Hermitian shortcut is a forward-only property");
 
     const uint32_t Dp = padded_dim(N);
     const uint32_t nS = Dp / P::SK;
     const uint32_t X0 = xb * XT;
+
+    // Slices walked (nK) and the map from the walk index to the slice index
+    // (a zero inserted at bit beta) when only half of K is summed.
+    uint32_t nK = nS, beta = 0;
+    bool half = false;
+    if constexpr (HERM) {
+        if (X0 >= (uint32_t)(GS * P::SK)) {
+            half = true;
+            beta = (uint32_t)(31 - __builtin_clz(X0)) - (PLANES == 3 ? 4u : 3u);
+            nK = nS >> 1;
+        }
+    }
+    auto slice_of = [&](uint32_t c) -> uint32_t {
+        if constexpr (HERM) {
+            const uint32_t low = (1u << beta) - 1u;
+            return half ? (((c & ~low) << 1) | (c & low)) : c;
+        } else {
+            return c;
+        }
+    };
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
     const uint32_t Pw = mb * MT + wave * RB * 32;          // first row of this wave
@@ -426,17 +467,22 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
     auto main_loop = [&](auto gs_tag) {
     constexpr int GSX = decltype(gs_tag)::value;
 #pragma unroll
-    for (int k = 0; k < PF; ++k) fetch(k, (uint32_t)k < nS ? k : nS - 1);
+    for (int k = 0; k < PF; ++k) fetch(k, slice_of((uint32_t)k < nK ? k : nK - 1));
 
     bf16x8 Ap[2], An[2];
     float ts = 1.f;
-    for (uint32_t s0 = 0; s0 < nS; s0 += GSX) {
+    for (uint32_t s0 = 0; s0 < nK; s0 += GSX) {
+        const uint32_t sr = slice_of(s0);   // the step's GSX slices are sr, sr+1, ...
+        // first slice of the next step (the refills of this step's last PF
+        // slots read it and its successors); after the last step the refills
+        // are never used and reread this step's slices
+        const uint32_t sn = s0 + GSX < nK ? slice_of(s0 + GSX) : sr;
 #pragma unroll
         for (int uu = 0; uu < GSX; ++uu) {
             const int u = uu % U, slot = uu % PF;
             if (u == 0) {
                 // sign of this wave's rows against this group of 32*RB K values
-                const bool neg_grp = __popc((Pw >> 5) & (((s0 + uu) * P::SK) >> 5)) & 1;
+                const bool neg_grp = __popc((Pw >> 5) & (((sr + uu) * P::SK) >> 5)) & 1;
                 if constexpr (PLANES == 3) {
                     const uint32_t tm = neg_grp ? 0x80008000u : 0u;
 #pragma unroll
@@ -488,22 +534,31 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
             // here, PF slices ahead of their use, instead of letting the
             // scheduler sink them next to the MFMAs that consume them.
             __builtin_amdgcn_sched_barrier(0);
-            const uint32_t nxt = s0 + uu + PF;
-            fetch(slot, nxt < nS ? nxt : nS - 1);
+            if constexpr (HERM) {
+                // walk index s0+uu+PF lies in this step or the next, whose
+                // slices are consecutive: a constant offset from sr or sn
+                fetch(slot, uu + PF < GSX ? sr + (uint32_t)(uu + PF) : sn + (uint32_t)(uu + PF - GSX));
+            } else {
+                const uint32_t nxt = s0 + uu + PF;
+                fetch(slot, nxt < nK ? nxt : nK - 1);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
     }
     };
     constexpr int GSL = (PLANES == 3 && RB == 4 && DIR == FORWARD) ? 4 * GS : GS;
-    if (active && nS % GSL == 0) {
+    // a half walk nests steps of GS slices (2^beta >= GS); the long step needs 2^beta >= GSL
+    const bool long_ok = !half || (1u << beta) >= (uint32_t)GSL;
+    if (active && nK % GSL == 0 && long_ok) {
         main_loop(std::integral_constant<int, GSL>{});
-    } else if (active && nS % GS == 0) {
+    } else if (active && nK % GS == 0) {
         main_loop(std::integral_constant<int, GS>{});
     } else if (active) {
         // Fewer K slices than one unrolled group (small matrices in a batch
         // whose tile shape was chosen for larger ones): one slice at a time,
-        // signs evaluated at run time.
-        for (uint32_t s = 0; s < nS; ++s) {
+        // signs evaluated at run time.  (A half walk never lands here.)
+        for (uint32_t c = 0; c < nK; ++c) {
+            const uint32_t s = slice_of(c);
             u32x4 B[P::NPL];
             const unsigned char* p = wsx + (size_t)s * P::SLICE_BYTES;
 #pragma unroll
@@ -533,16 +588,17 @@ __device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsi
                 }
             }
             if constexpr (PLANES == 1) {
-                if ((s + 1) % FLUSH_SLICES == 0) flush_into<RB>(tot, acc);
+                if ((c + 1) % FLUSH_SLICES == 0) flush_into<RB>(tot, acc);
             }
         }
     }
 
+    const double sc = half ? 2.0 * scale : scale;   // a half walk sums one member of each pair
     if constexpr (PLANES == 1) {
         flush_into<RB>(tot, acc);
-        store_tile<PLANES, RB, DIR>(tot, dst, N, X0, Pw, scale, out128, lds);
+        store_tile<PLANES, RB, DIR, HERM>(tot, dst, N, X0, Pw, sc, out128, lds);
     } else {
-        store_tile<PLANES, RB, DIR>(acc, dst, N, X0, Pw, scale, out128, lds);
+        store_tile<PLANES, RB, DIR, HERM>(acc, dst, N, X0, Pw, sc, out128, lds);
     }
 }
 

@@ -62,7 +62,8 @@ FAKE_IN = 0x10000000      # never dereferenced: every call below fails validatio
 FAKE_OUT = 0x20000000
 
 
-@pytest.mark.parametrize("fn", ["pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward"])
+@pytest.mark.parametrize("fn", ["pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward",
+                                "pauli_decompose_hermitian"])
 def test_validation_errors(lib, pauli, fn):
     f = getattr(lib, fn)
     o = opts(pauli)
@@ -155,6 +156,10 @@ def test_pass_entry_points_validation(lib, pauli):
     ws = opts(pauli, ws=0x30000000, ws_bytes=12 * 4 ** 10)
     assert lib.pauli_pack(None, 10, 1, 0, ctypes.byref(ws)) == EINVAL
     assert lib.pauli_contract(10, 1, 0, 0x30000000 + 4096, ctypes.byref(ws)) == EINVAL   # overlaps workspace
+    # mode 3 (Hermitian decomposition) takes the register-ring tiles only
+    lds_tile = opts(pauli, tile=13, ws=0x30000000, ws_bytes=12 * 4 ** 10)
+    assert lib.pauli_contract(10, 1, 3, FAKE_OUT, ctypes.byref(lds_tile)) == EINVAL
+    assert lib.pauli_pack(FAKE_IN, 10, 1, 4, ctypes.byref(ws)) == EINVAL
 
 
 def test_autotune_validation(lib, pauli):
@@ -210,6 +215,28 @@ def test_fwht_algo_queries(lib, pauli):
     assert lib.pauli_decompose(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_pack(FAKE_IN, 10, 1, 0, ctypes.byref(o)) == EUNSUPPORTED
     assert lib.pauli_autotune(9, 10, ctypes.byref(o)) == EUNSUPPORTED
+
+
+def test_hermitian_queries_and_validation(lib, pauli):
+    """The Hermitian variant runs on the matrix-core algorithms' register-ring
+    tiles only; the other algorithms and the LDS-staged tiles are refused
+    before any device call."""
+    f = lib.pauli_decompose_hermitian
+    for algo in ("fp64_gray", "fwht"):
+        assert f(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(opts(pauli, algo=algo))) == EUNSUPPORTED
+    for t in range(1, 13):
+        assert lib.pauli_tile_valid_hermitian(2, t, 10) == lib.pauli_tile_valid(2, t, 10) == 1
+    for t in (13, 14, 15):
+        assert lib.pauli_tile_valid(2, t, 10) == 1 and lib.pauli_tile_valid_hermitian(2, t, 10) == 0
+        assert f(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(opts(pauli, tile=t))) == EINVAL
+        assert f(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(opts(pauli, algo="fp32", tile=t))) == EINVAL
+    for t in (1, 2, 7, 10, 11):
+        assert lib.pauli_tile_valid_hermitian(1, t, 12) == 0
+    for t in (3, 4, 5, 6, 8, 9, 12):
+        assert lib.pauli_tile_valid_hermitian(1, t, 12) == 1
+    assert lib.pauli_tile_valid_hermitian(0, 1, 10) == 0 and lib.pauli_tile_valid_hermitian(3, 1, 10) == 0
+    assert lib.pauli_tile_valid_hermitian(2, 1, 8) == 0 and lib.pauli_tile_valid_hermitian(2, 1, 17) == 0
+    assert f(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(opts(pauli, tile=-1))) == EINVAL
 
 
 def test_coeffs_at_backward_validation(lib, pauli):
