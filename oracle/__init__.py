@@ -10,6 +10,9 @@ Functions follow the paper:
   coeff_slow   -- the natural-order variant with lambda in full (Fig. 1b)
   decompose    -- all 4^N coefficients, Eq. (1); optional thread fan-out over
                   disjoint ranges of n (coefficients are independent, section 3)
+  decompose_qgray -- all 4^N coefficients with n in quaternary Gray order and
+                  the recurrence of lambda_0 across n (section 2), serial
+  quaternary_gray -- the k-th string of that order
   recompose    -- sum_n c_n P_n, Eq. (1), from Eq. (pauli_tensor_elems_bitwise)
   grad_entries -- adjoint of the decomposition at chosen entries of G
 """
@@ -61,6 +64,10 @@ def _load():
         lib.oracle_decompose_range.restype = None
         lib.oracle_decompose.argtypes = [dp, ci, dp]
         lib.oracle_decompose.restype = None
+        lib.oracle_decompose_qgray.argtypes = [dp, ci, dp]
+        lib.oracle_decompose_qgray.restype = None
+        lib.oracle_quaternary_gray.argtypes = [u64, ci]
+        lib.oracle_quaternary_gray.restype = u64
         lib.oracle_coeffs_at.argtypes = [dp, ci, up, i64, dp]
         lib.oracle_coeffs_at.restype = None
         lib.oracle_pauli_element.argtypes = [u64, ci, u64, u64, dp]
@@ -145,6 +152,20 @@ def decompose(G: np.ndarray, threads: int = 1) -> np.ndarray:
     for th in ths:
         th.join()
     return out
+
+
+def decompose_qgray(G: np.ndarray) -> np.ndarray:
+    """All 4^N coefficients, strings walked in quaternary Gray order with the
+    across-n recurrence of lambda_0 (serial; equal to decompose bit for bit)."""
+    G = _as_c128(G)
+    N = _check_square(G)
+    out = np.zeros(1 << (2 * N), dtype=np.complex128)
+    _load().oracle_decompose_qgray(_dptr(G), N, _dptr(out))
+    return out
+
+
+def quaternary_gray(k: int, N: int) -> int:
+    return int(_load().oracle_quaternary_gray(k, N))
 
 
 def coeffs_at(G: np.ndarray, ns, threads: int = 1) -> np.ndarray:

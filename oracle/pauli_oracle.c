@@ -116,17 +116,14 @@ static cplx load(const double* G, uint64_t D, uint64_t r, uint64_t c) {
 }
 
 /*
- * One coefficient by the paper's algorithm (section 3, Fig. 1b, "Fast"):
- * evaluate Eq. (c_def_in_terms_of_fn) with i enumerated in Gray-code order,
- * lambda_0 computed in full and every later lambda obtained from the
- * previous one by the one-beta recurrence of Eq. (lambda_recurrence_over_i);
- * the sum is divided by 2^N at the end.  The paper's first accumulation
- * names an undefined "matrix"; it is read as G, i.e. the term G[m][0].
+ * Eq. (c_def_in_terms_of_fn) for string n with XY mask m, given lambda_0^(n):
+ * i enumerated in Gray-code order, every later lambda obtained from the
+ * previous one by the one-beta recurrence of Eq. (lambda_recurrence_over_i),
+ * the sum divided by 2^N at the end.  The paper's first accumulation names
+ * an undefined "matrix"; it is read as G, i.e. the term G[m][0].
  */
-void oracle_coeff_fast(const double* G, int N, uint64_t n, double* out) {
+static void gray_sum(const double* G, int N, uint64_t n, uint64_t m, cplx l, double* out) {
     uint64_t dim = (uint64_t)1 << N;
-    uint64_t m = oracle_xy_mask(n, N);
-    cplx l = get_lambda(n, 0, m, N);
     cplx c = cmul(l, load(G, dim, m, 0));
     for (uint64_t k = 1; k < dim; k++) {
         uint64_t i = gray_code(k);
@@ -139,6 +136,68 @@ void oracle_coeff_fast(const double* G, int N, uint64_t n, double* out) {
     }
     out[0] = c.re / (double)dim;
     out[1] = c.im / (double)dim;
+}
+
+/*
+ * One coefficient by the paper's algorithm (section 3, Fig. 1b, "Fast"):
+ * lambda_0 computed in full as the N-term product, then the Gray-order sum.
+ */
+void oracle_coeff_fast(const double* G, int N, uint64_t n, double* out) {
+    uint64_t m = oracle_xy_mask(n, N);
+    gray_sum(G, N, n, m, get_lambda(n, 0, m, N), out);
+}
+
+/*
+ * k-th string of the reflected quaternary Gray code over N base-4 digits
+ * (section 2, enumeration of the P_n by the quaternary Gray code): the
+ * sequence runs the lowest digit 0,1,2,3 and then back 3,2,1,0 each time
+ * the digit above advances, so digit t of the code is digit t of k when
+ * digit t+1 of k is even and 3 minus it when that digit is odd.  Consecutive
+ * codes differ in one digit, by one step (I-X, X-Y or Y-Z).
+ */
+uint64_t oracle_quaternary_gray(uint64_t k, int N) {
+    uint64_t g = 0;
+    for (int t = 0; t < N; t++) {
+        int d = oracle_pauli_flag(k, t);
+        int up = t + 1 < N ? oracle_pauli_flag(k, t + 1) : 0;
+        int e = (up & 1) ? 3 - d : d;
+        g |= (uint64_t)e << (2 * t);
+    }
+    return g;
+}
+
+/*
+ * All 4^N coefficients with the strings enumerated in quaternary Gray order
+ * and the recurrence across n of section 2: from string n to the next
+ * string n', which differs at one operator position t, the XY mask keeps
+ * bit t when that operator changes between identity and Z or between X
+ * and Y and flips it otherwise, and
+ *     lambda_0^(n') = lambda_0^(n) beta^(n',t)_{0, m'_[t]} / beta^(n,t)_{0, m_[t]},
+ * so lambda_0 is never formed as an N-term product (the serial saving the
+ * paper notes).  Each coefficient's sum over i is the Gray-order sum of
+ * oracle_coeff_fast; since every lambda is exactly one of +-1, +-i, the
+ * result equals oracle_decompose bit for bit.  out is indexed by n.
+ */
+void oracle_decompose_qgray(const double* G, int N, double* out) {
+    uint64_t total = (uint64_t)1 << (2 * N);
+    uint64_t n = 0, m = 0;          /* the identity string: no X/Y, lambda_0 = 1 */
+    cplx l = {1.0, 0.0};
+    gray_sum(G, N, n, m, l, out);
+    for (uint64_t k = 1; k < total; k++) {
+        uint64_t nn = oracle_quaternary_gray(k, N);
+        int t = 0;
+        while (oracle_pauli_flag(n, t) == oracle_pauli_flag(nn, t)) t++;
+        int fo = oracle_pauli_flag(n, t), fn = oracle_pauli_flag(nn, t);
+        int same_mask = (fo == 0 && fn == 3) || (fo == 3 && fn == 0) || (fo == 1 && fn == 2) ||
+                        (fo == 2 && fn == 1);
+        uint64_t mm = same_mask ? m : (m ^ ((uint64_t)1 << t));
+        cplx bnew = PAULI[fn][0][get_bit(mm, t)];
+        cplx bold = PAULI[fo][0][get_bit(m, t)];
+        l = cmul(l, cdiv_unit(bnew, bold));
+        n = nn;
+        m = mm;
+        gray_sum(G, N, n, m, l, out + 2 * n);
+    }
 }
 
 /* The paper's comparison algorithm (Fig. 1b, "Slow"): natural order of i,

@@ -251,3 +251,55 @@ def test_threaded_driver_matches_serial():
 def test_n0():
     G = np.array([[2.5 - 1.0j]])
     np.testing.assert_array_equal(oracle.decompose(G), np.array([2.5 - 1.0j]))
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
+def test_quaternary_gray_order(N):
+    """The quaternary Gray enumeration (section 2) visits every string once,
+    starts at the identity, and changes exactly one operator per step, to an
+    adjacent flag (I-X, X-Y or Y-Z)."""
+    seq = [oracle.quaternary_gray(k, N) for k in range(4 ** N)]
+    assert seq[0] == 0
+    assert sorted(seq) == list(range(4 ** N))
+    for a, b in zip(seq, seq[1:]):
+        diff = [t for t in range(N) if oracle.pauli_flag(a, t) != oracle.pauli_flag(b, t)]
+        assert len(diff) == 1
+        t = diff[0]
+        assert abs(oracle.pauli_flag(a, t) - oracle.pauli_flag(b, t)) == 1
+
+
+def test_quaternary_gray_two_digits():
+    """The reflected order for two operators written out: the low digit runs
+    up, then down each time the high digit advances."""
+    want = [0x0, 0x1, 0x2, 0x3, 0x7, 0x6, 0x5, 0x4, 0x8, 0x9, 0xA, 0xB, 0xF, 0xE, 0xD, 0xC]
+    # digits (high, low) -> n = 4 * high + low
+    assert [oracle.quaternary_gray(k, 2) for k in range(16)] == [4 * (w >> 2) + (w & 3) for w in want]
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 3, 4, 5, 6])
+def test_qgray_decomposition_bitexact(N):
+    """The across-n recurrence of lambda_0 only changes how lambda_0 is
+    formed; lambda stays exactly in {+-1, +-i}, so every coefficient equals
+    the per-string evaluation bit for bit (and brute force to rounding)."""
+    G = workloads.iid_complex(N, 900 + N)
+    c = oracle.decompose_qgray(G)
+    np.testing.assert_array_equal(c, oracle.decompose(G))
+    if N <= 3:
+        ref = np.array([pr.brute_coeff(G, n) for n in range(4 ** N)])
+        assert rel_err(c, ref) < 1e-14
+
+
+def test_qgray_eq2_example():
+    """Eq. (2)'s ordering: 1(x)X is string 1, X(x)1 string 4, Y(x)Y string
+    10 and Z(x)Z string 15, so G = 2 1(x)X - 3i X(x)1 + Y(x)Y + 0.5 Z(x)Z
+    decomposes to exactly those four coefficients and zeros (Eq. (3)
+    matrices)."""
+    I2 = np.eye(2, dtype=np.complex128)
+    X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+    Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+    G = 2 * np.kron(I2, X) - 3j * np.kron(X, I2) + np.kron(Y, Y) + 0.5 * np.kron(Z, Z)
+    c = oracle.decompose_qgray(G)
+    want = np.zeros(16, dtype=np.complex128)
+    want[1], want[4], want[10], want[15] = 2.0, -3j, 1.0, 0.5
+    np.testing.assert_array_equal(c, want)
