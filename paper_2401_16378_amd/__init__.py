@@ -335,6 +335,28 @@ def decompose_batched(mats, algo: str = "split_bf16", outs=None, tile: int = 0):
     return outs
 
 
+class BatchPlan:
+    """decompose_batched for a fixed list of matrices and outputs, marshalled
+    once: run() is one library call (a descriptor copy and a HIP graph
+    replay), for loops that decompose the same buffers again and again.
+    The tensors must stay alive and keep their storage while the plan is
+    used; run() enqueues on torch's current stream of their device."""
+
+    def __init__(self, mats, algo: str = "split_bf16", outs=None, tile: int = 0):
+        if len(mats) == 0:
+            raise ValueError("BatchPlan needs at least one matrix")
+        (self.mats, self.outs, self.count, self._Na, self._Gp, self._Op,
+         self._ws) = _batch_args(mats, algo, outs)
+        self._dev = self.mats[0].device
+        self._o = _opts(algo, 0, 0, tile, _stream(self.mats[0]), self._ws)
+        self._lib = load_library()
+
+    def run(self):
+        self._o.stream = ctypes.c_void_p(torch.cuda.current_stream(self._dev).cuda_stream)
+        _check(self._lib.pauli_decompose_batched(self.count, self._Gp, self._Na, self._Op, ctypes.byref(self._o)))
+        return self.outs
+
+
 def autotune_batched(mats, algo: str = "split_bf16", outs=None) -> int:
     """Time every persistent tile shape on this batch and keep the fastest for
     its N list; returns the chosen tile (outputs hold the decomposition)."""
@@ -376,7 +398,7 @@ def tile_selected(N: int, algo: str = "split_bf16") -> int:
 
 from .autograd import PauliCoeffsAt, PauliDecompose  # noqa: E402
 
-__all__ = ["decompose", "decompose_hermitian", "tile_valid_hermitian", "reconstruct", "decompose_backward", "decompose_batched", "coeffs_at",
+__all__ = ["BatchPlan", "decompose", "decompose_hermitian", "tile_valid_hermitian", "reconstruct", "decompose_backward", "decompose_batched", "coeffs_at",
            "coeffs_at_backward", "PauliCoeffsAt", "autotune",
            "autotune_batched", "workspace", "release_workspace", "tile_valid", "batched_tile_valid", "tile_count", "tile_selected",
            "PauliDecompose", "PauliError", "load_library", "last_error", "ALGOS", "EXPORTS"]

@@ -5,12 +5,15 @@
 // The host builds a descriptor table in device memory: one entry per matrix,
 // in decreasing order of N (longest-processing-time first), with the matrix's
 // packed-operand offset and its first pack tile and first output tile in the
-// batch-wide numbering.  The pack kernel maps its block index to (matrix,
-// tile) by binary search over the first-tile fields.  The contraction kernel
-// is persistent: each workgroup takes output tiles from a single atomic
-// counter until the list is exhausted, so every workgroup ends once the
-// counter passes the last tile and the grid drains.  A one-thread kernel
-// zeroes the counter before each contraction launch (no memset node, so the
+// batch-wide numbering, followed by the slot of every output tile.  The pack
+// kernel maps its block index to (matrix, tile) by binary search over the
+// first-tile fields.  The contraction kernel is persistent: each workgroup
+// takes output tiles from a single atomic counter until the list is
+// exhausted, so every workgroup ends once the counter passes the last tile
+// and the grid drains.  It claims its next tile when it starts the current
+// one (the atomic's round trip then overlaps the contraction) and finds a
+// tile's matrix with one read of the slot table.  A one-thread kernel zeroes
+// the counter before each contraction launch (no memset node, so the
 // sequence can be captured in a HIP graph and replayed).
 #include "mfma_tile.hpp"
 
@@ -19,13 +22,12 @@ namespace {
 
 using namespace mfma;
 
-// Slot of the matrix owning batch-wide index t (first_of[k] increasing).
-__device__ inline int find_slot(const BatchItem* items, int count, uint32_t t, bool pack) {
+// Slot of the matrix owning batch-wide pack tile t (pack0 increasing).
+__device__ inline int find_slot(const BatchItem* items, int count, uint32_t t) {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const uint32_t first = pack ? items[mid].pack0 : items[mid].tile0;
-        if (first <= t) lo = mid;
+        if (items[mid].pack0 <= t) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -35,7 +37,7 @@ template <int PLANES>
 __global__ __launch_bounds__(256) void pack_batched_kernel(const BatchItem* __restrict__ items, int count,
                                                            unsigned char* __restrict__ ws) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES>()];
-    const int k = find_slot(items, count, blockIdx.x, true);
+    const int k = find_slot(items, count, blockIdx.x);
     const BatchItem it = items[k];
     pack_tile<PLANES, FORWARD, false>((const unsigned char*)it.in, ws + it.ws_off, it.n,
                                       blockIdx.x - it.pack0, lds);
@@ -46,74 +48,106 @@ __global__ void reset_counter_kernel(unsigned int* counter) {
 }
 
 template <int PLANES, int RB, int WAVES, int PF>
-__global__ __launch_bounds__(WAVES * 64) void contract_batched_kernel(const BatchItem* __restrict__ items,
-                                                                      int count, uint32_t total,
-                                                                      const unsigned char* __restrict__ ws,
-                                                                      unsigned int* __restrict__ counter) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    __shared__ uint32_t next;
+__device__ __attribute__((always_inline)) inline void batched_loop(const BatchItem* __restrict__ items, const uint32_t* __restrict__ tile_slot,
+                                    uint32_t total, const unsigned char* __restrict__ ws,
+                                    unsigned int* __restrict__ counter, unsigned char* lds, uint32_t& next) {
     constexpr int MT = WAVES * RB * 32;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
-        __syncthreads();
-        const uint32_t t = next;
-        __syncthreads();           // everyone has read `next` before it is rewritten
-        if (t >= total) break;     // uniform: every workgroup leaves once the list is done
-        const int k = find_slot(items, count, t, false);
-        const BatchItem it = items[k];
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+    __syncthreads();
+    uint32_t t = next;
+    __syncthreads();                   // everyone has read `next` before it is rewritten
+    while (t < total) {                // uniform: every workgroup leaves once the list is done
+        uint32_t claimed = 0;
+        if (threadIdx.x == 0) claimed = atomicAdd(counter, 1u);   // read only after this tile
+        const BatchItem it = items[tile_slot[t]];
         const uint32_t Dp = padded_dim(it.n);
         const uint32_t nMB = Dp > (uint32_t)MT ? Dp / MT : 1u;
         const uint32_t local = t - it.tile0;
         contract_tile<PLANES, RB, WAVES, FORWARD, PF>(ws + it.ws_off, (unsigned char*)it.out, it.n,
                                                       local / nMB, local % nMB, 1.0 / (double)(1u << it.n),
                                                       0, lds);
+        if (threadIdx.x == 0) next = claimed;   // the epilogue ended with a barrier
+        __syncthreads();
+        t = next;
+        __syncthreads();
     }
 }
 
-// Tile shapes the persistent kernel can run with: (RB, WAVES, PF).
+template <int PLANES, int RB, int WAVES, int PF>
+__global__ __launch_bounds__(WAVES * 64) void contract_batched_kernel(const BatchItem* __restrict__ items,
+                                                                      const uint32_t* __restrict__ tile_slot,
+                                                                      uint32_t total,
+                                                                      const unsigned char* __restrict__ ws,
+                                                                      unsigned int* __restrict__ counter) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    __shared__ uint32_t next;
+    batched_loop<PLANES, RB, WAVES, PF>(items, tile_slot, total, ws, counter, lds, next);
+}
+
+// The same loop with the registers budgeted for two waves per SIMD, so that
+// a second workgroup's contraction covers one's change-over between tiles.
+template <int PLANES, int RB, int WAVES, int PF>
+__global__ __launch_bounds__(WAVES * 64, 2) void contract_batched2_kernel(const BatchItem* __restrict__ items,
+                                                                          const uint32_t* __restrict__ tile_slot,
+                                                                          uint32_t total,
+                                                                          const unsigned char* __restrict__ ws,
+                                                                          unsigned int* __restrict__ counter) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    __shared__ uint32_t next;
+    batched_loop<PLANES, RB, WAVES, PF>(items, tile_slot, total, ws, counter, lds, next);
+}
+
+// Tile shapes the persistent kernel can run with: (RB, WAVES, PF, waves per
+// SIMD the registers are budgeted for).
 struct BTile {
-    int rb, waves, pf;
+    int rb, waves, pf, occ;
 };
 constexpr BTile BTILES[] = {
-    {2, 4, 4},  // 1: 256 rows per output tile
-    {1, 4, 2},  // 2: 128 rows
-    {4, 4, 4},  // 3: 512 rows
-    {1, 2, 2},  // 4: 64 rows
+    {2, 4, 4, 1},  // 1: 256 rows per output tile
+    {1, 4, 2, 1},  // 2: 128 rows
+    {4, 4, 4, 1},  // 3: 512 rows
+    {1, 2, 2, 1},  // 4: 64 rows
+    {2, 4, 2, 2},  // 5: 256 rows, shallower ring, two workgroups per CU
 };
 constexpr int NBTILES = sizeof(BTILES) / sizeof(BTILES[0]);
 
-template <int PLANES, int RB, int WAVES, int PF>
-hipError_t launch_contract_batched(const BatchItem* items, int count, uint32_t total, const unsigned char* ws,
-                                   unsigned int* counter, hipStream_t s) {
+template <int PLANES, int RB, int WAVES, int PF, int OCC>
+hipError_t launch_contract_batched(const BatchItem* items, const uint32_t* tile_slot, uint32_t total,
+                                   const unsigned char* ws, unsigned int* counter, hipStream_t s) {
     if constexpr (!ring_tile_ok(PLANES, RB)) {
         return hipErrorInvalidValue;
     } else {
-        auto kern = contract_batched_kernel<PLANES, RB, WAVES, PF>;
-        const int lds = WAVES * 1024 * 8;
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) return e;
-        int dev = 0, cus = 0, per_cu = 0;
-        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WAVES * 64, lds)) !=
-            hipSuccess)
-            return e;
-        if (per_cu < 1) per_cu = 1;
-        uint32_t grid = (uint32_t)cus * (uint32_t)per_cu;
-        if (grid > total) grid = total;   // never more workgroups than tiles
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES * 64), lds, s, items, count, total, ws, counter);
-        return hipGetLastError();
+        auto launch = [&](auto kern) -> hipError_t {
+            const int lds = WAVES * 1024 * 8;
+            hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e != hipSuccess) return e;
+            int dev = 0, cus = 0, per_cu = 0;
+            if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+            if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+                return e;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WAVES * 64, lds)) !=
+                hipSuccess)
+                return e;
+            if (per_cu < 1) per_cu = 1;
+            uint32_t grid = (uint32_t)cus * (uint32_t)per_cu;
+            if (grid > total) grid = total;   // never more workgroups than tiles
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES * 64), lds, s, items, tile_slot, total, ws, counter);
+            return hipGetLastError();
+        };
+        if constexpr (OCC == 2) return launch(contract_batched2_kernel<PLANES, RB, WAVES, PF>);
+        else return launch(contract_batched_kernel<PLANES, RB, WAVES, PF>);
     }
 }
 
 template <int PLANES>
-hipError_t launch_contract_btile(int btile, const BatchItem* items, int count, uint32_t total,
+hipError_t launch_contract_btile(int btile, const BatchItem* items, const uint32_t* tile_slot, uint32_t total,
                                  const unsigned char* ws, unsigned int* counter, hipStream_t s) {
     switch (btile) {
-        case 1: return launch_contract_batched<PLANES, 2, 4, 4>(items, count, total, ws, counter, s);
-        case 2: return launch_contract_batched<PLANES, 1, 4, 2>(items, count, total, ws, counter, s);
-        case 3: return launch_contract_batched<PLANES, 4, 4, 4>(items, count, total, ws, counter, s);
-        case 4: return launch_contract_batched<PLANES, 1, 2, 2>(items, count, total, ws, counter, s);
+        case 1: return launch_contract_batched<PLANES, 2, 4, 4, 1>(items, tile_slot, total, ws, counter, s);
+        case 2: return launch_contract_batched<PLANES, 1, 4, 2, 1>(items, tile_slot, total, ws, counter, s);
+        case 3: return launch_contract_batched<PLANES, 4, 4, 4, 1>(items, tile_slot, total, ws, counter, s);
+        case 4: return launch_contract_batched<PLANES, 1, 2, 2, 1>(items, tile_slot, total, ws, counter, s);
+        case 5: return launch_contract_batched<PLANES, 2, 4, 2, 2>(items, tile_slot, total, ws, counter, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -140,8 +174,8 @@ size_t batched_packed_bytes(int planes, int n) {
     return Dp * Dp * (size_t)(planes == 3 ? mfma::Pack<3>::EB : mfma::Pack<1>::EB);
 }
 
-hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, int count, uint32_t pack_total,
-                          uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
+hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, const uint32_t* tile_slot_dev, int count,
+                          uint32_t pack_total, uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
                           hipStream_t stream) {
     if (!batched_tile_valid(planes, btile)) return hipErrorInvalidValue;
     if (planes == 3)
@@ -152,8 +186,9 @@ hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, int
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, counter_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return planes == 3 ? launch_contract_btile<3>(btile, items_dev, count, tile_total, packed, counter_dev, stream)
-                       : launch_contract_btile<1>(btile, items_dev, count, tile_total, packed, counter_dev, stream);
+    return planes == 3
+               ? launch_contract_btile<3>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, stream)
+               : launch_contract_btile<1>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, stream);
 }
 
 }  // namespace pauli
