@@ -47,7 +47,11 @@ __global__ void reset_counter_kernel(unsigned int* counter) {
     if (threadIdx.x == 0) *counter = 0u;
 }
 
-template <int PLANES, int RB, int WAVES, int PF>
+// AHEAD > 0: output tiles of matrices with at least MT rows and a whole
+// number of sign groups of slice pairs take the LDS-staged contraction
+// (each fragment copied once per workgroup, AHEAD pairs ahead); smaller ones
+// take the register ring.
+template <int PLANES, int RB, int WAVES, int PF, int AHEAD = 0>
 __device__ __attribute__((always_inline)) inline void batched_loop(const BatchItem* __restrict__ items, const uint32_t* __restrict__ tile_slot,
                                     uint32_t total, const unsigned char* __restrict__ ws,
                                     unsigned int* __restrict__ counter, unsigned char* lds, uint32_t& next) {
@@ -63,9 +67,22 @@ __device__ __attribute__((always_inline)) inline void batched_loop(const BatchIt
         const uint32_t Dp = padded_dim(it.n);
         const uint32_t nMB = Dp > (uint32_t)MT ? Dp / MT : 1u;
         const uint32_t local = t - it.tile0;
-        contract_tile<PLANES, RB, WAVES, FORWARD, PF>(ws + it.ws_off, (unsigned char*)it.out, it.n,
-                                                      local / nMB, local % nMB, 1.0 / (double)(1u << it.n),
-                                                      0, lds);
+        const double sc = 1.0 / (double)(1u << it.n);
+        bool staged = false;
+        if constexpr (AHEAD > 0) {
+            constexpr uint32_t GP = 32 * RB / Pack<PLANES>::SK / 2;   // slice pairs per sign group
+            const uint32_t nP = Dp / Pack<PLANES>::SK / 2;
+            staged = Dp >= (uint32_t)MT && nP % GP == 0;
+            if (staged) {
+                // its waits count only its own copies: let the claim return first
+                wait_vmcnt<0>();
+                contract_tile_lds<PLANES, RB, FORWARD, AHEAD>(ws + it.ws_off, (unsigned char*)it.out, it.n,
+                                                              local / nMB, local % nMB, sc, 0, lds);
+            }
+        }
+        if (!staged)
+            contract_tile<PLANES, RB, WAVES, FORWARD, PF>(ws + it.ws_off, (unsigned char*)it.out, it.n,
+                                                          local / nMB, local % nMB, sc, 0, lds);
         if (threadIdx.x == 0) next = claimed;   // the epilogue ended with a barrier
         __syncthreads();
         t = next;
@@ -73,7 +90,7 @@ __device__ __attribute__((always_inline)) inline void batched_loop(const BatchIt
     }
 }
 
-template <int PLANES, int RB, int WAVES, int PF>
+template <int PLANES, int RB, int WAVES, int PF, int AHEAD = 0>
 __global__ __launch_bounds__(WAVES * 64) void contract_batched_kernel(const BatchItem* __restrict__ items,
                                                                       const uint32_t* __restrict__ tile_slot,
                                                                       uint32_t total,
@@ -81,12 +98,12 @@ __global__ __launch_bounds__(WAVES * 64) void contract_batched_kernel(const Batc
                                                                       unsigned int* __restrict__ counter) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     __shared__ uint32_t next;
-    batched_loop<PLANES, RB, WAVES, PF>(items, tile_slot, total, ws, counter, lds, next);
+    batched_loop<PLANES, RB, WAVES, PF, AHEAD>(items, tile_slot, total, ws, counter, lds, next);
 }
 
 // The same loop with the registers budgeted for two waves per SIMD, so that
 // a second workgroup's contraction covers one's change-over between tiles.
-template <int PLANES, int RB, int WAVES, int PF>
+template <int PLANES, int RB, int WAVES, int PF, int AHEAD = 0>
 __global__ __launch_bounds__(WAVES * 64, 2) void contract_batched2_kernel(const BatchItem* __restrict__ items,
                                                                           const uint32_t* __restrict__ tile_slot,
                                                                           uint32_t total,
@@ -94,31 +111,34 @@ __global__ __launch_bounds__(WAVES * 64, 2) void contract_batched2_kernel(const 
                                                                           unsigned int* __restrict__ counter) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     __shared__ uint32_t next;
-    batched_loop<PLANES, RB, WAVES, PF>(items, tile_slot, total, ws, counter, lds, next);
+    batched_loop<PLANES, RB, WAVES, PF, AHEAD>(items, tile_slot, total, ws, counter, lds, next);
 }
 
 // Tile shapes the persistent kernel can run with: (RB, WAVES, PF, waves per
-// SIMD the registers are budgeted for).
+// SIMD the registers are budgeted for, LDS-staged pairs ahead or 0).
 struct BTile {
-    int rb, waves, pf, occ;
+    int rb, waves, pf, occ, ahead = 0;
 };
 constexpr BTile BTILES[] = {
     {2, 4, 4, 1},  // 1: 256 rows per output tile
     {1, 4, 2, 1},  // 2: 128 rows
     {4, 4, 4, 1},  // 3: 512 rows
     {1, 2, 2, 1},  // 4: 64 rows
-    {2, 4, 2, 2},  // 5: 256 rows, shallower ring, two workgroups per CU
+    {2, 4, 2, 2},     // 5: 256 rows, shallower ring, two workgroups per CU
+    {2, 4, 2, 1, 3},  // 6: 256 rows, LDS-staged 3 pairs ahead (ring for small matrices)
 };
 constexpr int NBTILES = sizeof(BTILES) / sizeof(BTILES[0]);
 
-template <int PLANES, int RB, int WAVES, int PF, int OCC>
+template <int PLANES, int RB, int WAVES, int PF, int OCC, int AHEAD = 0>
 hipError_t launch_contract_batched(const BatchItem* items, const uint32_t* tile_slot, uint32_t total,
                                    const unsigned char* ws, unsigned int* counter, hipStream_t s) {
     if constexpr (!ring_tile_ok(PLANES, RB)) {
         return hipErrorInvalidValue;
     } else {
         auto launch = [&](auto kern) -> hipError_t {
-            const int lds = WAVES * 1024 * 8;
+            const int stage = WAVES * 1024 * 8;
+            const int ring = AHEAD > 0 ? (AHEAD + 1) * 2 * Pack<PLANES>::NPL * FRAG : 0;
+            const int lds = ring > stage ? ring : stage;
             hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e != hipSuccess) return e;
             int dev = 0, cus = 0, per_cu = 0;
@@ -134,8 +154,8 @@ hipError_t launch_contract_batched(const BatchItem* items, const uint32_t* tile_
             hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES * 64), lds, s, items, tile_slot, total, ws, counter);
             return hipGetLastError();
         };
-        if constexpr (OCC == 2) return launch(contract_batched2_kernel<PLANES, RB, WAVES, PF>);
-        else return launch(contract_batched_kernel<PLANES, RB, WAVES, PF>);
+        if constexpr (OCC == 2) return launch(contract_batched2_kernel<PLANES, RB, WAVES, PF, AHEAD>);
+        else return launch(contract_batched_kernel<PLANES, RB, WAVES, PF, AHEAD>);
     }
 }
 
@@ -148,6 +168,7 @@ hipError_t launch_contract_btile(int btile, const BatchItem* items, const uint32
         case 3: return launch_contract_batched<PLANES, 4, 4, 4, 1>(items, tile_slot, total, ws, counter, s);
         case 4: return launch_contract_batched<PLANES, 1, 2, 2, 1>(items, tile_slot, total, ws, counter, s);
         case 5: return launch_contract_batched<PLANES, 2, 4, 2, 2>(items, tile_slot, total, ws, counter, s);
+        case 6: return launch_contract_batched<PLANES, 2, 4, 2, 1, 3>(items, tile_slot, total, ws, counter, s);
         default: return hipErrorInvalidValue;
     }
 }

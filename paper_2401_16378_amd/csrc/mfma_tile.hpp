@@ -288,7 +288,7 @@ __device__ inline void flush_into(f32x16 (&tot)[1][RB][2], f32x16 (&acc)[1][RB][
 // imaginary when it is odd; the other component, zero in exact arithmetic,
 // is dropped before the phase, which leaves every coefficient exactly real.
 template <int PLANES, int RB, int DIR, bool HERM = false>
-__device__ inline void store_tile(const f32x16 (&acc)[PLANES == 3 ? 2 : 1][RB][2], unsigned char* __restrict__ dst,
+__device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&acc)[PLANES == 3 ? 2 : 1][RB][2], unsigned char* __restrict__ dst,
                                   int N, uint32_t X0, uint32_t Pw, double scale, int out128, unsigned char* lds) {
     constexpr int ACC = PLANES == 3 ? 2 : 1;
     const uint32_t D = 1u << N;
@@ -377,7 +377,7 @@ __device__ inline void store_tile(const f32x16 (&acc)[PLANES == 3 ? 2 : 1][RB][2
 // same compile-time sign pattern, half as many steps.  Tiles with smaller X0
 // walk the whole K range (the same result without the shortcut).
 template <int PLANES, int RB, int WAVES, int DIR, int PF, bool HERM = false>
-__device__ inline void contract_tile(const unsigned char* __restrict__ wsm, unsigned char* __restrict__ dst,
+__device__ __attribute__((always_inline)) inline void contract_tile(const unsigned char* __restrict__ wsm, unsigned char* __restrict__ dst,
                                      int N, uint32_t xb, uint32_t mb, double scale, int out128,
                                      unsigned char* lds) {
     using P = Pack<PLANES>;
@@ -621,7 +621,7 @@ __device__ inline void wait_vmcnt() {
 // and the slot refilled next held a pair every wave has finished), refill,
 // then the MFMAs.  lds must hold max(ring, epilogue staging) bytes.
 template <int PLANES, int RB, int DIR, int AHEAD>
-__device__ inline void contract_tile_lds(const unsigned char* __restrict__ wsm, unsigned char* __restrict__ dst,
+__device__ __attribute__((always_inline)) inline void contract_tile_lds(const unsigned char* __restrict__ wsm, unsigned char* __restrict__ dst,
                                          int N, uint32_t xb, uint32_t mb, double scale, int out128,
                                          unsigned char* lds) {
     using P = Pack<PLANES>;

@@ -69,7 +69,7 @@ def test_batch_bitexact_vs_single(batch):
         assert torch.equal(outs[k], single), k
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
 def test_every_tile_shape(batch, tile):
     p = lib()
     Ns, mats, herm, dev = batch
