@@ -44,6 +44,7 @@ STRINGS_SOURCES = ["paper_2401_16378_amd/csrc/strings.hip", "paper_2401_16378_am
 STRINGS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_strings_n14.json")
 FWHT_SOURCES = ["paper_2401_16378_amd/csrc/fwht.hip", "paper_2401_16378_amd/csrc/common.hpp"]
 FWHT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwht_n14.json")
+HERM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hermitian_n14.json")
 
 
 def source_hash(sources=KERNEL_SOURCES) -> str:
@@ -420,7 +421,7 @@ def main():
         res["max_err_vs_oracle_sample"] = err_cpu
         log("[bench] oracle %.0f coeffs/s on %d cores, sample err %.3g" % (cpu["value"], cpu["cores"], err_cpu))
 
-    traffic = None if herm else measured_traffic()
+    traffic = measured_traffic(HERM_TRAFFIC_FILE if herm else TRAFFIC_FILE) if N == 14 else None
     if herm:
         res["imag_exactly_zero"] = bool(np.all(c_bf16.imag == 0))
     line = {
