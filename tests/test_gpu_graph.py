@@ -51,3 +51,35 @@ def test_capture_and_replay(algo):
             assert torch.equal(r, back), (algo, rep)
         del junk
     del g
+
+
+@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+def test_capture_and_replay_hermitian(algo):
+    """The Hermitian entry point enqueues the same two kernels (pack, then
+    the Hermitian contraction): captured, it must match the eager result on
+    every replay."""
+    p = lib()
+    N = 10
+    H = torch.from_numpy(workloads.hermitian(N, 1502)).cuda()
+    H2 = torch.from_numpy(workloads.hermitian(N, 1503)).cuda()
+    eager = p.decompose_hermitian(H, algo=algo)
+    eager2 = p.decompose_hermitian(H2, algo=algo)
+    torch.cuda.synchronize()
+    src = H.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        p.decompose_hermitian(src, algo=algo)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        c = p.decompose_hermitian(src, algo=algo)
+    for rep in range(4):
+        junk = torch.randn(1 << 18, device="cuda").sum()
+        src.copy_(H if rep % 2 == 0 else H2)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(c, eager if rep % 2 == 0 else eager2), (algo, rep)
+        del junk
+    del g

@@ -152,3 +152,34 @@ def test_requires_grad_refused():
     G = torch.from_numpy(workloads.hermitian(4, 5)).cuda().requires_grad_()
     with pytest.raises(ValueError):
         p.decompose_hermitian(G)
+
+
+def test_complex128_input():
+    """complex128 input is read rounded to binary32 (as for every matrix-core
+    path): the same coefficients as the complex64 copy of the matrix."""
+    p = lib()
+    G64 = workloads.hermitian(9, 740)
+    G128 = torch.from_numpy(G64.astype(np.complex128)).cuda()
+    a = p.decompose_hermitian(G128, out_dtype=torch.complex128)
+    b = p.decompose_hermitian(torch.from_numpy(G64).cuda(), out_dtype=torch.complex128)
+    assert torch.equal(a, b)
+    ref = oracle.decompose(G64.astype(np.complex128), threads=16)
+    assert rel_err(a.cpu().numpy(), ref) <= 1e-6
+
+
+def test_explicit_workspace_and_stream():
+    """The C entry point with a caller workspace on a side stream."""
+    import ctypes
+    p = lib()
+    N = 9
+    G = torch.from_numpy(workloads.hermitian(N, 741)).cuda()
+    want = p.decompose_hermitian(G)
+    need = p.load_library().pauli_workspace_bytes(p.ALGOS["split_bf16"], N, 1)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    out = torch.empty(4 ** N, dtype=torch.complex64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    o = p._opts("split_bf16", 0, 0, 0, ctypes.c_void_p(s.cuda_stream), ws)
+    assert p.load_library().pauli_decompose_hermitian(G.data_ptr(), N, 1, out.data_ptr(), ctypes.byref(o)) == 0
+    s.synchronize()
+    assert torch.equal(out, want)
