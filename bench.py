@@ -285,10 +285,47 @@ def bench_fwht(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_oracle(a):
+    """The CPU oracle's own timings on this host (no GPU work): full
+    decompositions single-threaded at N=6 and N=10 and on all cores at N=10
+    and N=12, and at N=14 the 65,536-coefficient sample on one core and on
+    all cores, extrapolated to all 4^14 coefficients."""
+    import oracle
+    import workloads
+    cores = len(os.sched_getaffinity(0))
+    rows = []
+
+    def run(label, N, threads, fn):
+        t0 = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t0
+        rows.append({"case": label, "N": N, "threads": threads, "seconds": dt})
+        log("[oracle] %s: %.3f s" % (label, dt))
+        return dt
+
+    G6 = workloads.iid_complex(6, workloads.SEED_N6)
+    run("N=6 full, 1 thread", 6, 1, lambda: oracle.decompose(G6))
+    G10 = workloads.iid_complex(10, workloads.SEED_N10)
+    run("N=10 full, 1 thread", 10, 1, lambda: oracle.decompose(G10))
+    run("N=10 full, all threads", 10, cores, lambda: oracle.decompose(G10, threads=cores))
+    G12 = workloads.hermitian(12, workloads.SEED_N12).astype(np.complex128)
+    run("N=12 full, all threads", 12, cores, lambda: oracle.decompose(G12, threads=cores))
+    del G12
+    G14 = workloads.hermitian(14, workloads.SEED_N14).astype(np.complex128)
+    ns = workloads.sample_indices(4 ** 14, 65536, seed=workloads.SEED_SAMPLE)
+    s1 = run("N=14 65,536-coefficient sample, 1 thread", 14, 1, lambda: oracle.coeffs_at(G14, ns))
+    sa = run("N=14 65,536-coefficient sample, all threads", 14, cores,
+             lambda: oracle.coeffs_at(G14, ns, threads=cores))
+    line = {"oracle_timing": rows, "cores": cores,
+            "n14_full_extrapolated_seconds": {"1 thread": s1 * 4096, "all threads": sa * 4096,
+                                              "note": "extrapolated: the sample's time x 4096 (4^14 / 65,536)"}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["n14", "hermitian", "batch", "backward", "strings", "fwht"],
+    ap.add_argument("--workload", choices=["n14", "hermitian", "batch", "backward", "strings", "fwht", "oracle"],
                     default="n14")
     ap.add_argument("--strings", type=int, default=65536, help="list length of the strings workload")
     ap.add_argument("--steps", type=int, default=20)
@@ -307,6 +344,9 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    if a.workload == "oracle":
+        return bench_oracle(a)
 
     import torch
     import paper_2401_16378_amd as pauli
