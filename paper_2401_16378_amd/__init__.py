@@ -247,7 +247,8 @@ def decompose_backward(grad_c: torch.Tensor, algo: str = "split_bf16", out_dtype
     return G
 
 
-_batch_ws = {}
+_batch_ws = {}          # (device, algo, N list) -> workspace, insertion order = recency
+_BATCH_WS_KEEP = 16
 
 
 def coeffs_at(G: torch.Tensor, strings, out_dtype=None, workspace_tensor=None) -> torch.Tensor:
@@ -313,10 +314,12 @@ def _batch_args(mats, algo, outs):
     Na = (ctypes.c_int * count)(*Ns)
     need = lib.pauli_batched_workspace_bytes(count, Na, ALGOS[algo])
     key = (dev, algo, tuple(Ns))
-    ws = _batch_ws.get(key)
+    ws = _batch_ws.pop(key, None)
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-        _batch_ws[key] = ws
+        while len(_batch_ws) >= _BATCH_WS_KEEP:   # least recently used first (freed in stream order)
+            _batch_ws.pop(next(iter(_batch_ws)))
+    _batch_ws[key] = ws                           # most recently used last
     Gp = (ctypes.c_void_p * count)(*[m.data_ptr() for m in mats])
     Op = (ctypes.c_void_p * count)(*[o.data_ptr() for o in outs])
     return mats, outs, count, Na, Gp, Op, ws

@@ -435,10 +435,35 @@ struct GraphEntry {
     BatchLayout layout;
     unsigned char* pinned = nullptr;   // host staging of the descriptor and tile slot tables
     hipEvent_t copied = nullptr;   // the staging may be rewritten once this has fired
+    hipEvent_t done = nullptr;     // the last replay has finished once this has fired
+    uint64_t last_use = 0;
 };
 
+// At most this many captured batches are kept; the least recently used one
+// makes room for a new one (after its last replay and staging copy finish).
+constexpr size_t MAX_GRAPHS = 64;
 std::mutex g_graph_mu;
 std::map<GraphKey, GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
+
+void release_entry(GraphEntry& g) {
+    if (g.done) (void)hipEventSynchronize(g.done);
+    if (g.copied) (void)hipEventSynchronize(g.copied);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.pinned) (void)hipHostFree(g.pinned);
+    if (g.copied) (void)hipEventDestroy(g.copied);
+    if (g.done) (void)hipEventDestroy(g.done);
+    g = GraphEntry{};
+}
+
+void evict_lru_locked() {
+    auto victim = g_graphs.end();
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+        if (victim == g_graphs.end() || it->second.last_use < victim->second.last_use) victim = it;
+    if (victim == g_graphs.end()) return;
+    release_entry(victim->second);
+    g_graphs.erase(victim);
+}
 std::map<std::pair<int, std::vector<int>>, int> g_btile;   // (planes, sorted Ns) -> tuned tile
 
 int validate_batch(int count, const void* const* G, const int* N, void* const* out, const pauli_opts& o,
@@ -501,26 +526,21 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
     const size_t staged = probe.items_bytes + sizeof(uint32_t) * (size_t)probe.tile_total;
     unsigned int* counter_dev = (unsigned int*)(ws + probe.counter_off);
     unsigned char* packed = ws + probe.packed_off;
+    if (found == g_graphs.end() && g_graphs.size() >= MAX_GRAPHS) evict_lru_locked();
     GraphEntry& ge = found != g_graphs.end() ? found->second : g_graphs[key];
+    ge.last_use = ++g_graph_clock;
     hipError_t e;
     if (!ge.exec) {
         ge.layout = probe;
-        if ((e = hipHostMalloc((void**)&ge.pinned, staged)) != hipSuccess) {
-            g_graphs.erase(key);
-            return hip_fail(e, fn);
-        }
-        memcpy(ge.pinned + probe.items_bytes, probe.tile_slot.data(), sizeof(uint32_t) * probe.tile_total);
-        if ((e = hipEventCreateWithFlags(&ge.copied, hipEventDisableTiming)) != hipSuccess) {
-            (void)hipHostFree(ge.pinned);
-            g_graphs.erase(key);
-            return hip_fail(e, fn);
-        }
         auto discard = [&](hipError_t err) {   // leave no half-built entry behind
-            (void)hipEventDestroy(ge.copied);
-            (void)hipHostFree(ge.pinned);
+            release_entry(ge);
             g_graphs.erase(key);
             return hip_fail(err, fn);
         };
+        if ((e = hipHostMalloc((void**)&ge.pinned, staged)) != hipSuccess) return discard(e);
+        memcpy(ge.pinned + probe.items_bytes, probe.tile_slot.data(), sizeof(uint32_t) * probe.tile_total);
+        if ((e = hipEventCreateWithFlags(&ge.copied, hipEventDisableTiming)) != hipSuccess) return discard(e);
+        if ((e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming)) != hipSuccess) return discard(e);
         // Capture on a private stream: batched pack, counter reset, persistent contraction.
         hipStream_t cap;
         if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return discard(e);
@@ -558,6 +578,7 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
         return hip_fail(e, fn);
     if ((e = hipEventRecord(ge.copied, s)) != hipSuccess) return hip_fail(e, fn);
     if ((e = hipGraphLaunch(ge.exec, s)) != hipSuccess) return hip_fail(e, fn);
+    if ((e = hipEventRecord(ge.done, s)) != hipSuccess) return hip_fail(e, fn);
     g_last_error.clear();
     return PAULI_OK;
 }

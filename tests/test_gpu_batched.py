@@ -150,3 +150,22 @@ def test_small_mixed_batch_fp32():
             ref = oracle.decompose(m)
             assert np.abs(o.cpu().numpy() - ref).max() / np.abs(ref).max() <= 1e-5, tile
     assert 1 <= p.autotune_batched(dev_m, algo="fp32") in tiles
+
+
+def test_graph_cache_bounded_by_eviction():
+    """More distinct batches (N lists) than the graph cache keeps: the least
+    recently used captures are released and rebuilt on demand, and every
+    call still returns the single-matrix result."""
+    p = lib()
+    rng = np.random.default_rng(4242)
+    mats = [torch.from_numpy(workloads.iid_complex(int(n), 4300 + k, np.complex64)).cuda()
+            for k, n in enumerate(rng.integers(3, 7, 80))]
+    singles = [p.decompose(m) for m in mats]
+    for k in range(1, 81):                      # 80 distinct N lists: prefixes of the list
+        outs = p.decompose_batched(mats[:k])
+        torch.cuda.synchronize()
+        for a, b in zip(outs, singles[:k]):
+            assert torch.equal(a, b), k
+    outs = p.decompose_batched(mats[:1])        # the first capture was evicted long ago
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], singles[0])
