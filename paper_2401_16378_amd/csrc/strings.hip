@@ -33,6 +33,9 @@ namespace pauli {
 namespace {
 
 constexpr int IB = 128;          // columns per LDS batch
+// A full batch (16 rows x IB columns) is exactly 8 elements per thread of the
+// 256-thread gather below, which loads them without bounds tests.
+static_assert(IB * 16 == 8 * 256, "the unguarded gather covers exactly one batch");
 
 // LDS row pitch (elements): rows start 64 bytes (16 banks) apart, so the row
 // segments that the strings of one 16-lane read phase touch do not collide.
