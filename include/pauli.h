@@ -275,8 +275,10 @@ const char* pauli_last_error(void);
  * callers that schedule or time them separately; opts->workspace is required
  * (pauli_workspace_bytes).  mode: 0 = decompose, 1 = reconstruct,
  * 2 = backward, 3 = decompose a Hermitian matrix (pauli_decompose_hermitian;
- * its pack is that of mode 0, its contraction takes the register-ring tiles
- * of pauli_tile_valid_hermitian).
+ * its pack writes only the parts of the operand that the half walk of any
+ * tile reads, its contraction takes the register-ring tiles of
+ * pauli_tile_valid_hermitian; a mode-3 contraction therefore needs a mode-3
+ * pack).
  *   pauli_pack: gather the input of the contraction (for mode 0 the XOR
  *     diagonals G[i ^ x][i] of section 2, Eq. (c_def_in_terms_of_fn); for
  *     modes 1 and 2 the coefficient blocks) and store it, converted to the

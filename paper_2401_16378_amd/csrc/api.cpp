@@ -306,8 +306,11 @@ int pauli_pack(const void* in, int N, int batch, int mode, const pauli_opts* opt
     const size_t bytes = ((size_t)1 << (2 * N)) * (size_t)batch * elem_bytes(o.in_dtype);
     if (overlaps(in, bytes, o.workspace, o.workspace_bytes))
         return fail(PAULI_EINVAL, "%s: workspace overlaps the input", fn);
-    const hipError_t e = launch_mfma_pack(mode == 0 || mode == 3 ? FORWARD : ADJOINT, planes_of(o.algo), in,
-                                          o.in_dtype == PAULI_C128, N, batch, o.workspace, (hipStream_t)o.stream);
+    const hipError_t e =
+        mode == 3 ? launch_mfma_pack_hermitian(planes_of(o.algo), in, o.in_dtype == PAULI_C128, N, batch, o.workspace,
+                                               (hipStream_t)o.stream)
+                  : launch_mfma_pack(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), in, o.in_dtype == PAULI_C128, N,
+                                     batch, o.workspace, (hipStream_t)o.stream);
     if (e != hipSuccess) return hip_fail(e, fn);
     g_last_error.clear();
     return PAULI_OK;

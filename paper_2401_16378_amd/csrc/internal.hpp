@@ -31,6 +31,8 @@ hipError_t launch_mfma_contract(Dir dir, int planes, const void* ws, void* out, 
 // exactly real coefficients; register-ring tiles only.
 hipError_t launch_mfma_hermitian(int planes, const void* in, bool in_c128, void* out, bool out_c128, int N,
                                  int batch, double scale, int tile, void* ws, hipStream_t stream);
+hipError_t launch_mfma_pack_hermitian(int planes, const void* in, bool in_c128, int N, int batch, void* ws,
+                                      hipStream_t stream);
 hipError_t launch_mfma_contract_hermitian(int planes, const void* ws, void* out, bool out_c128, int N, int batch,
                                           double scale, int tile, hipStream_t stream);
 bool mfma_tile_valid_hermitian(int planes, int tile, int N);

@@ -17,6 +17,17 @@ __global__ __launch_bounds__(256) void pack_kernel(const void* __restrict__ in, 
     pack_tile<PLANES, DIR, IN128>(src, wsm, N, blockIdx.x, lds);
 }
 
+// Pack for the Hermitian contraction: the K ranges its half walk skips are not packed.
+template <int PLANES, bool IN128>
+__global__ __launch_bounds__(256) void pack_herm_kernel(const void* __restrict__ in, void* __restrict__ ws, int N,
+                                                        uint32_t hmin) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES>()];
+    const uint32_t D = 1u << N, Dp = padded_dim(N);
+    const unsigned char* src = (const unsigned char*)in + (size_t)blockIdx.y * D * D * (IN128 ? 16 : 8);
+    unsigned char* wsm = (unsigned char*)ws + (size_t)blockIdx.y * Dp * Dp * Pack<PLANES>::EB;
+    pack_tile<PLANES, FORWARD, IN128, true>(src, wsm, N, blockIdx.x, lds, hmin);
+}
+
 struct Params {
     const void* ws;
     void* out;
@@ -228,11 +239,39 @@ hipError_t launch_mfma_contract_hermitian(int planes, const void* ws, void* out,
                        : launch_tile<1, FORWARD, true>(tile, p, batch, stream);
 }
 
+// The pack skips only what no Hermitian tile reads: from the largest
+// half-walk threshold of any register-ring tile on, so that the pack does not
+// depend on the contraction's tile choice.
+uint32_t herm_pack_min(int planes) {
+    uint32_t h = 128u;
+    for (int k = 0; k < NTILES; ++k) {
+        const TileDesc t = TILES[k];
+        if (t.lds || !ring_tile_ok(planes, t.rb)) continue;
+        const uint32_t v = herm_half_from(planes, t.rb, t.pf);
+        if (v > h) h = v;
+    }
+    return h;
+}
+
+hipError_t launch_mfma_pack_hermitian(int planes, const void* in, bool in_c128, int N, int batch, void* ws,
+                                      hipStream_t stream) {
+    const uint32_t hmin = herm_pack_min(planes);
+    const dim3 grid(pack_tiles(N), batch);
+    if (planes == 3) {
+        if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<3, true>), grid, dim3(256), 0, stream, in, ws, N, hmin);
+        else hipLaunchKernelGGL((pack_herm_kernel<3, false>), grid, dim3(256), 0, stream, in, ws, N, hmin);
+    } else {
+        if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<1, true>), grid, dim3(256), 0, stream, in, ws, N, hmin);
+        else hipLaunchKernelGGL((pack_herm_kernel<1, false>), grid, dim3(256), 0, stream, in, ws, N, hmin);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_mfma_hermitian(int planes, const void* in, bool in_c128, void* out, bool out_c128, int N,
                                  int batch, double scale, int tile, void* ws, hipStream_t stream) {
     if (tile == 0) tile = mfma_default_tile_hermitian(planes, N);
     if (!mfma_tile_valid_hermitian(planes, tile, N)) return hipErrorInvalidValue;
-    const hipError_t e = launch_mfma_pack(FORWARD, planes, in, in_c128, N, batch, ws, stream);
+    const hipError_t e = launch_mfma_pack_hermitian(planes, in, in_c128, N, batch, ws, stream);
     if (e != hipSuccess) return e;
     return launch_mfma_contract_hermitian(planes, ws, out, out_c128, N, batch, scale, tile, stream);
 }

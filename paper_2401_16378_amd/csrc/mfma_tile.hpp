@@ -146,9 +146,13 @@ inline uint32_t pack_tiles(int N) {
 // Pack tile t (of pack_tiles(N)) of one matrix: 32 flip masks x KT values of
 // q.  256 threads; src = the matrix (or coefficient vector), ws = its packed
 // operand; lds holds pack_lds_bytes<PLANES>() bytes.
-template <int PLANES, int DIR, bool IN128>
+// HSKIP (Hermitian forward): tiles of flip masks X0 >= hmin (hmin >= 128, a
+// power of two no smaller than the contraction's half-walk threshold) whose
+// K range has the top bit of X0 set are never read by the half walk and are
+// not packed; all 128 K values of a tile share that bit.
+template <int PLANES, int DIR, bool IN128, bool HSKIP = false>
 __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned char* __restrict__ ws,
-                                 int N, uint32_t t, unsigned char* lds) {
+                                 int N, uint32_t t, unsigned char* lds, uint32_t hmin = 0) {
     using P = Pack<PLANES>;
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
@@ -156,6 +160,10 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
     const uint32_t nKT = Dp / KT;
     const uint32_t xb = t / nKT, kt = t % nKT;
     const uint32_t X0 = xb * XT, Q0 = kt * KT;
+    if constexpr (HSKIP) {
+        static_assert(PACK_KT == 128, "a skipped tile's K values share bit 7 and above");
+        if (X0 >= hmin && ((Q0 >> (31 - __builtin_clz(X0))) & 1u)) return;   // whole workgroup
+    }
     const bool full = D >= 32u;
     const int tid = threadIdx.x;
 
@@ -250,6 +258,19 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
         const unsigned char* srcl = lds + pl * XT * pitch + xl * pitch + (s * P::SK + h * (P::SK / 2)) * P::ESZ;
         *(u32x4*)(dst + (size_t)f * FRAG + lane * 16) = *(const u32x4*)srcl;
     }
+}
+
+// Slices per unrolled step of the register-ring contraction: twice the
+// larger of the sign group (32*RB K values) and the ring depth.
+constexpr int ring_step_slices(int planes, int rb, int pf) {
+    const int u = 32 * rb / (planes == 3 ? 16 : 8);
+    return 2 * (u > pf ? u : pf);
+}
+
+// First flip mask X0 (a multiple of 32) from which the Hermitian contraction
+// of a register-ring tile walks half of K: X0 >= (step length) * (K per slice).
+constexpr uint32_t herm_half_from(int planes, int rb, int pf) {
+    return (uint32_t)ring_step_slices(planes, rb, pf) * (planes == 3 ? 16u : 8u);
 }
 
 // Binary32 plane: an MFMA accumulator chain adds at most FLUSH_SLICES slices
@@ -384,7 +405,7 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
     constexpr int ACC = PLANES == 3 ? 2 : 1;
     constexpr int MT = WAVES * RB * 32;                    // rows per workgroup
     constexpr int U = 32 * RB / P::SK;                     // slices per sign group (32*RB K)
-    constexpr int GS = 2 * (U > PF ? U : PF);              // slices per unrolled step
+    constexpr int GS = ring_step_slices(PLANES, RB, PF);   // slices per unrolled step
     static_assert(GS % U == 0 && GS % PF == 0, "ring depth and sign group must nest");
     static_assert(!HERM || DIR == FORWARD, "the Hermitian shortcut is a forward-only property");
 
@@ -397,7 +418,7 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
     uint32_t nK = nS, beta = 0;
     bool half = false;
     if constexpr (HERM) {
-        if (X0 >= (uint32_t)(GS * P::SK)) {
+        if (X0 >= herm_half_from(PLANES, RB, PF)) {
             half = true;
             beta = (uint32_t)(31 - __builtin_clz(X0)) - (PLANES == 3 ? 4u : 3u);
             nK = nS >> 1;

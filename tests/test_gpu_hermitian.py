@@ -183,3 +183,56 @@ def test_explicit_workspace_and_stream():
     assert p.load_library().pauli_decompose_hermitian(G.data_ptr(), N, 1, out.data_ptr(), ctypes.byref(o)) == 0
     s.synchronize()
     assert torch.equal(out, want)
+
+
+def _nan_workspace(p, algo, N, batch=1):
+    need = p.load_library().pauli_workspace_bytes(p.ALGOS[algo], N, batch)
+    return torch.full((need,), 0xFF, dtype=torch.uint8, device="cuda")   # NaN in bf16 and binary32
+
+
+@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("N", [9, 10, 12])
+def test_pack_skips_only_unread_parts(algo, N):
+    """The Hermitian pack leaves the K ranges that no tile's half walk reads
+    unwritten: on a workspace of NaN bytes every tile must still give the
+    oracle's coefficients (a read of an unpacked part would show as NaN)."""
+    import ctypes
+    p = lib()
+    G = workloads.hermitian(N, 750 + N)
+    Gd = torch.from_numpy(G).cuda()
+    ns = workloads.sample_indices(4 ** N, 2048, seed=workloads.SEED_SAMPLE + 90 + N)
+    ref = oracle.coeffs_at(G.astype(np.complex128), ns, threads=16)
+    idx = torch.from_numpy(ns.astype(np.int64)).cuda()
+    for tile in range(1, 13):
+        if not p.tile_valid_hermitian(tile, N, algo):
+            continue
+        ws = _nan_workspace(p, algo, N)
+        out = torch.empty(4 ** N, dtype=torch.complex64, device="cuda")
+        o = p._opts(algo, 0, 0, tile, p._stream(Gd), ws)
+        assert p.load_library().pauli_decompose_hermitian(Gd.data_ptr(), N, 1, out.data_ptr(), ctypes.byref(o)) == 0
+        c = out.cpu().numpy()
+        assert np.all(np.isfinite(c)), (algo, N, tile)
+        assert np.abs(c[ns.astype(np.int64)] - ref).max() <= TOL[algo] * np.abs(ref).max(), (algo, N, tile)
+        del ws
+
+
+@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+def test_split_passes_any_contraction_tile(algo):
+    """pauli_pack mode 3 does not depend on the tile: a contraction with any
+    register-ring tile after it equals the one-call Hermitian entry point."""
+    import ctypes
+    p = lib()
+    N = 11
+    G = torch.from_numpy(workloads.hermitian(N, 760)).cuda()
+    lib_ = p.load_library()
+    for tile in (1, 3, 6, 9, 12):
+        if not p.tile_valid_hermitian(tile, N, algo):
+            continue
+        want = p.decompose_hermitian(G, algo=algo, tile=tile)
+        ws = _nan_workspace(p, algo, N)
+        out = torch.empty(4 ** N, dtype=torch.complex64, device="cuda")
+        pack_o = p._opts(algo, 0, 0, 0, p._stream(G), ws)            # default tile for the pack
+        cont_o = p._opts(algo, 0, 0, tile, p._stream(G), ws)
+        assert lib_.pauli_pack(G.data_ptr(), N, 1, 3, ctypes.byref(pack_o)) == 0
+        assert lib_.pauli_contract(N, 1, 3, out.data_ptr(), ctypes.byref(cont_o)) == 0
+        assert torch.equal(out, want), (algo, tile)
