@@ -8,8 +8,9 @@ G is exact in complex64, c(G)_n = c(A)_{n >> 16} c(B)_{n & 0xFFFF} exactly
 without rounding: split-bf16 (the integers sit on the hi grid, FP32 sums
 stay below 2^24), binary32, the binary64 string list and the binary64 fast
 Walsh-Hadamard path (whose 64 GiB intermediate replaces split-bf16's 48 GiB
-workspace).  Sampled outputs are therefore compared for equality.  Needs
-about 150 GiB of device memory.
+workspace), and the Hermitian entry point on (A + A^H) (x) (B + B^H).
+Sampled outputs are therefore compared for equality.  Needs about 180 GiB
+of device memory.
 """
 import numpy as np
 import pytest
@@ -85,3 +86,26 @@ def test_n16_reconstruct(kron_case):
     assert torch.equal(G2[0, :64], G[0, :64]) or ((G2[0, :64] - G[0, :64]).abs().max() / G.abs().max()).item() <= 1e-6
     del G2
     p.release_workspace()
+
+
+def test_n16_hermitian_exact(kron_case):
+    """The Hermitian entry point at N = 16: H = (A + A^H) (x) (B + B^H) is
+    Hermitian with integer entries of modulus <= 32, so the half walk's sums
+    stay exact and c(H)_n = c(A_h)_{n >> 16} c(B_h)_{n & 0xFFFF} exactly
+    (real), including the flip-mask blocks with the highest skipped bits."""
+    p, _, ns, _ = kron_case
+    print("N=16 Hermitian decompose", flush=True)
+    A, B = small_int_matrix(16001), small_int_matrix(16002)
+    Ah = (A + A.conj().T).astype(np.complex64)
+    Bh = (B + B.conj().T).astype(np.complex64)
+    cA, cB = oracle.decompose(Ah), oracle.decompose(Bh)
+    ref = cA[(ns >> 16).astype(np.int64)] * cB[(ns & 0xFFFF).astype(np.int64)]
+    H = torch.kron(torch.from_numpy(Ah).cuda(), torch.from_numpy(Bh).cuda())
+    c = p.decompose_hermitian(H)
+    del H
+    got = c[torch.from_numpy(ns.astype(np.int64)).cuda()].cpu().numpy()
+    assert np.array_equal(got, ref.astype(np.complex64)), np.abs(got - ref).max()
+    assert torch.all(c.imag == 0)
+    del c
+    p.release_workspace()
+    torch.cuda.empty_cache()
