@@ -52,9 +52,12 @@ __global__ void reset_counter_kernel(unsigned int* counter) {
 // (each fragment copied once per workgroup, AHEAD pairs ahead); smaller ones
 // take the register ring.
 template <int PLANES, int RB, int WAVES, int PF, int AHEAD = 0>
-__device__ __attribute__((always_inline)) inline void batched_loop(const BatchItem* __restrict__ items, const uint32_t* __restrict__ tile_slot,
-                                    uint32_t total, const unsigned char* __restrict__ ws,
-                                    unsigned int* __restrict__ counter, unsigned char* lds, uint32_t& next) {
+__device__ __attribute__((always_inline)) inline void batched_loop(const BatchItem* __restrict__ items,
+                                                                   const uint32_t* __restrict__ tile_slot,
+                                                                   uint32_t total, const unsigned char* __restrict__ ws,
+                                                                   unsigned int* __restrict__ counter,
+                                                                   unsigned char* lds, uint32_t& next) {
+    static_assert(AHEAD == 0 || WAVES == 4, "the LDS-staged contraction runs four waves per workgroup");
     constexpr int MT = WAVES * RB * 32;
     if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
     __syncthreads();
@@ -120,10 +123,10 @@ struct BTile {
     int rb, waves, pf, occ, ahead = 0;
 };
 constexpr BTile BTILES[] = {
-    {2, 4, 4, 1},  // 1: 256 rows per output tile
-    {1, 4, 2, 1},  // 2: 128 rows
-    {4, 4, 4, 1},  // 3: 512 rows
-    {1, 2, 2, 1},  // 4: 64 rows
+    {2, 4, 4, 1},     // 1: 256 rows per output tile
+    {1, 4, 2, 1},     // 2: 128 rows
+    {4, 4, 4, 1},     // 3: 512 rows
+    {1, 2, 2, 1},     // 4: 64 rows
     {2, 4, 2, 2},     // 5: 256 rows, shallower ring, two workgroups per CU
     {2, 4, 2, 1, 3},  // 6: 256 rows, LDS-staged 3 pairs ahead (ring for small matrices)
 };
