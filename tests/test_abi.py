@@ -252,3 +252,28 @@ def test_coeffs_at_backward_validation(lib, pauli):
     assert f(FAKE_IN, 2, ns, 3, FAKE_OUT, ctypes.byref(small)) == ENOMEM
     # the workspace bound covers the adjoint's plan (entries + 2^N + 1 offsets)
     assert lib.pauli_coeffs_at_workspace_bytes(14, 1) >= 4 * (2 ** 14 + 1)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No CPU fallback, checked in a fresh interpreter whose library path
+    points at nothing: loading the library raises, and a decomposition of a
+    host tensor raises too (the binding has no CPU path to fall back on)."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2401_16378_amd as p\n"
+        "p.LIB_PATH = %r\n"
+        "import torch\n"
+        "G = torch.zeros(4, 4, dtype=torch.complex64)\n"
+        "for f in (lambda: p.load_library(p.LIB_PATH), lambda: p.decompose(G)):\n"
+        "    try:\n"
+        "        f()\n"
+        "    except Exception as e:\n"
+        "        print('raised', type(e).__name__)\n"
+        "    else:\n"
+        "        print('computed')\n"
+    ) % (ROOT, str(tmp_path / "absent" / "libpauli.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    lines = [l for l in r.stdout.splitlines() if l.startswith(("raised", "computed"))]
+    assert lines and all(l.startswith("raised") for l in lines), (r.stdout, r.stderr)
