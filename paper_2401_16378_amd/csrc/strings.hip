@@ -37,10 +37,12 @@ constexpr int IB = 128;          // columns per LDS batch
 // 256-thread gather below, which loads them without bounds tests.
 static_assert(IB * 16 == 8 * 256, "the unguarded gather covers exactly one batch");
 
-// LDS row pitch (elements): rows start 64 bytes (16 banks) apart, so the row
-// segments that the strings of one 16-lane read phase touch do not collide.
-template <typename InT>
-constexpr int pitch_of() { return IB + 64 / (int)sizeof(InT); }
+// LDS row pitch (binary64 complex elements): rows start 64 bytes (16 banks)
+// apart, so the row segments that the strings of one 16-lane read phase touch
+// do not collide.  Columns are staged already widened to binary64, so the
+// per-string sums read them without a conversion (each staged value feeds
+// every string of its flip mask).
+constexpr int PITCH = IB + 64 / 16;
 
 __device__ inline double flip_sign(double a, uint32_t neg) {
     return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, a) ^ ((uint64_t)neg << 63));
@@ -69,19 +71,19 @@ __device__ __attribute__((always_inline)) inline void fetch_batch(const InT* __r
     }
 }
 
-// Write a fetched batch to LDS transposed to v[x & 15][column].
+// Write a fetched batch to LDS transposed to v[x & 15][column], in binary64.
 template <typename InT, bool FULL>
-__device__ __attribute__((always_inline)) inline void stage_batch(InT* v, uint32_t W, uint32_t lw, uint32_t ib, int tid,
-                                                                  const InT (&f)[8]) {
+__device__ __attribute__((always_inline)) inline void stage_batch(double2* v, uint32_t W, uint32_t lw, uint32_t ib,
+                                                                  int tid, const InT (&f)[8]) {
     const uint32_t total = ib * W;
 #pragma clang loop unroll(full)
     for (int j = 0; j < 8; ++j) {
         const uint32_t e = (uint32_t)tid + 256u * j;
         if (FULL || e < total) {
             const uint32_t c = e & (W - 1u), r = (e >> lw) & (W - 1u), b = e >> (2 * lw);
-            InT& d = v[(r ^ c) * pitch_of<InT>() + (b << lw) + c];
-            d.x = f[j].x;
-            d.y = f[j].y;
+            double2& d = v[(r ^ c) * PITCH + (b << lw) + c];
+            d.x = (double)f[j].x;
+            d.y = (double)f[j].y;
         }
     }
 }
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(256) void strings_kernel(const InT* __restrict__ G,
                                                       const StringEntry* __restrict__ entries,
                                                       void* __restrict__ out, int out128, double scale,
                                                       double2* __restrict__ partial, uint32_t count_total) {
-    __shared__ InT v[16 * pitch_of<InT>()];
+    __shared__ double2 v[16 * PITCH];
     __shared__ double part[4][2];
 
     const uint32_t D = 1u << N;
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(256) void strings_kernel(const InT* __restrict__ G,
     uint32_t n = 0;
     if (has) n = entries[ch.first + s].n;
     const uint32_t x = flip_of_index(n), z = phase_of_index(n);
-    const InT* vrow = v + (x & (W - 1u)) * pitch_of<InT>();
+    const double2* vrow = v + (x & (W - 1u)) * PITCH;
 
     double re = 0.0, im = 0.0;
     // Columns il = q + T (8u + t) of a batch, t < 8.  The bits of q, T t,
@@ -135,13 +137,13 @@ __global__ __launch_bounds__(256) void strings_kernel(const InT* __restrict__ G,
         if (ib >= 8u * (uint32_t)T) {           // uniform: T and ib are per-workgroup
             const uint32_t step = 8u * (uint32_t)T;
             for (uint32_t g0 = 0; g0 < ib; g0 += step) {
-                const InT* src = vrow + g0 + (uint32_t)q;
+                const double2* src = vrow + g0 + (uint32_t)q;
                 double sr = 0.0, si = 0.0;
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
-                    const InT g = src[t << lt];
-                    sr = fma((double)g.x, st[t], sr);
-                    si = fma((double)g.y, st[t], si);
+                    const double2 g = src[t << lt];
+                    sr = fma(g.x, st[t], sr);
+                    si = fma(g.y, st[t], si);
                 }
                 const double su = ((par0 + (uint32_t)__popc(g0 & z)) & 1u) ? -1.0 : 1.0;
                 re = fma(sr, su, re);
@@ -149,10 +151,10 @@ __global__ __launch_bounds__(256) void strings_kernel(const InT* __restrict__ G,
             }
         } else {                                // fewer than 8 columns per thread
             for (uint32_t il = q; il < ib; il += T) {
-                const InT g = vrow[il];
+                const double2 g = vrow[il];
                 const uint32_t neg = (par0 + (uint32_t)__popc(il & z)) & 1u;
-                re += flip_sign((double)g.x, neg);
-                im += flip_sign((double)g.y, neg);
+                re += flip_sign(g.x, neg);
+                im += flip_sign(g.y, neg);
             }
         }
     };
