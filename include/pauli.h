@@ -181,7 +181,9 @@ int pauli_batched_tile_valid(int algo, int tile);
 /*
  * Run pauli_decompose_batched with every tile shape on the given buffers
  * (outputs are overwritten with the same correct result), time each and keep
- * the fastest for this list of N values.  Blocking.
+ * the fastest for this list of N values (in the process-wide table, and in
+ * the PAULI_TUNE_CACHE file if that variable is set, see pauli_autotune).
+ * Blocking.
  */
 int pauli_autotune_batched(int count, const void* const* G, const int* N, void* const* out,
                            const pauli_opts* opts);
@@ -204,6 +206,10 @@ size_t pauli_workspace_bytes(int algo, int N, int batch);
  * fastest per N in the process-wide tune table, and write the table to the
  * file named by the PAULI_TUNE_CACHE environment variable if it is set.
  * Blocking.  opts supplies algo and stream (may be NULL: SPLIT_BF16).
+ * The file, read once per process before the first tile choice, holds one
+ * entry per line: "algo N tile" for single matrices and
+ * "B planes tile c_1 ... c_12" for a batch of c_n matrices of order n
+ * (planes 3 = SPLIT_BF16, 1 = FP32); lines that do not parse are ignored.
  */
 int pauli_autotune(int N_min, int N_max, const pauli_opts* opts);
 

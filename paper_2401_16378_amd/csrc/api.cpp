@@ -10,7 +10,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -66,22 +68,61 @@ pauli_opts resolve(const pauli_opts* o) {
     return r;
 }
 
-// Tune table: (algo, N) -> tile id chosen by pauli_autotune.
+// Tune tables: (algo, N) -> tile id chosen by pauli_autotune, and (planes,
+// sorted N list) -> persistent tile shape chosen by pauli_autotune_batched.
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, int> g_tune;
+std::map<std::pair<int, std::vector<int>>, int> g_btile;
 bool g_tune_loaded = false;
 
+// The file named by PAULI_TUNE_CACHE, one entry per line:
+//   "algo N tile"                      single matrices
+//   "B planes tile c_1 c_2 ... c_12"   a batch with c_n matrices of order n
+// Lines that do not parse are ignored.
 void load_tune_cache_locked() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
     const char* path = getenv("PAULI_TUNE_CACHE");
     if (!path) return;
-    FILE* f = fopen(path, "r");
-    if (!f) return;
-    // one entry per line: "algo N tile"
-    int a, n, t;
-    while (fscanf(f, "%d %d %d", &a, &n, &t) == 3) g_tune[{a, n}] = t;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        if (!line.empty() && line[0] == 'B') {
+            std::string tag;
+            int planes = 0, tile = 0;
+            if (!(in >> tag >> planes >> tile)) continue;
+            std::vector<int> ns;
+            bool ok = true;
+            for (int n = 1; n <= N_MAX_BATCHED && ok; ++n) {
+                int c = -1;
+                ok = (bool)(in >> c) && c >= 0;
+                if (ok) ns.insert(ns.end(), (size_t)c, n);
+            }
+            if (ok && !ns.empty()) g_btile[{planes, ns}] = tile;
+        } else {
+            int a, n, t;
+            if (in >> a >> n >> t) g_tune[{a, n}] = t;
+        }
+    }
+}
+
+// Rewrite the tune file (if PAULI_TUNE_CACHE is set) with both tables.
+bool save_tune_cache_locked() {
+    const char* path = getenv("PAULI_TUNE_CACHE");
+    if (!path) return true;
+    FILE* f = fopen(path, "w");
+    if (!f) return false;
+    for (auto& kv : g_tune) fprintf(f, "%d %d %d\n", kv.first.first, kv.first.second, kv.second);
+    for (auto& kv : g_btile) {
+        int counts[N_MAX_BATCHED + 1] = {0};
+        for (int n : kv.first.second) counts[n]++;
+        fprintf(f, "B %d %d", kv.first.first, kv.second);
+        for (int n = 1; n <= N_MAX_BATCHED; ++n) fprintf(f, " %d", counts[n]);
+        fprintf(f, "\n");
+    }
     fclose(f);
+    return true;
 }
 
 int planes_of(int algo) { return algo == PAULI_ALGO_SPLIT_BF16 ? 3 : 1; }
@@ -467,7 +508,6 @@ void evict_lru_locked() {
     release_entry(victim->second);
     g_graphs.erase(victim);
 }
-std::map<std::pair<int, std::vector<int>>, int> g_btile;   // (planes, sorted Ns) -> tuned tile
 
 int validate_batch(int count, const void* const* G, const int* N, void* const* out, const pauli_opts& o,
                    const char* fn) {
@@ -498,6 +538,7 @@ int tuned_btile(int planes, int count, const int* N) {
     std::vector<int> ns(N, N + count);
     std::sort(ns.begin(), ns.end());
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
     auto it = g_btile.find({planes, ns});
     return it == g_btile.end() ? 1 : it->second;
 }
@@ -641,7 +682,10 @@ extern "C" int pauli_autotune_batched(int count, const void* const* G, const int
     std::sort(ns.begin(), ns.end());
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_cache_locked();
         g_btile[{planes, ns}] = best;
+        if (!save_tune_cache_locked())
+            return fail(PAULI_EINVAL, "%s: cannot write %s", fn, getenv("PAULI_TUNE_CACHE"));
     }
     g_last_error.clear();
     return PAULI_OK;
@@ -724,13 +768,10 @@ extern "C" int pauli_autotune(int N_min, int N_max, const pauli_opts* opts) {
             g_tune[{o.algo, N}] = best;
         }
     }
-    const char* path = getenv("PAULI_TUNE_CACHE");
-    if (path) {
+    {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        FILE* f = fopen(path, "w");
-        if (!f) return fail(PAULI_EINVAL, "%s: cannot write %s", fn, path);
-        for (auto& kv : g_tune) fprintf(f, "%d %d %d\n", kv.first.first, kv.first.second, kv.second);
-        fclose(f);
+        if (!save_tune_cache_locked())
+            return fail(PAULI_EINVAL, "%s: cannot write %s", fn, getenv("PAULI_TUNE_CACHE"));
     }
     g_last_error.clear();
     return PAULI_OK;

@@ -277,3 +277,29 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     lines = [l for l in r.stdout.splitlines() if l.startswith(("raised", "computed"))]
     assert lines and all(l.startswith("raised") for l in lines), (r.stdout, r.stderr)
+
+
+def test_tune_cache_file_is_read(tmp_path):
+    """The PAULI_TUNE_CACHE file feeds the tile choice of a fresh process:
+    single-matrix lines "algo N tile" and batch lines "B planes tile
+    c_1 .. c_12" (c_n matrices of order n); malformed lines are ignored."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    cache.write_text("2 10 3\n"
+                     "B 3 4 0 0 1 1 2 1 0 0 0 0 0 0\n"      # one N=3, one N=4, two N=5, one N=6
+                     "not a line\n")
+    code = (
+        "import sys, ctypes; sys.path.insert(0, %r)\n"
+        "import paper_2401_16378_amd as p\n"
+        "lib = p.load_library()\n"
+        "Na = (ctypes.c_int * 5)(5, 3, 6, 4, 5)\n"
+        "print(lib.pauli_tile_selected(2, 10), lib.pauli_batched_tile_selected(5, Na, 2),"
+        " lib.pauli_batched_tile_selected(5, Na, 1))\n"
+    ) % ROOT
+    env = dict(os.environ, PAULI_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    tile, btile, btile_fp32 = map(int, r.stdout.split())
+    assert (tile, btile) == (3, 4)
+    assert btile_fp32 == 1                       # binary32 has no entry: the default shape

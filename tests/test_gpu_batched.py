@@ -169,3 +169,26 @@ def test_graph_cache_bounded_by_eviction():
     outs = p.decompose_batched(mats[:1])        # the first capture was evicted long ago
     torch.cuda.synchronize()
     assert torch.equal(outs[0], singles[0])
+
+
+def test_autotune_batched_writes_tune_cache(tmp_path):
+    """pauli_autotune_batched records its choice in the PAULI_TUNE_CACHE file
+    (a "B planes tile c_1 .. c_12" line), which a later process reads back."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, PAULI_TUNE_CACHE=str(cache))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import numpy as np, torch, workloads, paper_2401_16378_amd as p\n"
+        "mats = [torch.from_numpy(workloads.iid_complex(n, 5200 + k, np.complex64)).cuda()\n"
+        "        for k, n in enumerate([3, 4, 5, 6, 6, 5])]\n"
+        "print('tuned', p.autotune_batched(mats), flush=True)\n"
+    ) % root
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    tuned = int([l for l in r.stdout.splitlines() if l.startswith("tuned")][0].split()[1])
+    lines = cache.read_text().splitlines()
+    assert "B 3 %d 0 0 1 1 2 2 0 0 0 0 0 0" % tuned in lines, lines
