@@ -137,31 +137,35 @@ def _opts(algo: str, in_dt: int, out_dt: int, tile: int = 0, stream=None, worksp
     return o
 
 
-_scratch = {}
+_scratch = {}   # (device, stream) -> scratch buffer
 
 
 def workspace(algo: str, N: int, batch: int, device) -> torch.Tensor:
-    """A cached device scratch buffer large enough for (algo, N, batch), or
-    None when the algorithm needs none.  Reused across calls on the device
-    (calls are ordered on torch's current stream)."""
+    """A cached device scratch buffer large enough for (algo, N, batch) on
+    torch's current stream of `device`, or None when the algorithm needs
+    none.  Each stream has its own buffer, reused by the calls enqueued on it
+    (which run in order), so work on different streams never shares one."""
     need = load_library().pauli_workspace_bytes(ALGOS[algo], N, batch)
     if need == 0:
         return None
-    key = torch.device(device)
+    dev = torch.device(device)
+    key = (dev, torch.cuda.current_stream(dev).cuda_stream)
     ws = _scratch.get(key)
     if ws is None or ws.numel() < need:
         _scratch.pop(key, None)
-        ws = torch.empty(need, dtype=torch.uint8, device=key)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
         _scratch[key] = ws
     return ws
 
 
 def release_workspace(device=None) -> None:
-    """Drop the cached scratch buffer of `device` (all devices if None)."""
+    """Drop the cached scratch buffers of `device` (all devices if None)."""
     if device is None:
         _scratch.clear()
     else:
-        _scratch.pop(torch.device(device), None)
+        dev = torch.device(device)
+        for key in [k for k in _scratch if k[0] == dev]:
+            del _scratch[key]
 
 
 def _stream(t: torch.Tensor):

@@ -93,3 +93,27 @@ def test_nonfinite_input_propagates(algo):
         bad[pr.n_of_xz(x_bad, z, N)] = True
     assert np.all(np.isfinite(out[~bad]))
     assert not np.any(np.isfinite(out[bad]))
+
+
+@pytest.mark.parametrize("algo", ["split_bf16", "fwht"])
+def test_concurrent_streams_do_not_share_scratch(algo):
+    """Decompositions enqueued on two streams at once, with no ordering
+    between them, each use their own cached scratch buffer: both results
+    equal the eager ones."""
+    import paper_2401_16378_amd as p
+    p.load_library()
+    N = 11
+    A = torch.from_numpy(workloads.iid_complex(N, 1600, np.complex64)).cuda()
+    B = torch.from_numpy(workloads.iid_complex(N, 1601, np.complex64)).cuda()
+    want_a, want_b = p.decompose(A, algo=algo), p.decompose(B, algo=algo)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs_a, outs_b = [], []
+    for _ in range(4):
+        with torch.cuda.stream(s1):
+            outs_a.append(p.decompose(A, algo=algo))
+        with torch.cuda.stream(s2):
+            outs_b.append(p.decompose(B, algo=algo))
+    torch.cuda.synchronize()
+    for a, b in zip(outs_a, outs_b):
+        assert torch.equal(a, want_a) and torch.equal(b, want_b)
