@@ -251,7 +251,7 @@ def decompose_backward(grad_c: torch.Tensor, algo: str = "split_bf16", out_dtype
     return G
 
 
-_batch_ws = {}          # (device, algo, N list) -> workspace, insertion order = recency
+_batch_ws = {}          # (device, stream, algo, N list) -> workspace, insertion order = recency
 _BATCH_WS_KEEP = 16
 
 
@@ -317,7 +317,7 @@ def _batch_args(mats, algo, outs):
     lib = load_library()
     Na = (ctypes.c_int * count)(*Ns)
     need = lib.pauli_batched_workspace_bytes(count, Na, ALGOS[algo])
-    key = (dev, algo, tuple(Ns))
+    key = (dev, torch.cuda.current_stream(dev).cuda_stream, algo, tuple(Ns))   # per stream: no sharing
     ws = _batch_ws.pop(key, None)
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
