@@ -137,7 +137,8 @@ def _opts(algo: str, in_dt: int, out_dt: int, tile: int = 0, stream=None, worksp
     return o
 
 
-_scratch = {}   # (device, stream) -> scratch buffer
+_scratch = {}   # (device, stream) -> scratch buffer, insertion order = recency
+_SCRATCH_KEEP = 8
 
 
 def workspace(algo: str, N: int, batch: int, device) -> torch.Tensor:
@@ -150,11 +151,12 @@ def workspace(algo: str, N: int, batch: int, device) -> torch.Tensor:
         return None
     dev = torch.device(device)
     key = (dev, torch.cuda.current_stream(dev).cuda_stream)
-    ws = _scratch.get(key)
+    ws = _scratch.pop(key, None)
     if ws is None or ws.numel() < need:
-        _scratch.pop(key, None)
+        while len(_scratch) >= _SCRATCH_KEEP:   # least recently used first (freed in stream order)
+            _scratch.pop(next(iter(_scratch)))
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-        _scratch[key] = ws
+    _scratch[key] = ws                           # most recently used last
     return ws
 
 
