@@ -10,7 +10,7 @@ using namespace mfma;
 
 template <int PLANES, int DIR, bool IN128>
 __global__ __launch_bounds__(256) void pack_kernel(const void* __restrict__ in, void* __restrict__ ws, int N) {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES>()];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES, DIR>()];
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const unsigned char* src = (const unsigned char*)in + (size_t)blockIdx.y * D * D * (IN128 ? 16 : 8);
     unsigned char* wsm = (unsigned char*)ws + (size_t)blockIdx.y * Dp * Dp * Pack<PLANES>::EB;

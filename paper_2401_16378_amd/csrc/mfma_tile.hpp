@@ -132,9 +132,16 @@ __host__ __device__ inline uint32_t padded_dim(int N) { return N < 5 ? 32u : (1u
 
 constexpr int PACK_KT = 128;   // K per pack workgroup (less when Dp < 128)
 
-template <int PLANES>
+// Adjoint pack: a wave's 32 x 32 block of coefficients staged in LDS as
+// binary32 pairs, 16 bytes of padding after every 16 entries (the per-thread
+// reads of 16 consecutive entries then fall in distinct banks).
+constexpr int ADJ_STAGE = 1024 + 2 * 64;   // f32x2 per wave
+
+template <int PLANES, int DIR = FORWARD>
 constexpr int pack_lds_bytes() {
-    return Pack<PLANES>::NPL * XT * (PACK_KT * Pack<PLANES>::ESZ + 16);
+    const int stage = Pack<PLANES>::NPL * XT * (PACK_KT * Pack<PLANES>::ESZ + 16);
+    const int adj = 4 * ADJ_STAGE * 8;
+    return DIR == FORWARD || stage >= adj ? stage : adj;
 }
 
 inline uint32_t pack_tiles(int N) {
@@ -145,7 +152,7 @@ inline uint32_t pack_tiles(int N) {
 
 // Pack tile t (of pack_tiles(N)) of one matrix: 32 flip masks x KT values of
 // q.  256 threads; src = the matrix (or coefficient vector), ws = its packed
-// operand; lds holds pack_lds_bytes<PLANES>() bytes.
+// operand; lds holds pack_lds_bytes<PLANES, DIR>() bytes.
 // HSKIP (Hermitian forward): tiles of flip masks X0 >= hmin (hmin >= 128, a
 // power of two no smaller than the contraction's half-walk threshold) whose
 // K range has the top bit of X0 set are never read by the half walk and are
@@ -166,11 +173,44 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
     }
     const bool full = D >= 32u;
     const int tid = threadIdx.x;
+    const bool active = (uint32_t)tid < 2 * KT;
+    const int g = tid >> 6, w6 = tid & 63;       // 32x32 square g, block w6 in it
+    f32x2 v[16];
+
+    if constexpr (DIR != FORWARD) {
+        // The 32 x 32 coefficients of square g are 1024 consecutive entries
+        // of the vector.  Read them lane-consecutive (each load instruction
+        // covers 64 neighbouring entries) into the wave's LDS block, then take
+        // each thread's 16 consecutive entries from there.  `full` is uniform.
+        if (full) {
+            f32x2* blk = (f32x2*)lds + g * ADJ_STAGE;
+            const uint32_t nb = pauli_index(X0, Q0 + 32 * g);
+            if (active) {
+                f32x2 c[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) c[i] = load_elem<IN128>(src, nb + 64 * i + w6);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int o = 64 * i + w6;
+                    blk[o + 2 * (o >> 4)] = c[i];
+                }
+            }
+            __syncthreads();
+            if (active) {
+                const f32x4* b4 = (const f32x4*)(blk + 18 * w6);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const f32x4 q = b4[j];
+                    v[2 * j] = f32x2{q.x, q.y};
+                    v[2 * j + 1] = f32x2{q.z, q.w};
+                }
+            }
+            __syncthreads();   // the staging below overwrites the LDS
+        }
+    }
 
     // one 4x4 micro-block per thread: 2*KT of them in the 32 x KT tile
-    if ((uint32_t)tid < 2 * KT) {
-        const int g = tid >> 6, w6 = tid & 63;   // 32x32 square g, block w6 in it
-        f32x2 v[16];
+    if (active) {
         int xh, kh;                              // column group (x_l / 4), first K slot
         if constexpr (DIR == FORWARD) {
             const int mr = w6 >> 3, mc = w6 & 7;
@@ -195,7 +235,8 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
                 const uint32_t zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
                 const uint32_t z = zb + zl, x = X0 + xl;
                 f32x2 c = {0.f, 0.f};
-                if (full || (z < D && x < D)) c = load_elem<IN128>(src, nb + o);
+                if (full) c = v[r];
+                else if (z < D && x < D) c = load_elem<IN128>(src, nb + o);
                 float re = c.x, im = c.y;
                 rotate_minus_i(re, im, 3u * (uint32_t)__popc(x & z));  // i^{popc(x&z)}
                 v[r] = f32x2{re, im};
