@@ -170,6 +170,12 @@ def release_workspace(device=None) -> None:
             del _scratch[key]
 
 
+def _on(dev):
+    """The library launches on the current HIP device: make `dev` current for
+    the duration of a call."""
+    return torch.cuda.device(dev)
+
+
 def _stream(t: torch.Tensor):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
@@ -205,7 +211,8 @@ def decompose(G: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: i
     batch = G.numel() // (1 << (2 * N))
     out = torch.empty(G.shape[:-2] + (1 << (2 * N),), dtype=out_dtype, device=G.device)
     o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G), workspace(algo, N, batch, G.device))
-    _check(load_library().pauli_decompose(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
+    with _on(G.device):
+        _check(load_library().pauli_decompose(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
     return out
 
 
@@ -222,7 +229,8 @@ def decompose_hermitian(G: torch.Tensor, algo: str = "split_bf16", out_dtype=Non
     batch = G.numel() // (1 << (2 * N))
     out = torch.empty(G.shape[:-2] + (1 << (2 * N),), dtype=out_dtype, device=G.device)
     o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G), workspace(algo, N, batch, G.device))
-    _check(load_library().pauli_decompose_hermitian(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
+    with _on(G.device):
+        _check(load_library().pauli_decompose_hermitian(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
     return out
 
 
@@ -235,7 +243,8 @@ def reconstruct(c: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile:
     batch = c.numel() // (D * D)
     G = torch.empty(c.shape[:-1] + (D, D), dtype=out_dtype, device=c.device)
     o = _opts(algo, _DT[c.dtype], _DT[out_dtype], tile, _stream(c), workspace(algo, N, batch, c.device))
-    _check(load_library().pauli_reconstruct(c.data_ptr(), N, batch, G.data_ptr(), ctypes.byref(o)))
+    with _on(c.device):
+        _check(load_library().pauli_reconstruct(c.data_ptr(), N, batch, G.data_ptr(), ctypes.byref(o)))
     return G
 
 
@@ -249,7 +258,8 @@ def decompose_backward(grad_c: torch.Tensor, algo: str = "split_bf16", out_dtype
     batch = g.numel() // (D * D)
     G = torch.empty(g.shape[:-1] + (D, D), dtype=out_dtype, device=g.device)
     o = _opts(algo, _DT[g.dtype], _DT[out_dtype], tile, _stream(g), workspace(algo, N, batch, g.device))
-    _check(load_library().pauli_decompose_backward(g.data_ptr(), N, batch, G.data_ptr(), ctypes.byref(o)))
+    with _on(g.device):
+        _check(load_library().pauli_decompose_backward(g.data_ptr(), N, batch, G.data_ptr(), ctypes.byref(o)))
     return G
 
 
@@ -277,8 +287,9 @@ def coeffs_at(G: torch.Tensor, strings, out_dtype=None, workspace_tensor=None) -
     if workspace_tensor is not None:
         o.workspace = workspace_tensor.data_ptr()
         o.workspace_bytes = workspace_tensor.numel() * workspace_tensor.element_size()
-    _check(load_library().pauli_coeffs_at(G.data_ptr(), N, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint)),
-                                          ns.shape[0], out.data_ptr(), ctypes.byref(o)))
+    with _on(G.device):
+        _check(load_library().pauli_coeffs_at(G.data_ptr(), N, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint)),
+                                              ns.shape[0], out.data_ptr(), ctypes.byref(o)))
     return out
 
 
@@ -301,8 +312,9 @@ def coeffs_at_backward(grad_c: torch.Tensor, N: int, strings, out_dtype=None, wo
     if workspace_tensor is not None:
         o.workspace = workspace_tensor.data_ptr()
         o.workspace_bytes = workspace_tensor.numel() * workspace_tensor.element_size()
-    _check(load_library().pauli_coeffs_at_backward(g.data_ptr(), N, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint)),
-                                                   ns.shape[0], out.data_ptr(), ctypes.byref(o)))
+    with _on(g.device):
+        _check(load_library().pauli_coeffs_at_backward(g.data_ptr(), N, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint)),
+                                                       ns.shape[0], out.data_ptr(), ctypes.byref(o)))
     return out
 
 
@@ -314,8 +326,20 @@ def _batch_args(mats, algo, outs):
     count = len(mats)
     dev = mats[0].device
     Ns = [_qubits_of_matrix(m) for m in mats]
+    for m in mats:
+        if m.device != dev:
+            raise ValueError("all matrices must be on one device, got %s and %s" % (dev, m.device))
+        if m.dim() != 2:
+            raise ValueError("decompose_batched takes single matrices, got shape %s" % (tuple(m.shape),))
     if outs is None:
         outs = [torch.empty(1 << (2 * n), dtype=torch.complex64, device=dev) for n in Ns]
+    else:
+        outs = list(outs)
+        if len(outs) != count:
+            raise ValueError("%d outputs for %d matrices" % (len(outs), count))
+        for o, n in zip(outs, Ns):   # the kernels write 4^N values through each pointer
+            if o.device != dev or o.dtype != torch.complex64 or not o.is_contiguous() or o.numel() != 1 << (2 * n):
+                raise ValueError("each output must be a contiguous complex64 tensor of 4^N values on %s" % dev)
     lib = load_library()
     Na = (ctypes.c_int * count)(*Ns)
     need = lib.pauli_batched_workspace_bytes(count, Na, ALGOS[algo])
@@ -340,7 +364,8 @@ def decompose_batched(mats, algo: str = "split_bf16", outs=None, tile: int = 0):
         return []
     mats, outs, count, Na, Gp, Op, ws = _batch_args(mats, algo, outs)
     o = _opts(algo, 0, 0, tile, _stream(mats[0]), ws)
-    _check(load_library().pauli_decompose_batched(count, Gp, Na, Op, ctypes.byref(o)))
+    with _on(mats[0].device):
+        _check(load_library().pauli_decompose_batched(count, Gp, Na, Op, ctypes.byref(o)))
     return outs
 
 
@@ -362,7 +387,8 @@ class BatchPlan:
 
     def run(self):
         self._o.stream = ctypes.c_void_p(torch.cuda.current_stream(self._dev).cuda_stream)
-        _check(self._lib.pauli_decompose_batched(self.count, self._Gp, self._Na, self._Op, ctypes.byref(self._o)))
+        with _on(self._dev):
+            _check(self._lib.pauli_decompose_batched(self.count, self._Gp, self._Na, self._Op, ctypes.byref(self._o)))
         return self.outs
 
 
@@ -372,7 +398,8 @@ def autotune_batched(mats, algo: str = "split_bf16", outs=None) -> int:
     mats, outs, count, Na, Gp, Op, ws = _batch_args(mats, algo, outs)
     o = _opts(algo, 0, 0, 0, _stream(mats[0]), ws)
     lib = load_library()
-    _check(lib.pauli_autotune_batched(count, Gp, Na, Op, ctypes.byref(o)))
+    with _on(mats[0].device):
+        _check(lib.pauli_autotune_batched(count, Gp, Na, Op, ctypes.byref(o)))
     return lib.pauli_batched_tile_selected(count, Na, ALGOS[algo])
 
 
@@ -381,7 +408,8 @@ def autotune(n_min: int, n_max: int, algo: str = "split_bf16", device=None) -> d
     dev = torch.device(device or "cuda")
     o = _opts(algo, 0, 0, 0, ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
     lib = load_library()
-    _check(lib.pauli_autotune(n_min, n_max, ctypes.byref(o)))
+    with _on(dev):
+        _check(lib.pauli_autotune(n_min, n_max, ctypes.byref(o)))
     return {n: lib.pauli_tile_selected(ALGOS[algo], n) for n in range(n_min, n_max + 1)}
 
 

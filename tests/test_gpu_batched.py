@@ -152,6 +152,33 @@ def test_small_mixed_batch_fp32():
     assert 1 <= p.autotune_batched(dev_m, algo="fp32") in tiles
 
 
+def test_batched_arguments_refused():
+    """Outputs of the wrong count, size, dtype or layout, and a matrix with a
+    batch dimension, are refused before any launch (the kernels write 4^N
+    values through each output pointer); correct outputs are filled."""
+    p = lib()
+    mats = [torch.from_numpy(workloads.iid_complex(n, 4400 + n, np.complex64)).cuda() for n in (3, 4)]
+    good = [torch.empty(4 ** n, dtype=torch.complex64, device="cuda") for n in (3, 4)]
+    bad_sets = [
+        good[:1],                                                                    # one output for two matrices
+        [good[0], torch.empty(4 ** 4 - 1, dtype=torch.complex64, device="cuda")],    # one value short
+        [good[0], torch.empty(4 ** 4, dtype=torch.complex128, device="cuda")],       # wrong dtype
+        [good[0], torch.empty(2 * 4 ** 4, dtype=torch.complex64, device="cuda")[::2]],   # not contiguous
+    ]
+    for outs in bad_sets:
+        with pytest.raises(ValueError):
+            p.decompose_batched(mats, outs=outs)
+        with pytest.raises(ValueError):
+            p.BatchPlan(mats, outs=outs)
+    with pytest.raises(ValueError):
+        p.decompose_batched([mats[0], torch.stack([mats[1], mats[1]])])
+    outs = p.decompose_batched(mats, outs=good)
+    torch.cuda.synchronize()
+    for m, o, g in zip(mats, outs, good):
+        assert o is g
+        assert torch.equal(o, p.decompose(m))
+
+
 def test_graph_cache_bounded_by_eviction():
     """More distinct batches (N lists) than the graph cache keeps: the least
     recently used captures are released and rebuilt on demand, and every
