@@ -158,8 +158,8 @@ int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
  * whose workgroups take output tiles (largest matrices first) from a counter
  * in the workspace.  Both are captured once per (stream, workspace, algo,
  * tile, N list) in a HIP graph that later calls replay; the descriptor table
- * (pointers) and the tile-to-matrix table are copied into the workspace on
- * every call, so new buffers are honoured.  The library keeps at most 64 such
+ * (pointers) and the pack-tile and output-tile to matrix tables are copied
+ * into the workspace on every call, so new buffers are honoured.  The library keeps at most 64 such
  * captures (with their pinned host staging) and releases the least recently
  * used one, after its last replay has finished, to make room for a new one.
  * opts->tile: 0 = the tuned or default shape, 1..

@@ -433,6 +433,7 @@ struct BatchLayout {
     std::vector<uint32_t> tile0;   // per slot
     uint32_t pack_total = 0, tile_total = 0;
     size_t items_bytes = 0, table_bytes = 0, counter_off = 0, packed_off = 0, total_bytes = 0;
+    std::vector<uint32_t> pack_slot;   // slot of every pack tile
     std::vector<uint32_t> tile_slot;   // slot of every output tile
 };
 
@@ -448,6 +449,7 @@ BatchLayout batch_layout(int count, const int* N, int planes, int btile) {
         L.pack0.push_back(L.pack_total);
         L.tile0.push_back(L.tile_total);
         off += round256(batched_packed_bytes(planes, n));
+        L.pack_slot.insert(L.pack_slot.end(), batched_pack_tiles(n), (uint32_t)slot);
         L.pack_total += batched_pack_tiles(n);
         const uint32_t tiles = batched_output_tiles(btile, n);
         L.tile_slot.insert(L.tile_slot.end(), tiles, (uint32_t)slot);
@@ -457,7 +459,8 @@ BatchLayout batch_layout(int count, const int* N, int planes, int btile) {
         max_tiles += most;
     }
     L.items_bytes = sizeof(BatchItem) * (size_t)count;
-    L.table_bytes = round256(L.items_bytes + sizeof(uint32_t) * max_tiles);
+    // descriptors, pack slots, output slots (room for the tile shape with the most tiles)
+    L.table_bytes = round256(L.items_bytes + sizeof(uint32_t) * ((size_t)L.pack_total + max_tiles));
     L.counter_off = L.table_bytes;
     L.packed_off = L.counter_off + 256;
     L.total_bytes = L.packed_off + off;
@@ -566,8 +569,9 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
     }
     unsigned char* ws = (unsigned char*)o.workspace;
     BatchItem* items_dev = (BatchItem*)ws;
-    const uint32_t* tile_slot_dev = (const uint32_t*)(ws + probe.items_bytes);
-    const size_t staged = probe.items_bytes + sizeof(uint32_t) * (size_t)probe.tile_total;
+    const uint32_t* pack_slot_dev = (const uint32_t*)(ws + probe.items_bytes);
+    const uint32_t* tile_slot_dev = pack_slot_dev + probe.pack_total;
+    const size_t staged = probe.items_bytes + sizeof(uint32_t) * ((size_t)probe.pack_total + probe.tile_total);
     unsigned int* counter_dev = (unsigned int*)(ws + probe.counter_off);
     unsigned char* packed = ws + probe.packed_off;
     if (found == g_graphs.end() && g_graphs.size() >= MAX_GRAPHS) evict_lru_locked();
@@ -582,17 +586,19 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
             return hip_fail(err, fn);
         };
         if ((e = hipHostMalloc((void**)&ge.pinned, staged)) != hipSuccess) return discard(e);
-        memcpy(ge.pinned + probe.items_bytes, probe.tile_slot.data(), sizeof(uint32_t) * probe.tile_total);
+        memcpy(ge.pinned + probe.items_bytes, probe.pack_slot.data(), sizeof(uint32_t) * probe.pack_total);
+        memcpy(ge.pinned + probe.items_bytes + sizeof(uint32_t) * probe.pack_total, probe.tile_slot.data(),
+               sizeof(uint32_t) * probe.tile_total);
         if ((e = hipEventCreateWithFlags(&ge.copied, hipEventDisableTiming)) != hipSuccess) return discard(e);
         if ((e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming)) != hipSuccess) return discard(e);
-        // Capture on a private stream: batched pack, counter reset, persistent contraction.
+        // Capture on a private stream: batched pack (which zeroes the counter), persistent contraction.
         hipStream_t cap;
         if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return discard(e);
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t le = launch_batched(planes, btile, items_dev, tile_slot_dev, count, probe.pack_total,
-                                                 probe.tile_total, packed, counter_dev, cap);
+            const hipError_t le = launch_batched(planes, btile, items_dev, pack_slot_dev, tile_slot_dev,
+                                                 probe.pack_total, probe.tile_total, packed, counter_dev, cap);
             e = hipStreamEndCapture(cap, &graph);
             if (le != hipSuccess) e = le;
         }

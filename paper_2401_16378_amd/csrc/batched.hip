@@ -5,16 +5,18 @@
 // The host builds a descriptor table in device memory: one entry per matrix,
 // in decreasing order of N (longest-processing-time first), with the matrix's
 // packed-operand offset and its first pack tile and first output tile in the
-// batch-wide numbering, followed by the slot of every output tile.  The pack
-// kernel maps its block index to (matrix, tile) by binary search over the
-// first-tile fields.  The contraction kernel is persistent: each workgroup
-// takes output tiles from a single atomic counter until the list is
-// exhausted, so every workgroup ends once the counter passes the last tile
-// and the grid drains.  It claims its next tile when it starts the current
-// one (the atomic's round trip then overlaps the contraction) and finds a
-// tile's matrix with one read of the slot table.  A one-thread kernel zeroes
-// the counter before each contraction launch (no memset node, so the
-// sequence can be captured in a HIP graph and replayed).
+// batch-wide numbering, followed by the slot of every pack tile and of every
+// output tile.  A pack workgroup finds its matrix with one read of the pack
+// slot table.  The contraction kernel is persistent: each workgroup takes
+// output tiles from a single atomic counter until the list is exhausted, so
+// every workgroup ends once the counter passes the last tile and the grid
+// drains.  It claims its next tile when it starts the current one (the
+// atomic's round trip then overlaps the contraction) and finds a tile's
+// matrix with one read of the output slot table.  The pack kernel's first
+// thread zeroes the counter: the contraction runs after the pack on the same
+// stream, and the previous contraction has finished before the pack starts
+// (no memset node, so the sequence can be captured in a HIP graph and
+// replayed).
 #include "mfma_tile.hpp"
 
 namespace pauli {
@@ -22,29 +24,16 @@ namespace {
 
 using namespace mfma;
 
-// Slot of the matrix owning batch-wide pack tile t (pack0 increasing).
-__device__ inline int find_slot(const BatchItem* items, int count, uint32_t t) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].pack0 <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 template <int PLANES>
-__global__ __launch_bounds__(256) void pack_batched_kernel(const BatchItem* __restrict__ items, int count,
-                                                           unsigned char* __restrict__ ws) {
+__global__ __launch_bounds__(256) void pack_batched_kernel(const BatchItem* __restrict__ items,
+                                                           const uint32_t* __restrict__ pack_slot,
+                                                           unsigned char* __restrict__ ws,
+                                                           unsigned int* __restrict__ counter) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES>()];
-    const int k = find_slot(items, count, blockIdx.x);
-    const BatchItem it = items[k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;   // for the contraction that follows
+    const BatchItem it = items[pack_slot[blockIdx.x]];
     pack_tile<PLANES, FORWARD, false>((const unsigned char*)it.in, ws + it.ws_off, it.n,
                                       blockIdx.x - it.pack0, lds);
-}
-
-__global__ void reset_counter_kernel(unsigned int* counter) {
-    if (threadIdx.x == 0) *counter = 0u;
 }
 
 // AHEAD > 0: output tiles of matrices with at least MT rows and a whole
@@ -198,18 +187,18 @@ size_t batched_packed_bytes(int planes, int n) {
     return Dp * Dp * (size_t)(planes == 3 ? mfma::Pack<3>::EB : mfma::Pack<1>::EB);
 }
 
-hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, const uint32_t* tile_slot_dev, int count,
-                          uint32_t pack_total, uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
-                          hipStream_t stream) {
-    if (!batched_tile_valid(planes, btile)) return hipErrorInvalidValue;
+hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, const uint32_t* pack_slot_dev,
+                          const uint32_t* tile_slot_dev, uint32_t pack_total, uint32_t tile_total,
+                          unsigned char* packed, unsigned int* counter_dev, hipStream_t stream) {
+    if (!batched_tile_valid(planes, btile) || pack_total == 0) return hipErrorInvalidValue;
     if (planes == 3)
-        hipLaunchKernelGGL((pack_batched_kernel<3>), dim3(pack_total), dim3(256), 0, stream, items_dev, count, packed);
+        hipLaunchKernelGGL((pack_batched_kernel<3>), dim3(pack_total), dim3(256), 0, stream, items_dev, pack_slot_dev,
+                           packed, counter_dev);
     else
-        hipLaunchKernelGGL((pack_batched_kernel<1>), dim3(pack_total), dim3(256), 0, stream, items_dev, count, packed);
-    hipError_t e = hipGetLastError();
+        hipLaunchKernelGGL((pack_batched_kernel<1>), dim3(pack_total), dim3(256), 0, stream, items_dev, pack_slot_dev,
+                           packed, counter_dev);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, counter_dev);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     return planes == 3
                ? launch_contract_btile<3>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, stream)
                : launch_contract_btile<1>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, stream);

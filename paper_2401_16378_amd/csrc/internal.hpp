@@ -56,10 +56,11 @@ bool batched_tile_valid(int planes, int btile);
 uint32_t batched_output_tiles(int btile, int n);
 uint32_t batched_pack_tiles(int n);
 size_t batched_packed_bytes(int planes, int n);
-// tile_slot_dev[t] = descriptor slot of the matrix owning output tile t.
-hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, const uint32_t* tile_slot_dev, int count,
-                          uint32_t pack_total, uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
-                          hipStream_t stream);
+// pack_slot_dev[t] / tile_slot_dev[t] = descriptor slot of the matrix owning
+// pack tile t / output tile t.  The pack launch also zeroes *counter_dev.
+hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, const uint32_t* pack_slot_dev,
+                          const uint32_t* tile_slot_dev, uint32_t pack_total, uint32_t tile_total,
+                          unsigned char* packed, unsigned int* counter_dev, hipStream_t stream);
 
 // Pauli-string list: the host sorts the strings into chunks of at most 256
 // strings sharing a line group (flip masks equal above bit 3); chunk k covers
