@@ -164,3 +164,21 @@ def test_n15_exact_kronecker():
     assert torch.equal(G2, Gd.to(torch.complex128))
     del c, G2, Gd
     p.release_workspace()
+
+
+@pytest.mark.parametrize("N", [6, 9, 10])
+@pytest.mark.parametrize("which", ["reconstruct", "decompose_backward"])
+def test_adjoint_dtype_combinations(N, which):
+    """complex64 coefficients are widened exactly and every sum is binary64,
+    so each input/output dtype pair equals the complex128 result (rounded
+    once to binary32 for complex64 output) bit for bit; N = 6 takes the
+    one-kernel path, N >= 9 the two passes."""
+    p = lib()
+    fn = getattr(p, which)
+    c64 = workloads.iid_complex(N, 1700 + N, np.complex64).reshape(-1)
+    c128 = c64.astype(np.complex128)
+    ref = fn(torch.from_numpy(c128).cuda(), algo="fwht", out_dtype=torch.complex128)
+    assert torch.equal(fn(torch.from_numpy(c64).cuda(), algo="fwht", out_dtype=torch.complex128), ref)
+    ref64 = ref.to(torch.complex64)
+    assert torch.equal(fn(torch.from_numpy(c64).cuda(), algo="fwht", out_dtype=torch.complex64), ref64)
+    assert torch.equal(fn(torch.from_numpy(c128).cuda(), algo="fwht", out_dtype=torch.complex64), ref64)

@@ -157,6 +157,23 @@ def test_backward_equals_full_adjoint_n10():
     assert ((got - full).abs().max() / full.abs().max()).item() <= 1e-12
 
 
+def test_backward_dtype_combinations():
+    """The list adjoint widens complex64 gradients exactly and sums in
+    binary64: every gradient/output dtype pair equals the complex128 result
+    (rounded once to binary32 for complex64 output) bit for bit."""
+    p = lib()
+    N = 8
+    rng = np.random.default_rng(945)
+    ns = rng.integers(0, 4 ** N, 3000).astype(np.uint32)
+    g64 = (rng.standard_normal(3000) + 1j * rng.standard_normal(3000)).astype(np.complex64)
+    g128 = g64.astype(np.complex128)
+    ref = p.coeffs_at_backward(torch.from_numpy(g128).cuda(), N, ns, out_dtype=torch.complex128)
+    assert torch.equal(p.coeffs_at_backward(torch.from_numpy(g64).cuda(), N, ns, out_dtype=torch.complex128), ref)
+    ref64 = ref.to(torch.complex64)
+    assert torch.equal(p.coeffs_at_backward(torch.from_numpy(g64).cuda(), N, ns, out_dtype=torch.complex64), ref64)
+    assert torch.equal(p.coeffs_at_backward(torch.from_numpy(g128).cuda(), N, ns, out_dtype=torch.complex64), ref64)
+
+
 def test_autograd_list_loss():
     """L = sum_k w_k |c_k - t_k|^2 over a list of strings, through
     PauliCoeffsAt: the gradient equals the oracle's adjoint of 2 w (c - t)."""
