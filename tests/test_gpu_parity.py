@@ -165,6 +165,35 @@ def test_adjoint_complex128_coefficients(algo, N):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("which", ["decompose", "reconstruct", "decompose_backward"])
+def test_dtype_combinations(algo, which):
+    """Every input/output dtype pair of every entry point.  Each path forms a
+    result in binary64 and rounds it once for complex64 output; complex64
+    input is widened exactly.  So for values representable in binary32 all
+    four pairs follow from one result bit for bit.  The matrix-core
+    algorithms read complex128 input rounded to binary32, so a general
+    complex128 input gives the result of its complex64 rounding."""
+    p = lib()
+    fn = getattr(p, which)
+    N = 7
+    x64 = workloads.iid_complex(N, 1800 + N, np.complex64)
+    if which != "decompose":
+        x64 = x64.reshape(-1)
+    x128 = x64.astype(np.complex128)
+    ref = fn(dev(x64), algo=algo, out_dtype=torch.complex128)
+    assert torch.equal(fn(dev(x128), algo=algo, out_dtype=torch.complex128), ref)
+    ref64 = ref.to(torch.complex64)
+    assert torch.equal(fn(dev(x64), algo=algo, out_dtype=torch.complex64), ref64)
+    assert torch.equal(fn(dev(x128), algo=algo, out_dtype=torch.complex64), ref64)
+    if algo != "fp64_gray":
+        y128 = workloads.iid_complex(N, 1850 + N)
+        if which != "decompose":
+            y128 = y128.reshape(-1)
+        assert torch.equal(fn(dev(y128), algo=algo, out_dtype=torch.complex128),
+                           fn(dev(y128.astype(np.complex64)), algo=algo, out_dtype=torch.complex128))
+
+
+@pytest.mark.parametrize("algo", ALGOS)
 def test_batch_dimension(algo):
     p = lib()
     N = 6
