@@ -192,7 +192,10 @@ hipError_t pool_for_current_device(hipMemPool_t* pool) {
     if (e != hipSuccess) return e;
     uint64_t keep = ~(uint64_t)0;
     e = hipMemPoolSetAttribute(*pool, hipMemPoolAttrReleaseThreshold, &keep);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(*pool);   // not kept: the next call tries again
+        return e;
+    }
     g_pools[dev] = *pool;
     return hipSuccess;
 }
