@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void pack_herm_kernel(const void* __restrict__
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const unsigned char* src = (const unsigned char*)in + (size_t)blockIdx.y * D * D * (IN128 ? 16 : 8);
     unsigned char* wsm = (unsigned char*)ws + (size_t)blockIdx.y * Dp * Dp * Pack<PLANES>::EB;
-    pack_tile<PLANES, FORWARD, IN128, true>(src, wsm, N, blockIdx.x, lds, hmin);
+    pack_tile<PLANES, FORWARD, IN128>(src, wsm, N, herm_pack_tile(N, hmin, blockIdx.x), lds);
 }
 
 struct Params {
@@ -256,7 +256,8 @@ uint32_t herm_pack_min(int planes) {
 hipError_t launch_mfma_pack_hermitian(int planes, const void* in, bool in_c128, int N, int batch, void* ws,
                                       hipStream_t stream) {
     const uint32_t hmin = herm_pack_min(planes);
-    const dim3 grid(pack_tiles(N), batch);
+    if (hmin < 128u || (hmin & (hmin - 1u))) return hipErrorInvalidValue;   // the grid mapping needs both
+    const dim3 grid(herm_pack_tiles(N, hmin), batch);
     if (planes == 3) {
         if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<3, true>), grid, dim3(256), 0, stream, in, ws, N, hmin);
         else hipLaunchKernelGGL((pack_herm_kernel<3, false>), grid, dim3(256), 0, stream, in, ws, N, hmin);

@@ -150,16 +150,44 @@ inline uint32_t pack_tiles(int N) {
     return (Dp / XT) * (Dp / KT);
 }
 
+// Hermitian forward pack: tiles of flip masks X0 >= hmin (hmin >= 128, a
+// power of two no smaller than the contraction's half-walk threshold) whose
+// K range has the top bit of X0 set are never read by the half walk, so they
+// are not packed.  All 128 K values of a tile share that bit, so exactly half
+// of the tiles of such a 32-mask slab remain.  The pack grid holds only the
+// remaining tiles: herm_pack_tiles(N, hmin) of them, block t packing tile
+// herm_pack_tile(N, hmin, t) of pack_tiles(N), in increasing order.
+static_assert(PACK_KT == 128, "the tiles of a slab split on bit 7 and above of K");
+
+__host__ __device__ inline uint32_t herm_pack_tiles(int N, uint32_t hmin) {
+    const uint32_t Dp = padded_dim(N);
+    const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
+    const uint32_t nKT = Dp / KT, nXB = Dp / XT;
+    const uint32_t whole = nXB < hmin / XT ? nXB : hmin / XT;   // slabs packed whole
+    return whole * nKT + (nXB - whole) * (nKT / 2);
+}
+
+__device__ inline uint32_t herm_pack_tile(int N, uint32_t hmin, uint32_t t) {
+    const uint32_t Dp = padded_dim(N);
+    const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
+    const uint32_t nKT = Dp / KT, nXB = Dp / XT;
+    const uint32_t whole = nXB < hmin / XT ? nXB : hmin / XT;
+    if (t < whole * nKT) return t;
+    // a half slab (then Dp > hmin >= 128, so KT = 128 and nKT >= 2): the j-th
+    // K tile whose bit b = log2(X0) - 7 is clear
+    const uint32_t u = t - whole * nKT, half = nKT / 2;
+    const uint32_t xb = whole + u / half, j = u % half;
+    const uint32_t b = 31u - (uint32_t)__builtin_clz(xb * XT) - 7u;
+    const uint32_t kt = ((j >> b) << (b + 1)) | (j & ((1u << b) - 1u));
+    return xb * nKT + kt;
+}
+
 // Pack tile t (of pack_tiles(N)) of one matrix: 32 flip masks x KT values of
 // q.  256 threads; src = the matrix (or coefficient vector), ws = its packed
 // operand; lds holds pack_lds_bytes<PLANES, DIR>() bytes.
-// HSKIP (Hermitian forward): tiles of flip masks X0 >= hmin (hmin >= 128, a
-// power of two no smaller than the contraction's half-walk threshold) whose
-// K range has the top bit of X0 set are never read by the half walk and are
-// not packed; all 128 K values of a tile share that bit.
-template <int PLANES, int DIR, bool IN128, bool HSKIP = false>
+template <int PLANES, int DIR, bool IN128>
 __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned char* __restrict__ ws,
-                                 int N, uint32_t t, unsigned char* lds, uint32_t hmin = 0) {
+                                 int N, uint32_t t, unsigned char* lds) {
     using P = Pack<PLANES>;
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
@@ -167,10 +195,6 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
     const uint32_t nKT = Dp / KT;
     const uint32_t xb = t / nKT, kt = t % nKT;
     const uint32_t X0 = xb * XT, Q0 = kt * KT;
-    if constexpr (HSKIP) {
-        static_assert(PACK_KT == 128, "a skipped tile's K values share bit 7 and above");
-        if (X0 >= hmin && ((Q0 >> (31 - __builtin_clz(X0))) & 1u)) return;   // whole workgroup
-    }
     const bool full = D >= 32u;
     const int tid = threadIdx.x;
     const bool active = (uint32_t)tid < 2 * KT;
