@@ -341,7 +341,7 @@ def main():
                     help="also run a device copy of this many GiB (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus,
+        print("bench.py: the decomposition runs on one GPU (it is not sharded across devices); --gpus %d is not supported" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
 

@@ -50,7 +50,7 @@ extern "C" {
 typedef enum pauli_status {
     PAULI_OK = 0,
     PAULI_EINVAL = 1,       /* bad argument: N out of range, NULL, misaligned, overlap, count */
-    PAULI_EUNSUPPORTED = 2, /* valid request this build does not implement */
+    PAULI_EUNSUPPORTED = 2, /* valid request the library does not implement */
     PAULI_EHIP = 3,         /* HIP runtime error; message carries hipGetErrorString */
     PAULI_ENOMEM = 4        /* caller workspace smaller than required */
 } pauli_status;

@@ -13,7 +13,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests are skipped (not failed) where no GPU is visible; the GPU machine runs them.
+    # GPU tests are skipped (not failed) where no GPU is visible.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
