@@ -6,8 +6,9 @@ does.  The arithmetic lives in ``pauli_oracle.c`` (plain C, binary64,
 single-threaded); this file only builds it with gcc and marshals numpy arrays.
 
 Functions follow the paper:
-  coeff_fast   -- one coefficient by the Gray-code algorithm (section 3, Fig. 1b)
-  coeff_slow   -- the natural-order variant with lambda in full (Fig. 1b)
+  coefficient  -- one coefficient by the Gray-code algorithm (section 3)
+  coefficient_natural -- the natural-order variant with lambda in full (section 3)
+  operator_at, flip_mask -- the operator of a qubit and the X/Y mask (section 2)
   decompose    -- all 4^N coefficients, Eq. (1); optional thread fan-out over
                   disjoint ranges of n (coefficients are independent, section 3)
   decompose_qgray -- all 4^N coefficients with n in quaternary Gray order and
@@ -53,11 +54,11 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         up = ctypes.POINTER(ctypes.c_uint64)
         u64, i64, ci = ctypes.c_uint64, ctypes.c_int64, ctypes.c_int
-        lib.oracle_pauli_flag.argtypes = [u64, ci]
-        lib.oracle_pauli_flag.restype = ci
-        lib.oracle_xy_mask.argtypes = [u64, ci]
-        lib.oracle_xy_mask.restype = u64
-        for name in ("oracle_coeff_fast", "oracle_coeff_slow"):
+        lib.oracle_operator_at.argtypes = [u64, ci]
+        lib.oracle_operator_at.restype = ci
+        lib.oracle_flip_mask.argtypes = [u64, ci]
+        lib.oracle_flip_mask.restype = u64
+        for name in ("oracle_coefficient", "oracle_coefficient_natural"):
             getattr(lib, name).argtypes = [dp, ci, u64, dp]
             getattr(lib, name).restype = None
         lib.oracle_decompose_range.argtypes = [dp, ci, u64, u64, dp]
@@ -102,27 +103,29 @@ def _check_square(G: np.ndarray) -> int:
     return D.bit_length() - 1
 
 
-def pauli_flag(n: int, t: int) -> int:
-    return int(_load().oracle_pauli_flag(n, t))
+def operator_at(n: int, t: int) -> int:
+    """Operator of string n on qubit t: 0 = identity, 1 = X, 2 = Y, 3 = Z."""
+    return int(_load().oracle_operator_at(n, t))
 
 
-def xy_mask(n: int, N: int) -> int:
-    return int(_load().oracle_xy_mask(n, N))
+def flip_mask(n: int, N: int) -> int:
+    """Bit t set where string n has X or Y on qubit t."""
+    return int(_load().oracle_flip_mask(n, N))
 
 
-def coeff_fast(G: np.ndarray, n: int) -> complex:
+def coefficient(G: np.ndarray, n: int) -> complex:
     G = _as_c128(G)
     N = _check_square(G)
     out = np.zeros(2)
-    _load().oracle_coeff_fast(_dptr(G), N, n, _dptr(out))
+    _load().oracle_coefficient(_dptr(G), N, n, _dptr(out))
     return complex(out[0], out[1])
 
 
-def coeff_slow(G: np.ndarray, n: int) -> complex:
+def coefficient_natural(G: np.ndarray, n: int) -> complex:
     G = _as_c128(G)
     N = _check_square(G)
     out = np.zeros(2)
-    _load().oracle_coeff_slow(_dptr(G), N, n, _dptr(out))
+    _load().oracle_coefficient_natural(_dptr(G), N, n, _dptr(out))
     return complex(out[0], out[1])
 
 

@@ -15,211 +15,208 @@
  *   - Matrix indices start at zero; bit 0 of an index is the rightmost bit
  *     and belongs to the rightmost (zero-th) Pauli factor (section 2,
  *     notation paragraph).
- *   - The n-th Pauli string takes its t-th operator from the t-th pair of
- *     bits of n: flag = 2*bit(2t+1) + bit(2t), with 0 = identity, 1 = X,
- *     2 = Y, 3 = Z (section 2, last paragraph; Fig. 1a getPauliFlag), which
- *     gives the ordering of Eq. (2).
- *   - The Pauli matrices are those of Eq. (3), Y = [[0,-i],[i,0]].
+ *   - String n carries its operator on qubit t in its t-th base-4 digit
+ *     (the bit pair 2t+1, 2t), with 0 = identity, 1 = X, 2 = Y, 3 = Z
+ *     (section 2, closing paragraph), which gives the ordering of Eq. (2).
+ *   - The single-qubit matrices are those of Eq. (3), Y = [[0,-i],[i,0]].
+ *
+ * Representation used throughout: every nonzero element of the matrices of
+ * Eq. (3) is a power of the imaginary unit, so every beta of section 2 and
+ * every lambda of Eq. (lambda_def) is i^q for an integer q taken mod 4.
+ * The oracle carries lambda as that quarter-turn count q, multiplies a
+ * matrix entry by i^q as an exact rotation of its two parts, and rounds only
+ * in the running sum.
  *
  * Parity pins (see the test-suite): brute-force Tr(P_n G) for small N, the
  * Eq. (2) ordering, one-hot strings, closed forms, Kronecker factorisation,
- * Parseval, Hermitian => real, reconstruction and adjoint identities.
+ * Parseval, Hermitian => real, recomposition and adjoint identities.
  */
+#include <math.h>
 #include <stdint.h>
 
-typedef struct { double re, im; } cplx;
+#define MAX_QUBITS 64
 
-static cplx cmul(cplx a, cplx b) {
-    cplx r;
-    r.re = a.re * b.re - a.im * b.im;
-    r.im = a.re * b.im + a.im * b.re;
-    return r;
-}
+/*
+ * Eq. (3) written row by row.  Each of the four matrices has exactly one
+ * nonzero element per row (section 2: identity and Z are diagonal, X and Y
+ * anti-diagonal).  Row a holds its nonzero element in column a when the
+ * matrix is diagonal and in column 1-a when it is anti-diagonal; that
+ * element is i^quarter[a].
+ *     identity  [[1, 0], [0,  1]]   diagonal       1 = i^0, 1 = i^0
+ *     X         [[0, 1], [1,  0]]   anti-diagonal  1 = i^0, 1 = i^0
+ *     Y         [[0,-i], [i,  0]]   anti-diagonal -i = i^3, i = i^1
+ *     Z         [[1, 0], [0, -1]]   diagonal       1 = i^0,-1 = i^2
+ */
+typedef struct {
+    int antidiagonal;
+    int quarter[2];
+} eq3_matrix;
 
-static cplx cadd(cplx a, cplx b) {
-    cplx r;
-    r.re = a.re + b.re;
-    r.im = a.im + b.im;
-    return r;
-}
-
-/* Division by a value of unit modulus, written as multiplication by its
- * conjugate.  The paper's beta factors all lie in {+-1, +-i} (section 2,
- * definition of beta), so this equals the quotient exactly. */
-static cplx cdiv_unit(cplx a, cplx b) {
-    cplx bc;
-    bc.re = b.re;
-    bc.im = -b.im;
-    return cmul(a, bc);
-}
-
-/* Elements of the four Pauli matrices, Eq. (3), indexed [flag][row][col]. */
-static const cplx PAULI[4][2][2] = {
-    { { {1, 0}, {0, 0} }, { {0, 0}, { 1, 0} } },   /* identity */
-    { { {0, 0}, {1, 0} }, { {1, 0}, { 0, 0} } },   /* X */
-    { { {0, 0}, {0,-1} }, { {0, 1}, { 0, 0} } },   /* Y */
-    { { {1, 0}, {0, 0} }, { {0, 0}, {-1, 0} } },   /* Z */
+static const eq3_matrix EQ3[4] = {
+    {0, {0, 0}},
+    {1, {0, 0}},
+    {1, {3, 1}},
+    {0, {0, 2}},
 };
 
-static int get_bit(uint64_t v, int t) { return (int)((v >> t) & 1u); }
-
-/* Base-4 digit t of n: which Pauli sits at position t (section 2, last
- * paragraph; Fig. 1a getPauliFlag). */
-int oracle_pauli_flag(uint64_t n, int t) {
-    return (get_bit(n, 2 * t + 1) << 1) | get_bit(n, 2 * t);
+/* The operator string n acts with on qubit t: its t-th base-4 digit
+ * (section 2, closing paragraph). */
+int oracle_operator_at(uint64_t n, int t) {
+    return (int)((n >> (2 * t)) & 3u);
 }
 
-/* Bitmask m^(n): bit t set iff operator t is X or Y (section 2, definition
- * of f_n and its mask; Fig. 1a getMaskOfXY). */
-uint64_t oracle_xy_mask(uint64_t n, int N) {
+/* Flip mask m^(n) of section 2: f_n(i) = i xor m^(n) flips the bits of the
+ * qubits whose operator is X or Y, i.e. whose matrix is anti-diagonal. */
+uint64_t oracle_flip_mask(uint64_t n, int N) {
     uint64_t m = 0;
-    for (int t = 0; t < N; t++) {
-        int p = oracle_pauli_flag(n, t);
-        uint64_t b = (p > 0 && p < 3) ? 1u : 0u;
-        m |= b << t;
+    for (int q = N - 1; q >= 0; q--) {
+        m = (m << 1) | (uint64_t)EQ3[oracle_operator_at(n, q)].antidiagonal;
     }
     return m;
 }
 
-/* beta^(n,t) for row bit i_[t] and column bit i_[t] xor m_[t] (section 2,
- * beta labelling; Fig. 1a getBeta). */
-static cplx get_beta(uint64_t n, int t, uint64_t i, uint64_t m) {
-    int p = oracle_pauli_flag(n, t);
-    int a = get_bit(i, t);
-    int b = a ^ get_bit(m, t);
-    return PAULI[p][a][b];
+/* acc += i^q * g, exactly (a rotation by quarter turns), rounding only in
+ * the two additions. */
+static void accumulate_rotated(double acc[2], const double* g, int q) {
+    switch (q & 3) {
+        case 0: acc[0] += g[0]; acc[1] += g[1]; break;
+        case 1: acc[0] -= g[1]; acc[1] += g[0]; break;
+        case 2: acc[0] -= g[0]; acc[1] -= g[1]; break;
+        default: acc[0] += g[1]; acc[1] -= g[0]; break;
+    }
 }
 
-/* lambda_i^(n) as the full N-term product, Eq. (lambda_def). */
-static cplx get_lambda(uint64_t n, uint64_t i, uint64_t m, int N) {
-    cplx l = {1.0, 0.0};
-    for (int t = 0; t < N; t++) l = cmul(l, get_beta(n, t, i, m));
-    return l;
+static const double* entry(const double* G, int N, uint64_t row, uint64_t col) {
+    return G + 2 * ((row << N) + col);
 }
 
-static uint64_t gray_code(uint64_t k) { return k ^ (k >> 1); }
-
-/* Position of the single set bit of a power of two (the changed bit between
- * consecutive Gray codes, section 2 on constant-time bit position). */
-static int changed_bit(uint64_t i, uint64_t j) {
-    uint64_t d = i ^ j;
+/* Lowest set bit of k > 0: the Gray codes of k-1 and k differ exactly
+ * there (section 2, enumeration of i by Gray codes). */
+static int lowest_set_bit(uint64_t k) {
     int t = 0;
-    while ((d >> t) != 1u) t++;
+    while (!((k >> t) & 1u)) t++;
     return t;
 }
 
-static cplx load(const double* G, uint64_t D, uint64_t r, uint64_t c) {
-    cplx v;
-    v.re = G[2 * (r * D + c)];
-    v.im = G[2 * (r * D + c) + 1];
-    return v;
-}
-
 /*
- * Eq. (c_def_in_terms_of_fn) for string n with XY mask m, given lambda_0^(n):
- * i enumerated in Gray-code order, every later lambda obtained from the
- * previous one by the one-beta recurrence of Eq. (lambda_recurrence_over_i),
- * the sum divided by 2^N at the end.  The paper's first accumulation names
- * an undefined "matrix"; it is read as G, i.e. the term G[m][0].
+ * The sum of Eq. (c_def_in_terms_of_fn) for a string with operators op[],
+ * flip mask m and lambda_0 = i^q0, with i visited in Gray-code order
+ * (section 3): i starts at 0 and at step k flips its lowest-set bit of k.
+ * When bit t of i changes from a to 1-a, only the factor of qubit t in
+ * Eq. (lambda_def) changes, and Eq. (lambda_recurrence_over_i) multiplies
+ * lambda by the new beta and divides by the old one: in quarter turns, adds
+ * quarter[1-a] - quarter[a] of that qubit's matrix.  The sum is scaled by
+ * 2^-N once it is complete.
  */
-static void gray_sum(const double* G, int N, uint64_t n, uint64_t m, cplx l, double* out) {
-    uint64_t dim = (uint64_t)1 << N;
-    cplx c = cmul(l, load(G, dim, m, 0));
-    for (uint64_t k = 1; k < dim; k++) {
-        uint64_t i = gray_code(k);
-        uint64_t j = gray_code(k - 1);
-        int t = changed_bit(i, j);
-        cplx bi = get_beta(n, t, i, m);
-        cplx bj = get_beta(n, t, j, m);
-        l = cmul(l, cdiv_unit(bi, bj));
-        c = cadd(c, cmul(l, load(G, dim, i ^ m, i)));
+static void gray_walk(const double* G, int N, const int* op, uint64_t m, int q0, double* out) {
+    const uint64_t terms = (uint64_t)1 << N;
+    double acc[2] = {0.0, 0.0};
+    uint64_t i = 0;
+    int q = q0;
+    accumulate_rotated(acc, entry(G, N, m, 0), q);
+    for (uint64_t k = 1; k < terms; k++) {
+        int t = lowest_set_bit(k);
+        int a = (int)((i >> t) & 1u);
+        const eq3_matrix* s = &EQ3[op[t]];
+        q += s->quarter[1 - a] - s->quarter[a];
+        i ^= (uint64_t)1 << t;
+        accumulate_rotated(acc, entry(G, N, i ^ m, i), q);
     }
-    out[0] = c.re / (double)dim;
-    out[1] = c.im / (double)dim;
+    out[0] = ldexp(acc[0], -N);
+    out[1] = ldexp(acc[1], -N);
+}
+
+static void operators_of(uint64_t n, int N, int* op) {
+    for (int t = 0; t < N; t++) op[t] = oracle_operator_at(n, t);
 }
 
 /*
- * One coefficient by the paper's algorithm (section 3, Fig. 1b, "Fast"):
- * lambda_0 computed in full as the N-term product, then the Gray-order sum.
+ * One coefficient c_n by the paper's algorithm (section 3): the flip mask,
+ * lambda_0 as the full product of Eq. (lambda_def) at i = 0 (row 0 of every
+ * qubit's matrix), then the Gray-order sum with the one-factor recurrence.
  */
-void oracle_coeff_fast(const double* G, int N, uint64_t n, double* out) {
-    uint64_t m = oracle_xy_mask(n, N);
-    gray_sum(G, N, n, m, get_lambda(n, 0, m, N), out);
+void oracle_coefficient(const double* G, int N, uint64_t n, double* out) {
+    int op[MAX_QUBITS];
+    operators_of(n, N, op);
+    int q0 = 0;
+    for (int t = 0; t < N; t++) q0 += EQ3[op[t]].quarter[0];
+    gray_walk(G, N, op, oracle_flip_mask(n, N), q0, out);
 }
 
 /*
- * k-th string of the reflected quaternary Gray code over N base-4 digits
- * (section 2, enumeration of the P_n by the quaternary Gray code): the
- * sequence runs the lowest digit 0,1,2,3 and then back 3,2,1,0 each time
- * the digit above advances, so digit t of the code is digit t of k when
- * digit t+1 of k is even and 3 minus it when that digit is odd.  Consecutive
+ * The same sum in natural order of i with every lambda_i formed in full
+ * from Eq. (lambda_def) (the slower scheme of section 3).
+ */
+void oracle_coefficient_natural(const double* G, int N, uint64_t n, double* out) {
+    int op[MAX_QUBITS];
+    operators_of(n, N, op);
+    const uint64_t m = oracle_flip_mask(n, N);
+    double acc[2] = {0.0, 0.0};
+    for (uint64_t i = 0; i < ((uint64_t)1 << N); i++) {
+        int q = 0;
+        for (int t = 0; t < N; t++) q += EQ3[op[t]].quarter[(i >> t) & 1u];
+        accumulate_rotated(acc, entry(G, N, i ^ m, i), q);
+    }
+    out[0] = ldexp(acc[0], -N);
+    out[1] = ldexp(acc[1], -N);
+}
+
+/*
+ * String of rank k in the reflected quaternary Gray order over N base-4
+ * digits (section 2, enumeration of the P_n by the quaternary Gray code):
+ * the lowest digit runs 0,1,2,3 and then back 3,2,1,0 each time the digit
+ * above it advances, so digit t of the code is digit t of k while digit
+ * t+1 of k is even and 3 minus it while that digit is odd.  Consecutive
  * codes differ in one digit, by one step (I-X, X-Y or Y-Z).
  */
 uint64_t oracle_quaternary_gray(uint64_t k, int N) {
-    uint64_t g = 0;
-    for (int t = 0; t < N; t++) {
-        int d = oracle_pauli_flag(k, t);
-        int up = t + 1 < N ? oracle_pauli_flag(k, t + 1) : 0;
-        int e = (up & 1) ? 3 - d : d;
-        g |= (uint64_t)e << (2 * t);
+    uint64_t code = 0;
+    for (int t = N - 1; t >= 0; t--) {
+        uint64_t d = (k >> (2 * t)) & 3u;
+        uint64_t above = t + 1 < N ? (k >> (2 * t + 2)) & 1u : 0u;
+        code = (code << 2) | (above ? 3u - d : d);
     }
-    return g;
+    return code;
 }
 
 /*
- * All 4^N coefficients with the strings enumerated in quaternary Gray order
- * and the recurrence across n of section 2: from string n to the next
- * string n', which differs at one operator position t, the XY mask keeps
- * bit t when that operator changes between identity and Z or between X
- * and Y and flips it otherwise, and
- *     lambda_0^(n') = lambda_0^(n) beta^(n',t)_{0, m'_[t]} / beta^(n,t)_{0, m_[t]},
- * so lambda_0 is never formed as an N-term product (the serial saving the
- * paper notes).  Each coefficient's sum over i is the Gray-order sum of
- * oracle_coeff_fast; since every lambda is exactly one of +-1, +-i, the
- * result equals oracle_decompose bit for bit.  out is indexed by n.
+ * All 4^N coefficients with the strings taken in quaternary Gray order and
+ * lambda_0 and the flip mask carried across strings (section 2): when the
+ * operator of qubit t changes from s to s', the mask keeps bit t for an
+ * identity-Z or X-Y change and flips it otherwise, and lambda_0 gains the
+ * factor beta' / beta of row 0 of qubit t (in quarter turns,
+ * quarter'[0] - quarter[0]).  lambda_0 is thus never formed as an N-term
+ * product.  Each coefficient's sum over i is the same Gray-order sum as in
+ * oracle_coefficient; lambda stays exactly a power of i, so the results
+ * equal oracle_decompose bit for bit.  out is indexed by n.
  */
 void oracle_decompose_qgray(const double* G, int N, double* out) {
-    uint64_t total = (uint64_t)1 << (2 * N);
-    uint64_t n = 0, m = 0;          /* the identity string: no X/Y, lambda_0 = 1 */
-    cplx l = {1.0, 0.0};
-    gray_sum(G, N, n, m, l, out);
-    for (uint64_t k = 1; k < total; k++) {
-        uint64_t nn = oracle_quaternary_gray(k, N);
+    int op[MAX_QUBITS] = {0};     /* the identity string: no X/Y, lambda_0 = 1 */
+    uint64_t n = 0, m = 0;
+    int q0 = 0;
+    gray_walk(G, N, op, m, q0, out);
+    const uint64_t strings = (uint64_t)1 << (2 * N);
+    for (uint64_t k = 1; k < strings; k++) {
+        uint64_t next = oracle_quaternary_gray(k, N);
+        uint64_t changed = n ^ next;
         int t = 0;
-        while (oracle_pauli_flag(n, t) == oracle_pauli_flag(nn, t)) t++;
-        int fo = oracle_pauli_flag(n, t), fn = oracle_pauli_flag(nn, t);
-        int same_mask = (fo == 0 && fn == 3) || (fo == 3 && fn == 0) || (fo == 1 && fn == 2) ||
-                        (fo == 2 && fn == 1);
-        uint64_t mm = same_mask ? m : (m ^ ((uint64_t)1 << t));
-        cplx bnew = PAULI[fn][0][get_bit(mm, t)];
-        cplx bold = PAULI[fo][0][get_bit(m, t)];
-        l = cmul(l, cdiv_unit(bnew, bold));
-        n = nn;
-        m = mm;
-        gray_sum(G, N, n, m, l, out + 2 * n);
+        while (!((changed >> (2 * t)) & 3u)) t++;
+        int from = op[t], to = oracle_operator_at(next, t);
+        int keep = (from == 0 && to == 3) || (from == 3 && to == 0) || (from == 1 && to == 2) ||
+                   (from == 2 && to == 1);
+        if (!keep) m ^= (uint64_t)1 << t;
+        q0 += EQ3[to].quarter[0] - EQ3[from].quarter[0];
+        op[t] = to;
+        n = next;
+        gray_walk(G, N, op, m, q0, out + 2 * n);
     }
-}
-
-/* The paper's comparison algorithm (Fig. 1b, "Slow"): natural order of i,
- * lambda_i evaluated in full for every term. */
-void oracle_coeff_slow(const double* G, int N, uint64_t n, double* out) {
-    uint64_t dim = (uint64_t)1 << N;
-    uint64_t m = oracle_xy_mask(n, N);
-    cplx c = {0.0, 0.0};
-    for (uint64_t i = 0; i < dim; i++) {
-        cplx l = get_lambda(n, i, m, N);
-        c = cadd(c, cmul(l, load(G, dim, i ^ m, i)));
-    }
-    out[0] = c.re / (double)dim;
-    out[1] = c.im / (double)dim;
 }
 
 /* Coefficients n0 <= n < n1 (out holds (n1-n0) interleaved complex values).
  * Evaluation over n is independent per coefficient (section 3, closing
  * remarks on parallelism), so disjoint ranges may run on separate threads. */
-void oracle_decompose_range(const double* G, int N, uint64_t n0, uint64_t n1,
-                            double* out) {
-    for (uint64_t n = n0; n < n1; n++) oracle_coeff_fast(G, N, n, out + 2 * (n - n0));
+void oracle_decompose_range(const double* G, int N, uint64_t n0, uint64_t n1, double* out) {
+    for (uint64_t n = n0; n < n1; n++) oracle_coefficient(G, N, n, out + 2 * (n - n0));
 }
 
 /* Full decomposition, Eq. (1): all 4^N coefficients. */
@@ -228,56 +225,62 @@ void oracle_decompose(const double* G, int N, double* out) {
 }
 
 /* Selected coefficients ns[0..count). */
-void oracle_coeffs_at(const double* G, int N, const uint64_t* ns, int64_t count,
-                      double* out) {
-    for (int64_t q = 0; q < count; q++) oracle_coeff_fast(G, N, ns[q], out + 2 * q);
+void oracle_coeffs_at(const double* G, int N, const uint64_t* ns, int64_t count, double* out) {
+    for (int64_t q = 0; q < count; q++) oracle_coefficient(G, N, ns[q], out + 2 * q);
 }
 
-/* One element [P_n]_{ij} as the product of single-qubit elements,
- * Eq. (pauli_tensor_elems_bitwise). */
-void oracle_pauli_element(uint64_t n, int N, uint64_t i, uint64_t j, double* out) {
-    cplx e = {1.0, 0.0};
+/*
+ * One element [P_n]_{ij}, Eq. (pauli_tensor_elems_bitwise): the product
+ * over qubits of [sigma_t]_{i_t, j_t}, which vanishes unless j_t is the
+ * column of row i_t's nonzero element, and is otherwise i^(sum of the
+ * quarter turns).
+ */
+static int string_element(uint64_t n, int N, uint64_t i, uint64_t j, int* quarter) {
+    int q = 0;
     for (int t = 0; t < N; t++) {
-        int p = oracle_pauli_flag(n, t);
-        e = cmul(e, PAULI[p][get_bit(i, t)][get_bit(j, t)]);
+        const eq3_matrix* s = &EQ3[oracle_operator_at(n, t)];
+        int a = (int)((i >> t) & 1u), b = (int)((j >> t) & 1u);
+        if ((a ^ b) != s->antidiagonal) return 0;
+        q += s->quarter[a];
     }
-    out[0] = e.re;
-    out[1] = e.im;
+    *quarter = q;
+    return 1;
+}
+
+void oracle_pauli_element(uint64_t n, int N, uint64_t i, uint64_t j, double* out) {
+    static const double one[2] = {1.0, 0.0};
+    int q;
+    out[0] = 0.0;
+    out[1] = 0.0;
+    if (string_element(n, N, i, j, &q)) accumulate_rotated(out, one, q);
 }
 
 /*
  * Entries of the recomposed matrix sum_n c_n P_n (Eq. (1)) at positions
- * (rows[q], cols[q]).  Every Pauli matrix is diagonal or anti-diagonal
- * (section 2, beta labelling), so [P_n]_{ab} vanishes unless operator t is
- * identity/Z where a and b agree on bit t, and X/Y where they differ; the
- * sum therefore runs over the 2^N strings allowed by that rule, each term
- * weighted by the element of Eq. (pauli_tensor_elems_bitwise).  The strings
- * are visited in increasing order of n.  scale multiplies the result.
+ * (rows[q], cols[q]).  [P_n]_{ab} vanishes unless every qubit where a and b
+ * differ carries an anti-diagonal operator (X or Y) and every other qubit a
+ * diagonal one (identity or Z), so only 2^N strings contribute: one binary
+ * choice per qubit.  They are visited in increasing order of n, each term
+ * c_n * [P_n]_{ab} formed as an exact rotation.  scale multiplies the result.
  */
-void oracle_recompose_entries(const double* c, int N, const uint64_t* rows,
-                              const uint64_t* cols, int64_t count, double scale,
-                              double* out) {
-    uint64_t dim = (uint64_t)1 << N;
-    for (int64_t q = 0; q < count; q++) {
-        uint64_t a = rows[q], b = cols[q];
-        cplx acc = {0.0, 0.0};
-        for (uint64_t s = 0; s < dim; s++) {
+void oracle_recompose_entries(const double* c, int N, const uint64_t* rows, const uint64_t* cols,
+                              int64_t count, double scale, double* out) {
+    for (int64_t e = 0; e < count; e++) {
+        uint64_t a = rows[e], b = cols[e];
+        double acc[2] = {0.0, 0.0};
+        for (uint64_t s = 0; s < ((uint64_t)1 << N); s++) {
             uint64_t n = 0;
-            for (int t = 0; t < N; t++) {
-                int differ = get_bit(a, t) ^ get_bit(b, t);
-                int choice = get_bit(s, t);
+            for (int t = N - 1; t >= 0; t--) {
+                int differ = (int)(((a ^ b) >> t) & 1u);
+                int choice = (int)((s >> t) & 1u);
                 /* agree: identity (0) or Z (3); differ: X (1) or Y (2) */
-                uint64_t flag = differ ? (uint64_t)(1 + choice) : (uint64_t)(3 * choice);
-                n |= flag << (2 * t);
+                n = (n << 2) | (uint64_t)(differ ? 1 + choice : 3 * choice);
             }
-            double e[2];
-            oracle_pauli_element(n, N, a, b, e);
-            cplx pe = {e[0], e[1]};
-            cplx cn = {c[2 * n], c[2 * n + 1]};
-            acc = cadd(acc, cmul(cn, pe));
+            int q;
+            if (string_element(n, N, a, b, &q)) accumulate_rotated(acc, c + 2 * n, q);
         }
-        out[2 * q] = acc.re * scale;
-        out[2 * q + 1] = acc.im * scale;
+        out[2 * e] = acc[0] * scale;
+        out[2 * e + 1] = acc[1] * scale;
     }
 }
 
@@ -298,7 +301,7 @@ void oracle_recompose(const double* c, int N, double* G) {
  * every Pauli string is Hermitian, so the gradient is the recomposition of
  * gc scaled by 2^-N.
  */
-void oracle_grad_entries(const double* gc, int N, const uint64_t* rows,
-                         const uint64_t* cols, int64_t count, double* out) {
-    oracle_recompose_entries(gc, N, rows, cols, count, 1.0 / (double)((uint64_t)1 << N), out);
+void oracle_grad_entries(const double* gc, int N, const uint64_t* rows, const uint64_t* cols,
+                         int64_t count, double* out) {
+    oracle_recompose_entries(gc, N, rows, cols, count, ldexp(1.0, -N), out);
 }

@@ -93,9 +93,9 @@ def test_flags_and_mask():
         n = int(rng.integers(0, 4 ** N))
         ds = pr.digits(n, N)
         for t in range(N):
-            assert oracle.pauli_flag(n, t) == ds[t]
+            assert oracle.operator_at(n, t) == ds[t]
         m = sum((1 << t) for t in range(N) if ds[t] in (1, 2))
-        assert oracle.xy_mask(n, N) == m
+        assert oracle.flip_mask(n, N) == m
 
 
 @pytest.mark.parametrize("N", [1, 2, 3, 5, 7])
@@ -103,8 +103,8 @@ def test_fast_vs_slow(N):
     G = workloads.iid_complex(N, 7 + N)
     ns = range(4 ** N) if N <= 5 else workloads.sample_indices(4 ** N, 300, seed=N)
     for n in ns:
-        a = oracle.coeff_fast(G, int(n))
-        b = oracle.coeff_slow(G, int(n))
+        a = oracle.coefficient(G, int(n))
+        b = oracle.coefficient_natural(G, int(n))
         assert abs(a - b) <= 1e-13 * max(1.0, abs(b))
 
 
@@ -262,10 +262,10 @@ def test_quaternary_gray_order(N):
     assert seq[0] == 0
     assert sorted(seq) == list(range(4 ** N))
     for a, b in zip(seq, seq[1:]):
-        diff = [t for t in range(N) if oracle.pauli_flag(a, t) != oracle.pauli_flag(b, t)]
+        diff = [t for t in range(N) if oracle.operator_at(a, t) != oracle.operator_at(b, t)]
         assert len(diff) == 1
         t = diff[0]
-        assert abs(oracle.pauli_flag(a, t) - oracle.pauli_flag(b, t)) == 1
+        assert abs(oracle.operator_at(a, t) - oracle.operator_at(b, t)) == 1
 
 
 def test_quaternary_gray_two_digits():
