@@ -175,7 +175,7 @@ size_t pauli_batched_workspace_bytes(int count, const int* N, int algo);
 /* Number of persistent-kernel tile shapes for the uneven batch. */
 int pauli_batched_tile_count(void);
 
-/* 1 if batched tile shape `tile` can run `algo` (FP32 excludes shape 3). */
+/* 1 if batched tile shape `tile` can run `algo` (every shape runs SPLIT_BF16 and FP32). */
 int pauli_batched_tile_valid(int algo, int tile);
 
 /*

@@ -546,7 +546,10 @@ int tuned_btile(int planes, int count, const int* N) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_cache_locked();
     auto it = g_btile.find({planes, ns});
-    return it == g_btile.end() ? 1 : it->second;
+    // a cached shape that is out of range or not built for these planes (a
+    // hand-edited or stale file) falls back to shape 1, which every algo has
+    if (it == g_btile.end() || !batched_tile_valid(planes, it->second)) return 1;
+    return it->second;
 }
 
 int run_batched(int count, const void* const* G, const int* N, void* const* out, const pauli_opts& o, int btile,

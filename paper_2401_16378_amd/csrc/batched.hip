@@ -111,13 +111,14 @@ __global__ __launch_bounds__(WAVES * 64, 2) void contract_batched2_kernel(const 
 struct BTile {
     int rb, waves, pf, occ, ahead = 0;
 };
+// (4 x 32 rows per wave does not fit the persistent loop's registers: its
+// accumulators, ring and tile bookkeeping would spill.)
 constexpr BTile BTILES[] = {
     {2, 4, 4, 1},     // 1: 256 rows per output tile
     {1, 4, 2, 1},     // 2: 128 rows
-    {4, 4, 4, 1},     // 3: 512 rows
-    {1, 2, 2, 1},     // 4: 64 rows
-    {2, 4, 2, 2},     // 5: 256 rows, shallower ring, two workgroups per CU
-    {2, 4, 2, 1, 3},  // 6: 256 rows, LDS-staged 3 pairs ahead (ring for small matrices)
+    {1, 2, 2, 1},     // 3: 64 rows
+    {2, 4, 2, 2},     // 4: 256 rows, shallower ring, two workgroups per CU
+    {2, 4, 2, 1, 3},  // 5: 256 rows, LDS-staged 3 pairs ahead (ring for small matrices)
 };
 constexpr int NBTILES = sizeof(BTILES) / sizeof(BTILES[0]);
 
@@ -157,10 +158,9 @@ hipError_t launch_contract_btile(int btile, const BatchItem* items, const uint32
     switch (btile) {
         case 1: return launch_contract_batched<PLANES, 2, 4, 4, 1>(items, tile_slot, total, ws, counter, s);
         case 2: return launch_contract_batched<PLANES, 1, 4, 2, 1>(items, tile_slot, total, ws, counter, s);
-        case 3: return launch_contract_batched<PLANES, 4, 4, 4, 1>(items, tile_slot, total, ws, counter, s);
-        case 4: return launch_contract_batched<PLANES, 1, 2, 2, 1>(items, tile_slot, total, ws, counter, s);
-        case 5: return launch_contract_batched<PLANES, 2, 4, 2, 2>(items, tile_slot, total, ws, counter, s);
-        case 6: return launch_contract_batched<PLANES, 2, 4, 2, 1, 3>(items, tile_slot, total, ws, counter, s);
+        case 3: return launch_contract_batched<PLANES, 1, 2, 2, 1>(items, tile_slot, total, ws, counter, s);
+        case 4: return launch_contract_batched<PLANES, 2, 4, 2, 2>(items, tile_slot, total, ws, counter, s);
+        case 5: return launch_contract_batched<PLANES, 2, 4, 2, 1, 3>(items, tile_slot, total, ws, counter, s);
         default: return hipErrorInvalidValue;
     }
 }

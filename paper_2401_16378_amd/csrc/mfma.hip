@@ -37,7 +37,7 @@ struct Params {
 };
 
 template <int PLANES, int RB, int WAVES, int DIR, int PF, bool HERM = false>
-__global__ __launch_bounds__(WAVES * 64) void contract_kernel(Params prm) {
+__global__ __launch_bounds__(WAVES * 64 > 256 ? WAVES * 64 : 256) void contract_kernel(Params prm) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     constexpr int MT = WAVES * RB * 32;
     const uint32_t D = 1u << prm.N, Dp = padded_dim(prm.N);

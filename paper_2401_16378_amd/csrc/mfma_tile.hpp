@@ -378,7 +378,14 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&
                                   int N, uint32_t X0, uint32_t Pw, double scale, int out128, unsigned char* lds) {
     constexpr int ACC = PLANES == 3 ? 2 : 1;
     const uint32_t D = 1u << N;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // The thread index passes through an empty asm statement, so that the
+    // staging addresses derived from it are formed here, at each call, and
+    // not hoisted by the compiler into registers held across the contraction
+    // (in the persistent kernel's tile loop they would otherwise stay live
+    // next to the accumulators and spill).
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
     const int esz = out128 ? 16 : 8;
     unsigned char* stage = lds + wave * 1024 * esz;
@@ -497,7 +504,9 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
             return c;
         }
     };
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));   // per call, as in store_tile
+    const int lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
     const uint32_t Pw = mb * MT + wave * RB * 32;          // first row of this wave
     const unsigned char* wsx = wsm + (size_t)xb * nS * P::SLICE_BYTES + lane * 16;

@@ -118,7 +118,9 @@ def test_tiles(lib):
     assert lib.pauli_tile_valid(0, 1, 10) == 1 and lib.pauli_tile_valid(0, 2, 10) == 0
     assert lib.pauli_tile_valid(2, 0, 10) == 0 and lib.pauli_tile_valid(2, n + 1, 10) == 0
     assert lib.pauli_batched_tile_count() >= 1
-    assert lib.pauli_batched_tile_valid(2, 3) == 1 and lib.pauli_batched_tile_valid(1, 3) == 0
+    nb = lib.pauli_batched_tile_count()
+    assert all(lib.pauli_batched_tile_valid(a, t) == 1 for a in (1, 2) for t in range(1, nb + 1))
+    assert lib.pauli_batched_tile_valid(2, nb + 1) == 0 and lib.pauli_batched_tile_valid(1, 0) == 0
     assert lib.pauli_batched_tile_valid(1, 1) == 1 and lib.pauli_batched_tile_valid(0, 1) == 0
 
 
@@ -142,7 +144,7 @@ def test_batched_validation(lib, pauli):
     assert lib.pauli_decompose_batched(2, G, Ns, O, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_batched_workspace_bytes(2, bad, 2) == 0
     assert lib.pauli_batched_tile_selected(2, Ns, 2) >= 1
-    ws = opts(pauli, algo="fp32", tile=3, ws=0x40000000, ws_bytes=need)
+    ws = opts(pauli, algo="fp32", tile=lib.pauli_batched_tile_count() + 1, ws=0x40000000, ws_bytes=need)
     assert lib.pauli_decompose_batched(2, G, Ns, O, ctypes.byref(ws)) == EINVAL
 
 
@@ -303,3 +305,33 @@ def test_tune_cache_file_is_read(tmp_path):
     tile, btile, btile_fp32 = map(int, r.stdout.split())
     assert (tile, btile) == (3, 4)
     assert btile_fp32 == 1                       # binary32 has no entry: the default shape
+
+
+def test_tune_cache_invalid_tiles_fall_back(tmp_path):
+    """A tune file naming a tile that does not exist, or one that the algo
+    does not build (binary32 has no 4 x 32-row register-ring tiles), is not
+    used: the lookups return the default shapes instead."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    cache.write_text("2 10 99\n"
+                     "1 10 1\n"                                  # fp32 register ring RB=4: not built
+                     "B 3 9 0 0 1 1 2 1 0 0 0 0 0 0\n"           # shape 9 does not exist
+                     "B 1 -2 0 0 1 1 2 1 0 0 0 0 0 0\n"          # negative shape
+                     "B 3 0 0 0 0 1 0 0 0 0 0 0 0 0\n")          # shape 0 for one N=5
+    code = (
+        "import sys, ctypes; sys.path.insert(0, %r)\n"
+        "import paper_2401_16378_amd as p\n"
+        "lib = p.load_library()\n"
+        "Na = (ctypes.c_int * 5)(5, 3, 6, 4, 5)\n"
+        "Nb = (ctypes.c_int * 1)(5)\n"
+        "print(lib.pauli_tile_selected(2, 10), lib.pauli_tile_selected(1, 10),"
+        " lib.pauli_batched_tile_selected(5, Na, 2), lib.pauli_batched_tile_selected(5, Na, 1),"
+        " lib.pauli_batched_tile_selected(1, Nb, 2))\n"
+    ) % ROOT
+    env = dict(os.environ, PAULI_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    t_bf16, t_fp32, b_bf16, b_fp32, b_one = map(int, r.stdout.split())
+    assert t_bf16 == 1 and t_fp32 == 15          # the defaults at N=10
+    assert (b_bf16, b_fp32, b_one) == (1, 1, 1)

@@ -10,55 +10,31 @@ torch.autograd) is checked on 64 seeded entries against
     differences are exact up to rounding).
 
 Tolerance: 1e-5 max|grad| for split-bf16 and fp32, 1e-10 for binary64.
+The oracle gradient itself is pinned to the finite differences on the CPU.
 """
-import os
-
 import numpy as np
 import pytest
 import torch
 
-import oracle
-import workloads
-from tests import pauli_ref as pr
+from tests import backward_workload as bw
 
 pytestmark = pytest.mark.gpu
 
-N = 11
-D = 1 << N
 TOL = {"split_bf16": 1e-5, "fp32": 1e-5, "fp64_gray": 1e-10, "fwht": 1e-10}
-
-
-def threads():
-    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 @pytest.fixture(scope="module")
 def problem():
-    G, G2, w = workloads.backward_problem(N, 8)
-    rng = np.random.default_rng(workloads.SEED_BWD_W + 1)
-    flat = rng.choice(8 * D * D, size=64, replace=False)
-    b, rem = np.divmod(flat, D * D)
-    rows, cols = np.divmod(rem, D)
-    # oracle coefficients of G and G2 on every string touching a sampled entry
-    ref = []
-    for q in range(64):
-        x = int(rows[q]) ^ int(cols[q])
-        ns = np.array([pr.n_of_xz(x, z, N) for z in range(D)], dtype=np.uint64)
-        c = oracle.coeffs_at(G[b[q]].astype(np.complex128), ns, threads=threads())
-        t = oracle.coeffs_at(G2[b[q]].astype(np.complex128), ns, threads=threads())
-        ref.append((ns, c, t))
-    return G, G2, w, (b, rows, cols), ref
+    return bw.make_problem()
+
+
+@pytest.fixture(scope="module")
+def finite_differences(problem):
+    return bw.make_finite_differences(problem)
 
 
 def oracle_gradient(problem):
-    G, G2, w, (b, rows, cols), ref = problem
-    out = np.zeros(64, dtype=np.complex128)
-    for q in range(64):
-        ns, c, t = ref[q]
-        gc = np.zeros(4 ** N, dtype=np.complex128)
-        gc[ns.astype(np.int64)] = 2.0 * w[b[q], ns.astype(np.int64)] * (c - t)
-        out[q] = oracle.grad_entries(gc, rows[q:q + 1], cols[q:q + 1])[0]
-    return out
+    return bw.oracle_gradient(problem)
 
 
 def gpu_gradient(problem, algo):
@@ -75,32 +51,22 @@ def gpu_gradient(problem, algo):
     return g.to(torch.complex128).cpu().numpy()
 
 
-def test_oracle_gradient_vs_finite_differences(problem):
-    """Pins the oracle gradient of this workload to central differences."""
-    G, G2, w, (b, rows, cols), ref = problem
-    grad = oracle_gradient(problem)
-    h = 1e-3
-    for q in range(0, 64, 4):   # 16 of the 64 entries keep the CPU time small
-        ns, c, t = ref[q]
-        Gq = G[b[q]].astype(np.complex128)
-        idx = ns.astype(np.int64)
-        wq = w[b[q], idx]
-
-        def loss_delta(delta):
-            Gp = Gq.copy()
-            Gp[rows[q], cols[q]] += delta
-            cp = oracle.coeffs_at(Gp, ns, threads=threads())
-            return float(np.sum(wq * np.abs(cp - t) ** 2))
-
-        d_re = (loss_delta(h) - loss_delta(-h)) / (2 * h)
-        d_im = (loss_delta(1j * h) - loss_delta(-1j * h)) / (2 * h)
-        fd = d_re + 1j * d_im
-        assert abs(grad[q] - fd) <= 1e-8 * np.abs(grad).max(), (q, grad[q], fd)
-
-
 @pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray", "fwht"])
 def test_adjoint_gradient_vs_oracle(problem, algo):
     ref = oracle_gradient(problem)
     got = gpu_gradient(problem, algo)
     err = np.abs(got - ref).max() / np.abs(ref).max()
     assert err <= TOL[algo], err
+
+
+@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray", "fwht"])
+def test_adjoint_gradient_vs_finite_differences(problem, finite_differences, algo):
+    """The GPU gradient (hand-written adjoint through torch.autograd) against
+    the central differences directly, all 64 entries.  The differences carry
+    a rounding error near 1e-10 of max|grad| (binary64 losses of order one
+    divided by 2h), so the binary64 algorithms are held to 1e-8 here; their
+    1e-10 bar is met against the oracle's gradient above."""
+    fd = finite_differences
+    got = gpu_gradient(problem, algo)
+    err = np.abs(got - fd).max() / np.abs(fd).max()
+    assert err <= max(TOL[algo], 1e-8), err

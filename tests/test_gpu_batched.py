@@ -69,7 +69,7 @@ def test_batch_bitexact_vs_single(batch):
         assert torch.equal(outs[k], single), k
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 def test_every_tile_shape(batch, tile):
     p = lib()
     Ns, mats, herm, dev = batch
@@ -143,7 +143,7 @@ def test_small_mixed_batch_fp32():
     mats = [workloads.iid_complex(n, 40 + n, np.complex64) for n in Ns]
     dev_m = [torch.from_numpy(m).to("cuda") for m in mats]
     tiles = [t for t in range(1, p.load_library().pauli_batched_tile_count() + 1) if p.batched_tile_valid(t, "fp32")]
-    assert 3 not in tiles and len(tiles) >= 3
+    assert len(tiles) == p.load_library().pauli_batched_tile_count()   # every shape runs binary32
     for tile in tiles:
         outs = p.decompose_batched(dev_m, algo="fp32", tile=tile)
         for m, o in zip(mats, outs):

@@ -76,7 +76,7 @@ def test_mfma_every_tile_n9(algo, tile):
     G = workloads.iid_complex(N, 700 + tile, np.complex64)
     c = p.decompose(dev(G), algo=algo, tile=tile).cpu().numpy()
     ref = oracle.decompose(G, threads=8)
-    assert rel_err(c, ref) <= TOL[algo] * 1.5  # c64 output rounding included
+    assert rel_err(c, ref) <= TOL[algo]
 
 
 @pytest.mark.parametrize("algo", ["fp32", "split_bf16"])
