@@ -298,6 +298,29 @@ const char* pauli_last_error(void);
 int pauli_pack(const void* in, int N, int batch, int mode, const pauli_opts* opts);
 int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts);
 
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * pauli_decompose with every argument, limit and result as there, except
+ * that the device scratch of the algorithm (the packed operand of SPLIT_BF16
+ * and FP32, the binary64 intermediate of FWHT; FP64_GRAY needs none) is a
+ * fixed array of pauli_noalloc_scratch_bytes() bytes (64 MiB) that the
+ * library holds on each GPU it runs on until the process ends, so the call
+ * itself allocates nothing (no hipMalloc, no pool, no host allocation of
+ * device memory).  opts->workspace and opts->workspace_bytes are ignored.
+ * A request whose scratch exceeds the array (pauli_workspace_bytes(algo, N,
+ * batch) > 64 MiB, e.g. SPLIT_BF16 at N >= 12, or batch > 1 at N = 11)
+ * fails with PAULI_ENOMEM before any launch.  All calls on one GPU share its
+ * array: calls that overlap in time on one GPU (different streams or host
+ * threads without ordering) race and give undefined results; calls ordered
+ * on one stream are safe.  Nothing in the array needs to start at zero:
+ * each call writes every byte it later reads.
+ */
+int pauli_decompose_noalloc(const void* G, int N, int batch, void* out, const pauli_opts* opts);
+
+/* Size in bytes of the fixed per-GPU scratch of pauli_decompose_noalloc. */
+size_t pauli_noalloc_scratch_bytes(void);
+
 /* Library ABI version, currently 1. */
 int pauli_version(void);
 

@@ -52,7 +52,8 @@ EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_
            "pauli_batched_tile_selected", "pauli_autotune", "pauli_tile_count", "pauli_tile_valid",
            "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_coeffs_at", "pauli_coeffs_at_backward",
            "pauli_decompose_hermitian", "pauli_tile_valid_hermitian",
-           "pauli_coeffs_at_workspace_bytes", "pauli_last_error", "pauli_version"]
+           "pauli_coeffs_at_workspace_bytes", "pauli_last_error", "pauli_version",
+           "pauli_decompose_noalloc", "pauli_noalloc_scratch_bytes"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -68,7 +69,7 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_opts_default.argtypes = [op]
         lib.pauli_opts_default.restype = None
         for name in ("pauli_decompose", "pauli_reconstruct", "pauli_decompose_backward",
-                     "pauli_decompose_hermitian"):
+                     "pauli_decompose_hermitian", "pauli_decompose_noalloc"):
             getattr(lib, name).argtypes = [vp, ci, ci, vp, op]
             getattr(lib, name).restype = ci
         lib.pauli_decompose_batched.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(ci),
@@ -109,6 +110,8 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_coeffs_at_workspace_bytes.restype = ctypes.c_size_t
         lib.pauli_last_error.argtypes = []
         lib.pauli_last_error.restype = ctypes.c_char_p
+        lib.pauli_noalloc_scratch_bytes.argtypes = []
+        lib.pauli_noalloc_scratch_bytes.restype = ctypes.c_size_t
         lib.pauli_version.argtypes = []
         lib.pauli_version.restype = ci
         _lib = lib
@@ -213,6 +216,21 @@ def decompose(G: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: i
     o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G), workspace(algo, N, batch, G.device))
     with _on(G.device):
         _check(load_library().pauli_decompose(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def decompose_noalloc(G: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: int = 0) -> torch.Tensor:
+    """decompose() through pauli_decompose_noalloc: the library's fixed
+    per-GPU scratch instead of a workspace (only the output is allocated
+    here, by torch)."""
+    G = _prep(G)
+    N = _qubits_of_matrix(G)
+    out_dtype = out_dtype or G.dtype
+    batch = G.numel() // (1 << (2 * N))
+    out = torch.empty(G.shape[:-2] + (1 << (2 * N),), dtype=out_dtype, device=G.device)
+    o = _opts(algo, _DT[G.dtype], _DT[out_dtype], tile, _stream(G))
+    with _on(G.device):
+        _check(load_library().pauli_decompose_noalloc(G.data_ptr(), N, batch, out.data_ptr(), ctypes.byref(o)))
     return out
 
 

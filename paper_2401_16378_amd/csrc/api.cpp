@@ -265,6 +265,34 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
     return PAULI_OK;
 }
 
+// Fixed device scratch of pauli_decompose_noalloc: one copy per GPU, held
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not the device copy: kernels get the device address looked up once per
+// device with hipGetSymbolAddress (with that device current) and kept here.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> address of its copy
+
+hipError_t scratch_for_current_device(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+    *ptr = p;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -286,6 +314,31 @@ int pauli_decompose(const void* G, int N, int batch, void* out, const pauli_opts
     if (st != PAULI_OK) return st;
     return run(FORWARD, G, N, batch, out, o, 1.0 / (double)(1u << N), "pauli_decompose");
 }
+
+int pauli_decompose_noalloc(const void* G, int N, int batch, void* out, const pauli_opts* opts) {
+    const char* fn = "pauli_decompose_noalloc";
+    pauli_opts o = resolve(opts);
+    o.workspace = nullptr;
+    o.workspace_bytes = 0;
+    int st = check_common(G, N, batch, out, o, fn);
+    if (st != PAULI_OK) return st;
+    size_t need = 0;
+    if (o.algo == PAULI_ALGO_FWHT) need = fwht_workspace_bytes(N, batch);
+    else if (is_mfma(o.algo)) need = mfma_workspace_bytes(planes_of(o.algo), N, batch);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(PAULI_ENOMEM, "%s: algo %d at N=%d, batch %d needs %zu bytes of scratch; the fixed scratch holds %zu",
+                    fn, o.algo, N, batch, need, NOALLOC_SCRATCH_BYTES);
+    if (need > 0) {
+        void* p = nullptr;
+        const hipError_t e = scratch_for_current_device(&p);
+        if (e != hipSuccess) return hip_fail(e, fn);
+        o.workspace = p;
+        o.workspace_bytes = NOALLOC_SCRATCH_BYTES;
+    }
+    return run(FORWARD, G, N, batch, out, o, 1.0 / (double)(1u << N), fn);
+}
+
+size_t pauli_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
 int pauli_decompose_hermitian(const void* G, int N, int batch, void* out, const pauli_opts* opts) {
     const char* fn = "pauli_decompose_hermitian";

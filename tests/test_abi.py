@@ -335,3 +335,23 @@ def test_tune_cache_invalid_tiles_fall_back(tmp_path):
     t_bf16, t_fp32, b_bf16, b_fp32, b_one = map(int, r.stdout.split())
     assert t_bf16 == 1 and t_fp32 == 15          # the defaults at N=10
     assert (b_bf16, b_fp32, b_one) == (1, 1, 1)
+
+
+def test_noalloc_validation(lib, pauli):
+    """The no-allocation entry point checks its arguments like
+    pauli_decompose and refuses, before any HIP call, a request whose scratch
+    exceeds the fixed array."""
+    assert lib.pauli_noalloc_scratch_bytes() == 64 << 20
+    o = opts(pauli)
+    f = lib.pauli_decompose_noalloc
+    assert f(FAKE_IN, -1, 1, FAKE_OUT, ctypes.byref(o)) == EINVAL
+    assert f(None, 4, 1, FAKE_OUT, ctypes.byref(o)) == EINVAL
+    assert f(FAKE_IN, 4, 0, FAKE_OUT, ctypes.byref(o)) == EINVAL
+    assert f(FAKE_IN, 12, 1, FAKE_OUT, ctypes.byref(o)) == ENOMEM            # 192 MiB packed operand
+    assert "fixed scratch" in pauli.last_error()
+    assert f(FAKE_IN, 11, 2, FAKE_OUT, ctypes.byref(o)) == ENOMEM            # 2 x 48 MiB
+    assert f(FAKE_IN, 12, 1, FAKE_OUT, ctypes.byref(opts(pauli, algo="fwht"))) == ENOMEM
+    assert f(FAKE_IN, 17, 1, FAKE_OUT, ctypes.byref(opts(pauli, algo="fwht"))) == EINVAL
+    # a workspace in the options is ignored, not checked against the buffers
+    ws = opts(pauli, ws=FAKE_IN, ws_bytes=1 << 30)
+    assert f(FAKE_IN, 12, 1, FAKE_OUT, ctypes.byref(ws)) == ENOMEM
