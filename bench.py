@@ -40,6 +40,10 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2401_16378_amd/csrc/mfma_tile.hpp", "paper_2401_16378_amd/csrc/mfma.hip",
                   "paper_2401_16378_amd/csrc/common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_bf16_n14.json")
+TRAFFIC_FILES = {"split_bf16": TRAFFIC_FILE,
+                 "split_fp16": os.path.join(ROOT, "profiles", "traffic_split_fp16_n14.json")}
+PLANES = {"split_bf16": 3, "split_fp16": 2, "fp32": 1}
+DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "fp32": "f32"}
 STRINGS_SOURCES = ["paper_2401_16378_amd/csrc/strings.hip", "paper_2401_16378_amd/csrc/common.hpp"]
 STRINGS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_strings_n14.json")
 FWHT_SOURCES = ["paper_2401_16378_amd/csrc/fwht.hip", "paper_2401_16378_amd/csrc/common.hpp"]
@@ -383,8 +387,9 @@ def main():
     ws = pauli.workspace(a.algo, N, 1, dev)
     o = pauli._opts(a.algo, 0, 0, a.tile, ctypes.c_void_p(stream.cuda_stream), ws)
     herm = a.workload == "hermitian"
-    if herm and a.algo != "split_bf16":
-        raise SystemExit("bench.py: the hermitian workload times the split_bf16 algorithm")
+    if a.algo not in PLANES:
+        raise SystemExit("bench.py: the n14 and hermitian workloads time a matrix-core algorithm (%s)"
+                         % ", ".join(PLANES))
     mode = 3 if herm else 0   # 3: pauli_decompose_hermitian split at the kernel boundary
 
     def step(mid=None):
@@ -413,22 +418,26 @@ def main():
     wall = time.perf_counter() - t0
     launch_ms = [m.elapsed_time(e) for b, m, e in evs]      # contraction kernel
     pack_ms = float(np.mean([b.elapsed_time(m) for b, m, e in evs]))
+    step_ms = [b.elapsed_time(e) for b, m, e in evs]        # whole step, per step
     ms_step = wall * 1000.0 / a.steps
     mean_launch = float(np.mean(launch_ms))
     coeffs = float(4 ** N)
     value = coeffs / (ms_step / 1000.0)
-    planes = 3 if a.algo == "split_bf16" else 1
+    planes = PLANES[a.algo]
     flops_exec = 2.0 * 2.0 * planes * float(8 ** N)   # 2 (re,im) x 2 flop/MAC x planes x D^3
-    flops_useful = 4.0 * float(8 ** N)
+    flops_useful = 4.0 * float(8 ** N)                 # the method's own work (section 3)
     if herm:
         # the Hermitian variant's algorithmic work: half of K for every flip mask
         # (the first few flip-mask tiles walk all of K, so this undercounts)
         flops_exec /= 2.0
         flops_useful /= 2.0
-    achieved = flops_exec / (mean_launch / 1000.0) / 1e12
-    peak = PEAK_BF16_TFLOPS if a.algo == "split_bf16" else 157.3
-    log("[bench] %.3f ms/step, pack %.3f ms, contraction %.3f ms, %.1f TFLOP/s executed"
-        % (ms_step, pack_ms, mean_launch, achieved))
+    achieved = flops_useful / (mean_launch / 1000.0) / 1e12
+    executed = flops_exec / (mean_launch / 1000.0) / 1e12
+    peak = 157.3 if a.algo == "fp32" else PEAK_BF16_TFLOPS   # bf16 and fp16 share the dense peak
+    log("[bench] %.3f ms/step (median %.3f), pack %.3f ms, contraction %.3f ms (median %.3f), "
+        "%.1f TFLOP/s useful, %.1f executed"
+        % (ms_step, float(np.median(step_ms)), pack_ms, mean_launch, float(np.median(launch_ms)), achieved,
+           executed))
 
     c_bf16 = out.cpu().numpy()
     res = {}
@@ -463,16 +472,20 @@ def main():
 
     # committed counter summaries cover the split-bf16 kernels at N=14 only
     tile_used = a.tile if a.tile else pauli.tile_selected(N, a.algo)   # the general path's choice
-    traffic = (measured_traffic(HERM_TRAFFIC_FILE if herm else TRAFFIC_FILE)
-               if (N == 14 and a.algo == "split_bf16") else None)
+    traffic = None
+    if N == 14 and herm and a.algo == "split_bf16":
+        traffic = measured_traffic(HERM_TRAFFIC_FILE)
+    elif N == 14 and not herm and a.algo in TRAFFIC_FILES:
+        traffic = measured_traffic(TRAFFIC_FILES[a.algo])
     if herm:
         res["imag_exactly_zero"] = bool(np.all(c_bf16.imag == 0))
     line = {
-        "metric": METRIC_HERM if herm else (METRIC if a.algo == "split_bf16" else
+        "metric": METRIC_HERM if herm else (METRIC if a.algo in ("split_bf16", "split_fp16") else
                                             "Pauli coeffs/sec + %% MFMA peak at N=%d, %s matrix-core path"
                                             % (N, a.algo)), "value": value, "unit": "coeffs/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16" if a.algo == "split_bf16" else "f32", "data": "synthetic",
+        "warmup": a.warmup, "ms_per_step": ms_step, "ms_per_step_median": float(np.median(step_ms)),
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[a.algo], "data": "synthetic",
         "config": {"workload": "dense Pauli decomposition, N=%d (%dx%d complex64 Hermitian, "
                                "G=(A+A^H)/2, A iid N(0,1)), all 4^%d coefficients, %s%s"
                                % (N, 1 << N, 1 << N, N, a.algo,
@@ -481,8 +494,12 @@ def main():
                    "algo": a.algo, "tile": tile_used},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "useful_frac": flops_useful / (mean_launch / 1000.0) / 1e12 / peak,
-                     "launch_ms": mean_launch, "flops_per_launch": flops_exec,
+                     "counts": "the method's own flops, 4*8^N (re, im x 2 flop per term)%s; executed "
+                               "matrix-core flops (%d planes) in executed_*" % (", halved" if herm else "", planes),
+                     "flops_per_launch": flops_useful,
+                     "executed_tflops": executed, "executed_frac": executed / peak,
+                     "executed_flops_per_launch": flops_exec,
+                     "launch_ms": mean_launch, "launch_ms_median": float(np.median(launch_ms)),
                      "kernel": "%s%s (%s, tile %d)" % ("contract_lds_kernel" if tile_used >= 13 else "contract_kernel",
                                                       " <..., HERM=true>" if herm else "", a.algo, tile_used),
                      "pack_ms": pack_ms},

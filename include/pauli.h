@@ -79,7 +79,18 @@ typedef enum pauli_algo {
      * through a workspace of 16 bytes per matrix element (N >= 9; up to
      * N = 8 one kernel works in LDS and needs none).  All three directions
      * (decompose, reconstruct, backward), 0 <= N <= 16. */
-    PAULI_ALGO_FWHT = 3
+    PAULI_ALGO_FWHT = 3,
+    /* The matrix-core contraction of FP32 and SPLIT_BF16 on two fp16 planes:
+     * a reduction pass finds the largest |re|, |im| of each input and a
+     * power of two 2^pe brings it just below 2^15; each scaled binary32
+     * component g is then split as g = hi + 2^-11 lo + r, hi with at most 11
+     * significant bits on a power-of-two grid shared by a 4x4 block of G, lo
+     * the fp16 rounding of 2^11 (g - hi), |r| <= 2^-24 of the block's
+     * largest component; fp16 MFMA with one FP32 accumulator per plane,
+     * recombined in binary64 (hi + 2^-11 lo) with 2^-pe folded into the
+     * output scale.  Two thirds of SPLIT_BF16's matrix-core work; finite
+     * inputs only (an infinite or NaN component gives unspecified output). */
+    PAULI_ALGO_SPLIT_FP16 = 4
 } pauli_algo;
 
 typedef struct pauli_opts {
@@ -202,7 +213,10 @@ size_t pauli_workspace_bytes(int algo, int N, int batch);
 
 /*
  * Time every tile configuration of `algo` for N_min <= N <= N_max on the
- * current device (allocating and freeing its own scratch matrices), keep the
+ * current device (allocating and freeing its own scratch matrices, timed on
+ * a fixed pseudo-random matrix with components uniform on [-1, 1), since
+ * the power drawn by the matrix cores, and so the clock, depends on the
+ * operand values), keep the
  * fastest per N in the process-wide tune table, and write the table to the
  * file named by the PAULI_TUNE_CACHE environment variable if it is set.
  * Blocking.  opts supplies algo and stream (may be NULL: SPLIT_BF16).

@@ -49,11 +49,12 @@ size_t elem_bytes(int dtype) { return dtype == PAULI_C128 ? 16 : 8; }
 
 bool valid_dtype(int d) { return d == PAULI_C64 || d == PAULI_C128; }
 bool valid_algo(int a) {
-    return a == PAULI_ALGO_FP64_GRAY || a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16 || a == PAULI_ALGO_FWHT;
+    return a == PAULI_ALGO_FP64_GRAY || a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16 || a == PAULI_ALGO_FWHT ||
+           a == PAULI_ALGO_SPLIT_FP16;
 }
 
 // Matrix-core algorithms (packed operand, tile shapes, separate passes).
-bool is_mfma(int a) { return a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16; }
+bool is_mfma(int a) { return a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16 || a == PAULI_ALGO_SPLIT_FP16; }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     const char* pa = (const char*)a;
@@ -125,7 +126,9 @@ bool save_tune_cache_locked() {
     return true;
 }
 
-int planes_of(int algo) { return algo == PAULI_ALGO_SPLIT_BF16 ? 3 : 1; }
+int planes_of(int algo) {
+    return algo == PAULI_ALGO_SPLIT_BF16 ? 3 : (algo == PAULI_ALGO_SPLIT_FP16 ? 2 : 1);
+}
 
 int pick_tile(int algo, int N, int forced) {
     if (!is_mfma(algo)) return 0;
@@ -344,8 +347,8 @@ int pauli_decompose_hermitian(const void* G, int N, int batch, void* out, const 
     const char* fn = "pauli_decompose_hermitian";
     pauli_opts o = resolve(opts);
     if (valid_algo(o.algo) && !is_mfma(o.algo))
-        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no Hermitian variant (split-bf16 and fp32 have)", fn,
-                    o.algo);
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no Hermitian variant (the matrix-core algorithms have)",
+                    fn, o.algo);
     const int forced = o.tile;
     o.tile = 0;   // the general tile check below does not apply; the Hermitian one does
     int st = check_common(G, N, batch, out, o, fn);
@@ -378,8 +381,7 @@ static int stage_check(int N, int batch, int mode, const pauli_opts& o, const ch
     if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
     if (batch < 1) return fail(PAULI_EINVAL, "%s: batch=%d must be >= 1", fn, batch);
     if (mode < 0 || mode > 3) return fail(PAULI_EINVAL, "%s: mode %d not in {0, 1, 2, 3}", fn, mode);
-    if (o.algo != PAULI_ALGO_SPLIT_BF16 && o.algo != PAULI_ALGO_FP32)
-        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes", fn, o.algo);
+    if (!is_mfma(o.algo)) return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes", fn, o.algo);
     if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
         return fail(PAULI_EINVAL, "%s: unknown dtype (in %d, out %d)", fn, o.in_dtype, o.out_dtype);
     const size_t need = mfma_workspace_bytes(planes_of(o.algo), N, batch);
@@ -771,11 +773,34 @@ extern "C" int pauli_batched_tile_selected(int count, const int* N, int algo) {
 // ---------------------------------------------------------------------------
 // Autotuner: time each tile id per N on scratch matrices, keep the fastest.
 // ---------------------------------------------------------------------------
+namespace {
+
+// 32-bit integer mixer (C. Wellons' "lowbias32" constants).
+__device__ inline uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Autotuner input: a fixed pseudo-random complex64 matrix, each component
+// uniform on [-1, 1) from the hash of its position.
+__global__ __launch_bounds__(256) void tune_fill_kernel(float2* __restrict__ p, size_t n) {
+    const float k = 1.0f / 2147483648.0f;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const uint32_t h = mix32((uint32_t)(2 * i)), g = mix32((uint32_t)(2 * i + 1));
+        p[i] = make_float2((float)(int32_t)h * k, (float)(int32_t)g * k);
+    }
+}
+
+}  // namespace
+
 extern "C" int pauli_autotune(int N_min, int N_max, const pauli_opts* opts) {
     const char* fn = "pauli_autotune";
     pauli_opts o = resolve(opts);
-    if (o.algo != PAULI_ALGO_SPLIT_BF16 && o.algo != PAULI_ALGO_FP32)
-        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no tile choice", fn, o.algo);
+    if (!is_mfma(o.algo)) return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no tile choice", fn, o.algo);
     if (N_min < 1 || N_max > N_MAX || N_min > N_max)
         return fail(PAULI_EINVAL, "%s: bad range [%d, %d]", fn, N_min, N_max);
     const int planes = planes_of(o.algo);
@@ -794,9 +819,11 @@ extern "C" int pauli_autotune(int N_min, int N_max, const pauli_opts* opts) {
             (void)hipFree(out);
             return hip_fail(e, fn);
         }
-        // the data values do not affect timing; zero is enough
+        // operands like real data: zero operands draw less matrix-core power,
+        // and the clock is power-limited, so a ranking taken on zeros may not hold
         hipEvent_t a = nullptr, b = nullptr;
-        e = hipMemsetAsync(in, 0, elems * 8, s);
+        hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, s, (float2*)in, elems);
+        e = hipGetLastError();
         if (e == hipSuccess) e = hipEventCreate(&a);
         if (e == hipSuccess) e = hipEventCreate(&b);
         int best = 0;

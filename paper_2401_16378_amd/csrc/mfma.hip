@@ -8,24 +8,82 @@ namespace {
 
 using namespace mfma;
 
+// pe: prescale exponent of each matrix of the batch (two-plane split only).
 template <int PLANES, int DIR, bool IN128>
-__global__ __launch_bounds__(256) void pack_kernel(const void* __restrict__ in, void* __restrict__ ws, int N) {
+__global__ __launch_bounds__(256) void pack_kernel(const void* __restrict__ in, void* __restrict__ ws, int N,
+                                                   const int* __restrict__ pe) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES, DIR>()];
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const unsigned char* src = (const unsigned char*)in + (size_t)blockIdx.y * D * D * (IN128 ? 16 : 8);
     unsigned char* wsm = (unsigned char*)ws + (size_t)blockIdx.y * Dp * Dp * Pack<PLANES>::EB;
-    pack_tile<PLANES, DIR, IN128>(src, wsm, N, blockIdx.x, lds);
+    pack_tile<PLANES, DIR, IN128>(src, wsm, N, blockIdx.x, lds, PLANES == 2 ? pe[blockIdx.y] : 0);
 }
 
 // Pack for the Hermitian contraction: the K ranges its half walk skips are not packed.
 template <int PLANES, bool IN128>
 __global__ __launch_bounds__(256) void pack_herm_kernel(const void* __restrict__ in, void* __restrict__ ws, int N,
-                                                        uint32_t hmin) {
+                                                        uint32_t hmin, const int* __restrict__ pe) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES>()];
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const unsigned char* src = (const unsigned char*)in + (size_t)blockIdx.y * D * D * (IN128 ? 16 : 8);
     unsigned char* wsm = (unsigned char*)ws + (size_t)blockIdx.y * Dp * Dp * Pack<PLANES>::EB;
-    pack_tile<PLANES, FORWARD, IN128>(src, wsm, N, herm_pack_tile(N, hmin, blockIdx.x), lds);
+    pack_tile<PLANES, FORWARD, IN128>(src, wsm, N, herm_pack_tile(N, hmin, blockIdx.x), lds,
+                                      PLANES == 2 ? pe[blockIdx.y] : 0);
+}
+
+// ---- prescale of the two-plane split ----
+// Largest |re|, |im| of each matrix (as binary32, the precision the pack
+// reads), in two launches: absmax_kernel reduces R contiguous ranges of the
+// 4^N elements of matrix blockIdx.y to R partial maxima, prescale_kernel
+// reduces those and stores the matrix's prescale exponent.  Both write every
+// value they produce, so the workspace needs no clearing.
+__device__ inline float block_max256(float m, float* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = __builtin_fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    return __builtin_fmaxf(__builtin_fmaxf(red[0], red[1]), __builtin_fmaxf(red[2], red[3]));
+}
+
+template <bool IN128>
+__global__ __launch_bounds__(256) void absmax_kernel(const void* __restrict__ in, int N, float* __restrict__ partial,
+                                                     uint32_t R) {
+    __shared__ float red[4];
+    const size_t n = (size_t)1 << (2 * N);            // elements per matrix
+    const size_t per = n / R;                          // R divides n; per is even unless N = 0
+    const size_t lo = (size_t)blockIdx.x * per;
+    float m = 0.f;
+    if constexpr (IN128) {
+        const double2* p = (const double2*)in + (size_t)blockIdx.y * n + lo;
+        for (size_t i = threadIdx.x; i < per; i += 256) {
+            const double2 v = p[i];
+            m = __builtin_fmaxf(m, __builtin_fmaxf(__builtin_fabsf((float)v.x), __builtin_fabsf((float)v.y)));
+        }
+    } else if (per % 2 == 0) {
+        const float4* p = (const float4*)((const float2*)in + (size_t)blockIdx.y * n + lo);
+        for (size_t i = threadIdx.x; i < per / 2; i += 256) {
+            const float4 v = p[i];
+            m = __builtin_fmaxf(m, __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(v.x), __builtin_fabsf(v.y)),
+                                                   __builtin_fmaxf(__builtin_fabsf(v.z), __builtin_fabsf(v.w))));
+        }
+    } else {
+        const float2* p = (const float2*)in + (size_t)blockIdx.y * n + lo;
+        for (size_t i = threadIdx.x; i < per; i += 256) {
+            const float2 v = p[i];
+            m = __builtin_fmaxf(m, __builtin_fmaxf(__builtin_fabsf(v.x), __builtin_fabsf(v.y)));
+        }
+    }
+    m = block_max256(m, red);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * R + blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void prescale_kernel(const float* __restrict__ partial, uint32_t R,
+                                                       int* __restrict__ pe) {
+    __shared__ float red[4];
+    float m = 0.f;
+    for (uint32_t i = threadIdx.x; i < R; i += 256) m = __builtin_fmaxf(m, partial[(size_t)blockIdx.x * R + i]);
+    m = block_max256(m, red);
+    if (threadIdx.x == 0) pe[blockIdx.x] = prescale_exponent(m);
 }
 
 struct Params {
@@ -34,7 +92,15 @@ struct Params {
     int N;
     int out128;
     double scale;
+    const int* pe;   // prescale exponents (two-plane split), else unused
 };
+
+// The output scale of matrix blockIdx.y: the two-plane split undoes its prescale here.
+template <int PLANES>
+__device__ inline double out_scale(const Params& prm) {
+    if constexpr (PLANES == 2) return __builtin_ldexp(prm.scale, -prm.pe[blockIdx.y]);
+    else return prm.scale;
+}
 
 template <int PLANES, int RB, int WAVES, int DIR, int PF, bool HERM = false>
 __global__ __launch_bounds__(WAVES * 64 > 256 ? WAVES * 64 : 256) void contract_kernel(Params prm) {
@@ -57,7 +123,8 @@ __global__ __launch_bounds__(WAVES * 64 > 256 ? WAVES * 64 : 256) void contract_
             xb = (xb % S) * 8 + xb / S;
         }
     }
-    contract_tile<PLANES, RB, WAVES, DIR, PF, HERM>(wsm, dst, prm.N, xb, L % nMB, prm.scale, prm.out128, lds);
+    contract_tile<PLANES, RB, WAVES, DIR, PF, HERM>(wsm, dst, prm.N, xb, L % nMB, out_scale<PLANES>(prm), prm.out128,
+                                                    lds);
 }
 
 template <int PLANES, int RB, int DIR, int AHEAD>
@@ -69,7 +136,8 @@ __global__ __launch_bounds__(256) void contract_lds_kernel(Params prm) {
     const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
     const unsigned char* wsm = (const unsigned char*)prm.ws + (size_t)blockIdx.y * Dp * Dp * Pack<PLANES>::EB;
     unsigned char* dst = (unsigned char*)prm.out + (size_t)blockIdx.y * D * D * (prm.out128 ? 16 : 8);
-    contract_tile_lds<PLANES, RB, DIR, AHEAD>(wsm, dst, prm.N, L / nMB, L % nMB, prm.scale, prm.out128, lds);
+    contract_tile_lds<PLANES, RB, DIR, AHEAD>(wsm, dst, prm.N, L / nMB, L % nMB, out_scale<PLANES>(prm),
+                                              prm.out128, lds);
 }
 
 template <int PLANES, int RB, int AHEAD, int DIR>
@@ -157,12 +225,57 @@ hipError_t launch_tile(int tile, const Params& p, int batch, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+// Reduction blocks per matrix for the prescale: a power of two dividing
+// 4^N, one per 4096 elements, at most 1024.
+uint32_t absmax_blocks(int N) {
+    const int lg = 2 * N - 12;
+    return lg <= 0 ? 1u : (lg >= 10 ? 1024u : 1u << lg);
+}
+
+size_t packed_bytes(int planes, int N, int batch) {
+    const size_t Dp = padded_dim(N);
+    const size_t eb = planes == 3 ? Pack<3>::EB : (planes == 2 ? Pack<2>::EB : Pack<1>::EB);
+    return Dp * Dp * eb * (size_t)batch;
+}
+
+size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Two-plane workspace: [packed operands | prescale exponents (int per
+// matrix) | partial maxima (absmax_blocks(N) floats per matrix)].
+int* prescale_exponents(void* ws, int N, int batch) {
+    return (int*)((unsigned char*)ws + packed_bytes(2, N, batch));
+}
+float* prescale_partials(void* ws, int N, int batch) {
+    return (float*)((unsigned char*)prescale_exponents(ws, N, batch) + round256(sizeof(int) * (size_t)batch));
+}
+
+hipError_t launch_prescale(const void* in, bool in128, void* ws, int N, int batch, hipStream_t s) {
+    const uint32_t R = absmax_blocks(N);
+    float* partial = prescale_partials(ws, N, batch);
+    if (in128) hipLaunchKernelGGL((absmax_kernel<true>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+    else hipLaunchKernelGGL((absmax_kernel<false>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+    hipLaunchKernelGGL(prescale_kernel, dim3(batch), dim3(256), 0, s, (const float*)partial, R,
+                       prescale_exponents(ws, N, batch));
+    return hipGetLastError();
+}
+
 template <int PLANES, int DIR>
 hipError_t launch_pack(const void* in, bool in128, void* ws, int N, int batch, hipStream_t s) {
+    const int* pe = nullptr;
+    if constexpr (PLANES == 2) {
+        const hipError_t e = launch_prescale(in, in128, ws, N, batch, s);
+        if (e != hipSuccess) return e;
+        pe = prescale_exponents(ws, N, batch);
+    }
     const dim3 grid(pack_tiles(N), batch);
-    if (in128) hipLaunchKernelGGL((pack_kernel<PLANES, DIR, true>), grid, dim3(256), 0, s, in, ws, N);
-    else hipLaunchKernelGGL((pack_kernel<PLANES, DIR, false>), grid, dim3(256), 0, s, in, ws, N);
+    if (in128) hipLaunchKernelGGL((pack_kernel<PLANES, DIR, true>), grid, dim3(256), 0, s, in, ws, N, pe);
+    else hipLaunchKernelGGL((pack_kernel<PLANES, DIR, false>), grid, dim3(256), 0, s, in, ws, N, pe);
     return hipGetLastError();
+}
+
+Params make_params(int planes, const void* ws, void* out, bool out_c128, int N, int batch, double scale) {
+    return Params{ws, out, N, out_c128 ? 1 : 0, scale,
+                  planes == 2 ? prescale_exponents(const_cast<void*>(ws), N, batch) : nullptr};
 }
 
 }  // namespace
@@ -195,8 +308,10 @@ int mfma_default_tile_hermitian(int planes, int N) {
 }
 
 size_t mfma_workspace_bytes(int planes, int N, int batch) {
-    const size_t Dp = padded_dim(N);
-    return Dp * Dp * (size_t)(planes == 3 ? Pack<3>::EB : Pack<1>::EB) * (size_t)batch;
+    size_t b = packed_bytes(planes, N, batch);
+    if (planes == 2)
+        b += round256(sizeof(int) * (size_t)batch) + sizeof(float) * (size_t)absmax_blocks(N) * (size_t)batch;
+    return b;
 }
 
 hipError_t launch_mfma_pack(Dir dir, int planes, const void* in, bool in_c128, int N, int batch, void* ws,
@@ -204,6 +319,9 @@ hipError_t launch_mfma_pack(Dir dir, int planes, const void* in, bool in_c128, i
     if (planes == 3)
         return dir == FORWARD ? launch_pack<3, FORWARD>(in, in_c128, ws, N, batch, stream)
                               : launch_pack<3, ADJOINT>(in, in_c128, ws, N, batch, stream);
+    if (planes == 2)
+        return dir == FORWARD ? launch_pack<2, FORWARD>(in, in_c128, ws, N, batch, stream)
+                              : launch_pack<2, ADJOINT>(in, in_c128, ws, N, batch, stream);
     return dir == FORWARD ? launch_pack<1, FORWARD>(in, in_c128, ws, N, batch, stream)
                           : launch_pack<1, ADJOINT>(in, in_c128, ws, N, batch, stream);
 }
@@ -212,10 +330,13 @@ hipError_t launch_mfma_contract(Dir dir, int planes, const void* ws, void* out, 
                                 double scale, int tile, hipStream_t stream) {
     if (tile == 0) tile = mfma_default_tile(planes, N);
     if (!mfma_tile_valid(planes, tile, N)) return hipErrorInvalidValue;
-    Params p{ws, out, N, out_c128 ? 1 : 0, scale};
+    const Params p = make_params(planes, ws, out, out_c128, N, batch, scale);
     if (planes == 3)
         return dir == FORWARD ? launch_tile<3, FORWARD>(tile, p, batch, stream)
                               : launch_tile<3, ADJOINT>(tile, p, batch, stream);
+    if (planes == 2)
+        return dir == FORWARD ? launch_tile<2, FORWARD>(tile, p, batch, stream)
+                              : launch_tile<2, ADJOINT>(tile, p, batch, stream);
     return dir == FORWARD ? launch_tile<1, FORWARD>(tile, p, batch, stream)
                           : launch_tile<1, ADJOINT>(tile, p, batch, stream);
 }
@@ -234,9 +355,10 @@ hipError_t launch_mfma_contract_hermitian(int planes, const void* ws, void* out,
                                           double scale, int tile, hipStream_t stream) {
     if (tile == 0) tile = mfma_default_tile_hermitian(planes, N);
     if (!mfma_tile_valid_hermitian(planes, tile, N)) return hipErrorInvalidValue;
-    Params p{ws, out, N, out_c128 ? 1 : 0, scale};
-    return planes == 3 ? launch_tile<3, FORWARD, true>(tile, p, batch, stream)
-                       : launch_tile<1, FORWARD, true>(tile, p, batch, stream);
+    const Params p = make_params(planes, ws, out, out_c128, N, batch, scale);
+    if (planes == 3) return launch_tile<3, FORWARD, true>(tile, p, batch, stream);
+    if (planes == 2) return launch_tile<2, FORWARD, true>(tile, p, batch, stream);
+    return launch_tile<1, FORWARD, true>(tile, p, batch, stream);
 }
 
 // The pack skips only what no Hermitian tile reads: from the largest
@@ -258,12 +380,19 @@ hipError_t launch_mfma_pack_hermitian(int planes, const void* in, bool in_c128, 
     const uint32_t hmin = herm_pack_min(planes);
     if (hmin < 128u || (hmin & (hmin - 1u))) return hipErrorInvalidValue;   // the grid mapping needs both
     const dim3 grid(herm_pack_tiles(N, hmin), batch);
+    const int* pe = nullptr;
     if (planes == 3) {
-        if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<3, true>), grid, dim3(256), 0, stream, in, ws, N, hmin);
-        else hipLaunchKernelGGL((pack_herm_kernel<3, false>), grid, dim3(256), 0, stream, in, ws, N, hmin);
+        if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<3, true>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
+        else hipLaunchKernelGGL((pack_herm_kernel<3, false>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
+    } else if (planes == 2) {
+        const hipError_t e = launch_prescale(in, in_c128, ws, N, batch, stream);
+        if (e != hipSuccess) return e;
+        pe = prescale_exponents(ws, N, batch);
+        if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<2, true>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
+        else hipLaunchKernelGGL((pack_herm_kernel<2, false>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
     } else {
-        if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<1, true>), grid, dim3(256), 0, stream, in, ws, N, hmin);
-        else hipLaunchKernelGGL((pack_herm_kernel<1, false>), grid, dim3(256), 0, stream, in, ws, N, hmin);
+        if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<1, true>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
+        else hipLaunchKernelGGL((pack_herm_kernel<1, false>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
     }
     return hipGetLastError();
 }

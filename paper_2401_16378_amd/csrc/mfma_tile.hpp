@@ -43,6 +43,12 @@
 // the 4x4 micro-block, see split3); bf16 MFMA accumulates hi into one FP32
 // accumulator, where the sums stay exact, and mid + lo into a second, and the
 // two are added in binary64 in the epilogue before the phase and scale.
+// PLANES = 2: the matrix is first multiplied by a power of two 2^pe that
+// brings its largest component just below 2^15 (a reduction pass finds it),
+// then each component is split as g ~ hi + 2^-11 lo (two fp16 numbers, hi
+// with 11 significant bits on the micro-block grid, see split2); fp16 MFMA
+// accumulates each plane into its own FP32 accumulator and the epilogue
+// forms hi + 2^-11 lo in binary64 and undoes 2^pe with the scale.
 // PLANES = 1: binary32 MFMA on the binary32 components.
 #include <type_traits>
 
@@ -54,6 +60,8 @@ namespace mfma {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -69,6 +77,26 @@ __device__ inline uint32_t pack_bf16(float a, float b) {
 }
 __device__ inline float lo_half(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
 __device__ inline float hi_half(uint32_t u) { return __builtin_bit_cast(float, u & 0xFFFF0000u); }
+__device__ inline uint32_t pack_f16(float a, float b) {
+    f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+}
+
+// Bits of +1 in the 16-bit operand format of the split (bf16 for three
+// planes, fp16 for two); setting bit 15 negates.
+template <int PLANES>
+constexpr uint32_t ONE16 = PLANES == 2 ? 0x3C00u : 0x3F80u;
+
+// One 32x32x16 MFMA step of a 16-bit plane, operands given as raw bits.
+template <int PLANES>
+__device__ inline f32x16 mfma16(const u32x4& a, const u32x4& b, const f32x16& c) {
+    if constexpr (PLANES == 2)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
+}
 
 // Three-way bf16 split of two binary32 values a, b against a power-of-two
 // grid u (with inv_u = 1/u, both exact):
@@ -100,6 +128,38 @@ __device__ inline void block_grid(float maxabs, float& u, float& inv_u) {
     inv_u = __builtin_bit_cast(float, (uint32_t)(127 - e + 8) << 23);
 }
 
+// Two-way fp16 split of two prescaled binary32 values a, b against the
+// micro-block grid u (|x| < 2^11 u, 2^-24 <= u <= 2^4, inv_u = 1/u):
+//   hi = u * rint(x / u)          an integer of at most 11 bits times u, so
+//                                 exact in fp16 (|hi| <= 2^15)
+//   lo = fp16(2^11 (x - hi))      x - hi is exact in binary32, |x - hi| <= u/2
+// hi + 2^-11 lo equals x to within 2^-12 |x - hi| <= 2^-13 u, i.e. about
+// 2^-24 of the block's largest component.  As for split3, every hi term is a
+// multiple of its block's grid, so the FP32 sums of hi terms are exact while
+// they stay below 2^24 times the smallest grid.
+__device__ inline void split2(float a, float b, float u, float inv_u, uint32_t& h, uint32_t& l) {
+    const float ha = __builtin_rintf(a * inv_u) * u, hb = __builtin_rintf(b * inv_u) * u;
+    h = pack_f16(ha, hb);
+    l = pack_f16((a - ha) * 2048.f, (b - hb) * 2048.f);
+}
+
+// Grid of a micro-block for split2: u = 2^(e-11) for the exponent e with
+// max|x| < 2^e, at least 2^-24 (the smallest fp16 step).
+__device__ inline void block_grid16(float maxabs, float& u, float& inv_u) {
+    int e = (int)((__builtin_bit_cast(uint32_t, maxabs) >> 23) & 0xFFu) - 126;
+    e = e < -13 ? -13 : e;
+    u = __builtin_bit_cast(float, (uint32_t)(127 + e - 11) << 23);
+    inv_u = __builtin_bit_cast(float, (uint32_t)(127 - e + 11) << 23);
+}
+
+// Prescale exponent of the two-plane split for a matrix whose largest
+// component (in absolute value, as binary32) is maxabs: pe = 15 - e with
+// maxabs < 2^e, so that 2^pe maxabs < 2^15.
+__host__ __device__ inline int prescale_exponent(float maxabs) {
+    const int e = (int)((__builtin_bit_cast(uint32_t, maxabs) >> 23) & 0xFFu) - 126;
+    return 15 - e;
+}
+
 template <bool IN128>
 __device__ inline f32x2 load_elem(const unsigned char* base, size_t idx) {
     if constexpr (IN128) {
@@ -113,20 +173,26 @@ __device__ inline f32x2 load_elem(const unsigned char* base, size_t idx) {
 
 // ---------------------------------------------------------------------------
 // Packed operand layout, per matrix, with Dp = max(2^N, 32):
-//   bf16: fragment (xb, s, pl, cb) at ((xb * Dp/16 + s) * 6 + pl * 2 + cb) KiB,
+//   16-bit planes (P = 3 bf16 or P = 2 fp16): fragment (xb, s, pl, cb) at
+//         ((xb * Dp/16 + s) * 2P + pl * 2 + cb) KiB,
 //         lane l = x_l + 32h holds K = 16s + 8h + j, j < 8, of column x_l;
 //   fp32: fragment (xb, s, cb) at ((xb * Dp/8 + s) * 2 + cb) KiB,
 //         lane l holds K = 8s + 4h + t, t < 4.
-// pl = hi/mid/lo plane, cb = 0 real parts, 1 imaginary parts.
+// pl = hi/mid/lo (or hi/lo) plane, cb = 0 real parts, 1 imaginary parts.
 // ---------------------------------------------------------------------------
 template <int PLANES>
 struct Pack {
-    static constexpr int SK = PLANES == 3 ? 16 : 8;        // K per slice
-    static constexpr int NPL = PLANES == 3 ? 6 : 2;        // fragments per slice
-    static constexpr int ESZ = PLANES == 3 ? 2 : 4;        // bytes per element
+    static_assert(PLANES >= 1 && PLANES <= 3, "one, two or three planes");
+    static constexpr int SK = PLANES == 1 ? 8 : 16;        // K per slice
+    static constexpr int LOG_SK = PLANES == 1 ? 3 : 4;
+    static constexpr int NPL = 2 * PLANES;                 // fragments per slice
+    static constexpr int ESZ = PLANES == 1 ? 4 : 2;        // bytes per element
     static constexpr int SLICE_BYTES = NPL * FRAG;
     static constexpr int EB = NPL * ESZ;                   // packed bytes per matrix element
+    static constexpr int ACC = PLANES == 1 ? 1 : 2;        // FP32 accumulators per output
 };
+
+constexpr int slice_k(int planes) { return planes == 1 ? 8 : 16; }
 
 __host__ __device__ inline uint32_t padded_dim(int N) { return N < 5 ? 32u : (1u << N); }
 
@@ -185,9 +251,10 @@ __device__ inline uint32_t herm_pack_tile(int N, uint32_t hmin, uint32_t t) {
 // Pack tile t (of pack_tiles(N)) of one matrix: 32 flip masks x KT values of
 // q.  256 threads; src = the matrix (or coefficient vector), ws = its packed
 // operand; lds holds pack_lds_bytes<PLANES, DIR>() bytes.
+// pe: the prescale exponent of the two-plane split (unused otherwise).
 template <int PLANES, int DIR, bool IN128>
 __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned char* __restrict__ ws,
-                                 int N, uint32_t t, unsigned char* lds) {
+                                 int N, uint32_t t, unsigned char* lds, int pe = 0) {
     using P = Pack<PLANES>;
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
@@ -272,12 +339,18 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
             kh = 32 * g + zl;
         }
         float gu = 1.f, ginv = 1.f;
-        if constexpr (PLANES == 3) {
+        if constexpr (PLANES == 2) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                v[r] = f32x2{__builtin_ldexpf(v[r].x, pe), __builtin_ldexpf(v[r].y, pe)};
+        }
+        if constexpr (PLANES >= 2) {
             float mx = 0.f;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 mx = __builtin_fmaxf(mx, __builtin_fmaxf(__builtin_fabsf(v[r].x), __builtin_fabsf(v[r].y)));
-            block_grid(mx, gu, ginv);
+            if constexpr (PLANES == 3) block_grid(mx, gu, ginv);
+            else block_grid16(mx, gu, ginv);
         }
 #pragma unroll
         for (int x2 = 0; x2 < 4; ++x2) {
@@ -305,6 +378,16 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
                 *(u32x2*)(cbase + 3 * PS) = u32x2{mi0, mi1};
                 *(u32x2*)(cbase + 4 * PS) = u32x2{lr0, lr1};
                 *(u32x2*)(cbase + 5 * PS) = u32x2{li0, li1};
+            } else if constexpr (PLANES == 2) {
+                uint32_t hr0, lr0, hr1, lr1, hi0, li0, hi1, li1;
+                split2(e[0].x, e[1].x, gu, ginv, hr0, lr0);
+                split2(e[2].x, e[3].x, gu, ginv, hr1, lr1);
+                split2(e[0].y, e[1].y, gu, ginv, hi0, li0);
+                split2(e[2].y, e[3].y, gu, ginv, hi1, li1);
+                *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
+                *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
+                *(u32x2*)(cbase + 2 * PS) = u32x2{lr0, lr1};
+                *(u32x2*)(cbase + 3 * PS) = u32x2{li0, li1};
             } else {
                 *(f32x4*)(cbase) = f32x4{e[0].x, e[1].x, e[2].x, e[3].x};
                 *(f32x4*)(cbase + PS) = f32x4{e[0].y, e[1].y, e[2].y, e[3].y};
@@ -328,14 +411,14 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
 // Slices per unrolled step of the register-ring contraction: twice the
 // larger of the sign group (32*RB K values) and the ring depth.
 constexpr int ring_step_slices(int planes, int rb, int pf) {
-    const int u = 32 * rb / (planes == 3 ? 16 : 8);
+    const int u = 32 * rb / slice_k(planes);
     return 2 * (u > pf ? u : pf);
 }
 
 // First flip mask X0 (a multiple of 32) from which the Hermitian contraction
 // of a register-ring tile walks half of K: X0 >= (step length) * (K per slice).
 constexpr uint32_t herm_half_from(int planes, int rb, int pf) {
-    return (uint32_t)ring_step_slices(planes, rb, pf) * (planes == 3 ? 16u : 8u);
+    return (uint32_t)ring_step_slices(planes, rb, pf) * (uint32_t)slice_k(planes);
 }
 
 // Binary32 plane: an MFMA accumulator chain adds at most FLUSH_SLICES slices
@@ -374,9 +457,10 @@ __device__ inline void flush_into(f32x16 (&tot)[1][RB][2], f32x16 (&acc)[1][RB][
 // imaginary when it is odd; the other component, zero in exact arithmetic,
 // is dropped before the phase, which leaves every coefficient exactly real.
 template <int PLANES, int RB, int DIR, bool HERM = false>
-__device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&acc)[PLANES == 3 ? 2 : 1][RB][2], unsigned char* __restrict__ dst,
+__device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&acc)[Pack<PLANES>::ACC][RB][2], unsigned char* __restrict__ dst,
                                   int N, uint32_t X0, uint32_t Pw, double scale, int out128, unsigned char* lds) {
-    constexpr int ACC = PLANES == 3 ? 2 : 1;
+    constexpr int ACC = Pack<PLANES>::ACC;
+    constexpr double LOW = PLANES == 2 ? 1.0 / 2048.0 : 1.0;   // weight of the second accumulator
     const uint32_t D = 1u << N;
     // The thread index passes through an empty asm statement, so that the
     // staging addresses derived from it are formed here, at each call, and
@@ -398,8 +482,8 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&
             double re = (double)acc[0][rb][0][r];
             double im = (double)acc[0][rb][1][r];
             if constexpr (ACC == 2) {
-                re += (double)acc[ACC - 1][rb][0][r];
-                im += (double)acc[ACC - 1][rb][1][r];
+                re += LOW * (double)acc[ACC - 1][rb][0][r];
+                im += LOW * (double)acc[ACC - 1][rb][1][r];
             }
             re *= scale;
             im *= scale;
@@ -474,7 +558,7 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
                                      int N, uint32_t xb, uint32_t mb, double scale, int out128,
                                      unsigned char* lds) {
     using P = Pack<PLANES>;
-    constexpr int ACC = PLANES == 3 ? 2 : 1;
+    constexpr int ACC = P::ACC;
     constexpr int MT = WAVES * RB * 32;                    // rows per workgroup
     constexpr int U = 32 * RB / P::SK;                     // slices per sign group (32*RB K)
     constexpr int GS = ring_step_slices(PLANES, RB, PF);   // slices per unrolled step
@@ -492,7 +576,7 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
     if constexpr (HERM) {
         if (X0 >= herm_half_from(PLANES, RB, PF)) {
             half = true;
-            beta = (uint32_t)(31 - __builtin_clz(X0)) - (PLANES == 3 ? 4u : 3u);
+            beta = (uint32_t)(31 - __builtin_clz(X0)) - (uint32_t)P::LOG_SK;
             nK = nS >> 1;
         }
     }
@@ -512,19 +596,19 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
     const unsigned char* wsx = wsm + (size_t)xb * nS * P::SLICE_BYTES + lane * 16;
 
     // ---- sign fragments of the 32x32 Sylvester block ----
-    // bf16: lane (row p_l = l32, half h) holds K slots q_l = 16e + 8h + j, j < 8,
+    // 16-bit: lane (row p_l = l32, half h) holds K slots q_l = 16e + 8h + j, j < 8,
     //       for the two 16-wide slices e of a 32-wide block.
     // fp32: lane holds q_l = 8e + 4h + t for slice e < 4, step t < 4.
-    uint32_t fA[2][4];   // bf16 pairs, [e][j/2]
+    uint32_t fA[2][4];   // 16-bit pairs, [e][j/2]
     float fF[4][4];      // fp32, [e][t]
-    if constexpr (PLANES == 3) {
+    if constexpr (PLANES >= 2) {
 #pragma unroll
         for (int e = 0; e < 2; ++e)
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const uint32_t q0 = 16 * e + 8 * h + 2 * jj;
-                const uint32_t s0 = (__popc(l32 & q0) & 1) ? 0xBF80u : 0x3F80u;
-                const uint32_t s1 = (__popc(l32 & (q0 + 1)) & 1) ? 0xBF80u : 0x3F80u;
+                const uint32_t s0 = ONE16<PLANES> | ((__popc(l32 & q0) & 1) ? 0x8000u : 0u);
+                const uint32_t s1 = ONE16<PLANES> | ((__popc(l32 & (q0 + 1)) & 1) ? 0x8000u : 0u);
                 fA[e][jj] = s0 | (s1 << 16);
             }
     } else {
@@ -564,7 +648,7 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
 #pragma unroll
     for (int k = 0; k < PF; ++k) fetch(k, slice_of((uint32_t)k < nK ? k : nK - 1));
 
-    bf16x8 Ap[2], An[2];
+    u32x4 Ap[2], An[2];
     float ts = 1.f;
     for (uint32_t s0 = 0; s0 < nK; s0 += GSX) {
         const uint32_t sr = slice_of(s0);   // the step's GSX slices are sr, sr+1, ...
@@ -578,31 +662,30 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
             if (u == 0) {
                 // sign of this wave's rows against this group of 32*RB K values
                 const bool neg_grp = __popc((Pw >> 5) & (((sr + uu) * P::SK) >> 5)) & 1;
-                if constexpr (PLANES == 3) {
+                if constexpr (PLANES >= 2) {
                     const uint32_t tm = neg_grp ? 0x80008000u : 0u;
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         const u32x4 p = {fA[e][0] ^ tm, fA[e][1] ^ tm, fA[e][2] ^ tm, fA[e][3] ^ tm};
-                        Ap[e] = __builtin_bit_cast(bf16x8, p);
-                        An[e] = __builtin_bit_cast(bf16x8, p ^ 0x80008000u);
+                        Ap[e] = p;
+                        An[e] = p ^ 0x80008000u;
                     }
                 } else {
                     ts = neg_grp ? -1.f : 1.f;
                 }
             }
-            if constexpr (PLANES == 3) {
+            if constexpr (PLANES >= 2) {
                 // plane-outer order: consecutive MFMAs never share an accumulator
 #pragma unroll
-                for (int pl = 0; pl < 3; ++pl)
+                for (int pl = 0; pl < PLANES; ++pl)
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
                         const bool neg = popc_const((uint32_t)rb & (uint32_t)(u >> 1)) & 1;
-                        const bf16x8 A = neg ? An[u & 1] : Ap[u & 1];
+                        const u32x4 A = neg ? An[u & 1] : Ap[u & 1];
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
-                            acc[pl == 0 ? 0 : ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                A, __builtin_bit_cast(bf16x8, ring[slot][pl * 2 + cb]),
-                                acc[pl == 0 ? 0 : ACC - 1][rb][cb], 0, 0, 0);
+                            acc[pl == 0 ? 0 : ACC - 1][rb][cb] =
+                                mfma16<PLANES>(A, ring[slot][pl * 2 + cb], acc[pl == 0 ? 0 : ACC - 1][rb][cb]);
                     }
             } else {
                 const f32x4 Bv[2] = {__builtin_bit_cast(f32x4, ring[slot][0]),
@@ -641,7 +724,7 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
         }
     }
     };
-    constexpr int GSL = (PLANES == 3 && RB == 4 && DIR == FORWARD) ? 4 * GS : GS;
+    constexpr int GSL = (PLANES >= 2 && RB == 4 && DIR == FORWARD && !(PLANES == 2 && HERM)) ? 4 * GS : GS;
     // a half walk nests steps of GS slices (2^beta >= GS); the long step needs 2^beta >= GSL
     const bool long_ok = !half || (1u << beta) >= (uint32_t)GSL;
     if (active && nK % GSL == 0 && long_ok) {
@@ -662,16 +745,16 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const bool neg = __popc(((Pw >> 5) + rb) & qblk) & 1;
-                if constexpr (PLANES == 3) {
+                if constexpr (PLANES >= 2) {
                     const uint32_t m = neg ? 0x80008000u : 0u;
                     const int e = s & 1;
-                    const bf16x8 A = __builtin_bit_cast(bf16x8, u32x4{fA[e][0] ^ m, fA[e][1] ^ m, fA[e][2] ^ m, fA[e][3] ^ m});
+                    const u32x4 A = u32x4{fA[e][0] ^ m, fA[e][1] ^ m, fA[e][2] ^ m, fA[e][3] ^ m};
 #pragma unroll
-                    for (int pl = 0; pl < 3; ++pl)
+                    for (int pl = 0; pl < PLANES; ++pl)
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
-                            acc[pl == 0 ? 0 : ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                A, __builtin_bit_cast(bf16x8, B[pl * 2 + cb]), acc[pl == 0 ? 0 : ACC - 1][rb][cb], 0, 0, 0);
+                            acc[pl == 0 ? 0 : ACC - 1][rb][cb] =
+                                mfma16<PLANES>(A, B[pl * 2 + cb], acc[pl == 0 ? 0 : ACC - 1][rb][cb]);
                 } else {
                     const f32x4 B0 = __builtin_bit_cast(f32x4, B[0]), B1 = __builtin_bit_cast(f32x4, B[1]);
 #pragma unroll
@@ -721,7 +804,7 @@ __device__ __attribute__((always_inline)) inline void contract_tile_lds(const un
                                          unsigned char* lds) {
     using P = Pack<PLANES>;
     constexpr int WAVES = 4;
-    constexpr int ACC = PLANES == 3 ? 2 : 1;
+    constexpr int ACC = P::ACC;
     constexpr int MT = WAVES * RB * 32;
     constexpr int PAIR_FR = 2 * P::NPL;                    // fragments per slice pair
     constexpr int LPW = PAIR_FR / WAVES;                   // copies per wave per pair
@@ -742,14 +825,14 @@ __device__ __attribute__((always_inline)) inline void contract_tile_lds(const un
 
     uint32_t fA[2][4];
     float fF[4][4];
-    if constexpr (PLANES == 3) {
+    if constexpr (PLANES >= 2) {
 #pragma unroll
         for (int e = 0; e < 2; ++e)
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const uint32_t q0 = 16 * e + 8 * h + 2 * jj;
-                const uint32_t s0 = (__popc(l32 & q0) & 1) ? 0xBF80u : 0x3F80u;
-                const uint32_t s1 = (__popc(l32 & (q0 + 1)) & 1) ? 0xBF80u : 0x3F80u;
+                const uint32_t s0 = ONE16<PLANES> | ((__popc(l32 & q0) & 1) ? 0x8000u : 0u);
+                const uint32_t s1 = ONE16<PLANES> | ((__popc(l32 & (q0 + 1)) & 1) ? 0x8000u : 0u);
                 fA[e][jj] = s0 | (s1 << 16);
             }
     } else {
@@ -789,21 +872,20 @@ __device__ __attribute__((always_inline)) inline void contract_tile_lds(const un
 #pragma unroll
             for (int f = 0; f < P::NPL; ++f) Bb[buf][k][f] = *(const u32x4*)(base + (k * P::NPL + f) * FRAG);
     };
-    bf16x8 Ap[2], An[2];
+    u32x4 Ap[2], An[2];
     float ts = 1.f;
     auto slice_mfma = [&](int buf, int k, int u) {
-        if constexpr (PLANES == 3) {
+        if constexpr (PLANES >= 2) {
 #pragma unroll
-            for (int pl = 0; pl < 3; ++pl)
+            for (int pl = 0; pl < PLANES; ++pl)
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
                     const bool neg = popc_const((uint32_t)rb & (uint32_t)(u >> 1)) & 1;
-                    const bf16x8 A = neg ? An[u & 1] : Ap[u & 1];
+                    const u32x4 A = neg ? An[u & 1] : Ap[u & 1];
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb)
-                        acc[pl == 0 ? 0 : ACC - 1][rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            A, __builtin_bit_cast(bf16x8, Bb[buf][k][pl * 2 + cb]), acc[pl == 0 ? 0 : ACC - 1][rb][cb],
-                            0, 0, 0);
+                        acc[pl == 0 ? 0 : ACC - 1][rb][cb] =
+                            mfma16<PLANES>(A, Bb[buf][k][pl * 2 + cb], acc[pl == 0 ? 0 : ACC - 1][rb][cb]);
                 }
         } else {
             const f32x4 B0 = __builtin_bit_cast(f32x4, Bb[buf][k][0]), B1 = __builtin_bit_cast(f32x4, Bb[buf][k][1]);
@@ -829,13 +911,13 @@ __device__ __attribute__((always_inline)) inline void contract_tile_lds(const un
     static_assert(GP % 2 == 0 || GP == 1, "ping-pong over the pairs of a sign group");
     for (uint32_t p0 = 0; p0 < nP; p0 += GP) {
         const bool neg_grp = __popc((Pw >> 5) & ((2 * p0 * P::SK) >> 5)) & 1;
-        if constexpr (PLANES == 3) {
+        if constexpr (PLANES >= 2) {
             const uint32_t tm = neg_grp ? 0x80008000u : 0u;
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const u32x4 q = {fA[e][0] ^ tm, fA[e][1] ^ tm, fA[e][2] ^ tm, fA[e][3] ^ tm};
-                Ap[e] = __builtin_bit_cast(bf16x8, q);
-                An[e] = __builtin_bit_cast(bf16x8, q ^ 0x80008000u);
+                Ap[e] = q;
+                An[e] = q ^ 0x80008000u;
             }
         } else {
             ts = neg_grp ? -1.f : 1.f;

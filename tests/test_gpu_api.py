@@ -24,7 +24,7 @@ def stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_two_pass_equals_one_call(algo, mode):
     p = lib()
@@ -64,7 +64,7 @@ def test_library_pool_vs_caller_workspace_and_determinism():
         assert torch.equal(outs[0], o)
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray"])
 def test_complex128_in_and_out(algo):
     p = lib()
     N = 8
@@ -72,11 +72,11 @@ def test_complex128_in_and_out(algo):
     c = p.decompose(torch.from_numpy(G).cuda(), algo=algo).cpu().numpy()
     assert c.dtype == np.complex128
     ref = oracle.decompose(G, threads=8)
-    tol = {"split_bf16": 1e-6, "fp32": 1e-5, "fp64_gray": 1e-12}[algo]
+    tol = {"split_bf16": 1e-6, "split_fp16": 1e-6, "fp32": 1e-5, "fp64_gray": 1e-12}[algo]
     assert np.abs(c - ref).max() / np.abs(ref).max() <= tol
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray"])
 def test_nonfinite_input_propagates(algo):
     """A NaN on one XOR diagonal reaches exactly the coefficients of that flip
     mask; every other coefficient stays finite."""

@@ -20,7 +20,7 @@ from tests import backward_workload as bw
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"split_bf16": 1e-5, "fp32": 1e-5, "fp64_gray": 1e-10, "fwht": 1e-10}
+TOL = {"split_bf16": 1e-5, "split_fp16": 1e-5, "fp32": 1e-5, "fp64_gray": 1e-10, "fwht": 1e-10}
 
 
 @pytest.fixture(scope="module")
@@ -51,7 +51,7 @@ def gpu_gradient(problem, algo):
     return g.to(torch.complex128).cpu().numpy()
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray", "fwht"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray", "fwht"])
 def test_adjoint_gradient_vs_oracle(problem, algo):
     ref = oracle_gradient(problem)
     got = gpu_gradient(problem, algo)
@@ -59,7 +59,7 @@ def test_adjoint_gradient_vs_oracle(problem, algo):
     assert err <= TOL[algo], err
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray", "fwht"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray", "fwht"])
 def test_adjoint_gradient_vs_finite_differences(problem, finite_differences, algo):
     """The GPU gradient (hand-written adjoint through torch.autograd) against
     the central differences directly, all 64 entries.  The differences carry

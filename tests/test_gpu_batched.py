@@ -219,3 +219,29 @@ def test_autotune_batched_writes_tune_cache(tmp_path):
     tuned = int([l for l in r.stdout.splitlines() if l.startswith("tuned")][0].split()[1])
     lines = cache.read_text().splitlines()
     assert "B 3 %d 0 0 1 1 2 2 0 0 0 0 0 0" % tuned in lines, lines
+
+
+@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+def test_large_members(algo):
+    """Members up to the batched limit N = 12 next to small ones: every
+    member equals its single-matrix decomposition bit for bit, for every
+    tile shape, and a seeded sample of each large member matches the
+    oracle."""
+    p = lib()
+    Ns = [12, 3, 10, 11, 5, 12, 9]
+    mats = [workloads.iid_complex(n, 8400 + k, np.complex64) for k, n in enumerate(Ns)]
+    dev = [torch.from_numpy(m).cuda() for m in mats]
+    singles = [p.decompose(d, algo=algo) for d in dev]
+    nb = p.load_library().pauli_batched_tile_count()
+    for tile in range(1, nb + 1):
+        outs = p.decompose_batched(dev, algo=algo, tile=tile)
+        for k in range(len(Ns)):
+            assert torch.equal(outs[k], singles[k]), (tile, k, Ns[k])
+    tol = 1e-6 if algo == "split_bf16" else 1e-5
+    for k, (n, G) in enumerate(zip(Ns, mats)):
+        if n < 10:
+            continue
+        ns = workloads.sample_indices(4 ** n, 4096, seed=8500 + k)
+        ref = oracle.coeffs_at(G.astype(np.complex128), ns, threads=threads())
+        got = singles[k].cpu().numpy()[ns.astype(np.int64)].astype(np.complex128)
+        assert np.abs(got - ref).max() / np.abs(ref).max() <= tol, (k, n)

@@ -16,7 +16,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64_gray": 1e-12, "fp32": 1e-5, "split_bf16": 1e-6}
+TOL = {"fp64_gray": 1e-12, "fp32": 1e-5, "split_bf16": 1e-6, "split_fp16": 1e-6}
 
 
 def lib():
@@ -69,13 +69,14 @@ def test_precision_configs(N):
     G = workloads.hermitian(N, seed)
     Gd = torch.from_numpy(G).to("cuda")
     outs = {}
-    for algo in ("split_bf16", "fp32"):
+    for algo in ("split_bf16", "split_fp16", "fp32"):
         outs[algo] = p.decompose(Gd, algo=algo).cpu().numpy()
     c64d = p.decompose(Gd, algo="fp64_gray", out_dtype=torch.complex128)
     outs["fp64_gray"] = c64d.cpu().numpy()
     check_parseval(Gd, c64d, 1e-10)
     del c64d
     check_parseval(Gd, torch.from_numpy(outs["split_bf16"]).to("cuda"), 1e-6)
+    check_parseval(Gd, torch.from_numpy(outs["split_fp16"]).to("cuda"), 1e-6)
     del Gd
     torch.cuda.empty_cache()
     if N == 12:
@@ -96,12 +97,13 @@ def test_precision_configs(N):
     # all coefficients against the binary64 kernel
     c64 = outs["fp64_gray"]
     m64 = np.abs(c64).max()
-    for algo in ("split_bf16", "fp32"):
+    for algo in ("split_bf16", "split_fp16", "fp32"):
         err = np.abs(outs[algo].astype(np.complex128) - c64).max() / m64
         assert err <= TOL[algo], (algo, err)
     # Hermitian => real coefficients
     assert np.abs(c64.imag).max() <= 1e-12 * m64
     assert np.abs(outs["split_bf16"].imag).max() <= 1e-6 * m64
+    assert np.abs(outs["split_fp16"].imag).max() <= 1e-6 * m64
 
 
 def test_n6_config():
@@ -118,14 +120,15 @@ def test_n6_config():
             assert np.array_equal(c, ref)
 
 
-def test_kronecker_full_size_n14():
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16"])
+def test_kronecker_full_size_n14(algo):
     """G = A (x) B at N=14 (A: N=7, B: N=7): c(G)[nA*4^7 + nB] = c(A)[nA] c(B)[nB]
-    checked over all 2.7e8 coefficients of the split-bf16 output."""
+    checked over all 2.7e8 coefficients of the output."""
     p = lib()
     A = workloads.iid_complex(7, 77, np.complex64)
     B = workloads.iid_complex(7, 78, np.complex64)
     G = torch.kron(torch.from_numpy(A).to("cuda"), torch.from_numpy(B).to("cuda"))
-    c = p.decompose(G, algo="split_bf16")
+    c = p.decompose(G, algo=algo)
     cA = torch.from_numpy(oracle.decompose(A)).to("cuda")
     cB = torch.from_numpy(oracle.decompose(B)).to("cuda")
     ref = (cA[:, None] * cB[None, :]).reshape(-1)
@@ -133,7 +136,8 @@ def test_kronecker_full_size_n14():
     assert err <= 1e-6, err
 
 
-def test_one_hot_full_size_n14():
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16"])
+def test_one_hot_full_size_n14(algo):
     """G = P_m at N=14 for a few m: the output is exactly e_m (ordering, phase)."""
     p = lib()
     from tests import pauli_ref as pr
@@ -143,7 +147,7 @@ def test_one_hot_full_size_n14():
         A = torch.from_numpy(pr.pauli_string(m & 0x3FFF, 7).astype(np.complex64)).to("cuda")
         B = torch.from_numpy(pr.pauli_string(m >> 14, 7).astype(np.complex64)).to("cuda")
         P = torch.kron(B, A)  # qubits 7..13 from m's high digits
-        c = p.decompose(P, algo="split_bf16")
+        c = p.decompose(P, algo=algo)
         nz = torch.nonzero(c).flatten().cpu().numpy()
         assert list(nz) == [m]
         assert c[m].item() == 1

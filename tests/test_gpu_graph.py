@@ -18,7 +18,7 @@ def lib():
     return p
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32", "fp64_gray", "fwht"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray", "fwht"])
 def test_capture_and_replay(algo):
     p = lib()
     N = 10
@@ -53,7 +53,7 @@ def test_capture_and_replay(algo):
     del g
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 def test_capture_and_replay_hermitian(algo):
     """The Hermitian entry point enqueues the same two kernels (pack, then
     the Hermitian contraction): captured, it must match the eager result on

@@ -17,7 +17,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "split_bf16": 1e-6}
+TOL = {"fp32": 1e-5, "split_bf16": 1e-6, "split_fp16": 1e-6}
 
 
 def lib():
@@ -37,7 +37,7 @@ def herm_int(D, rng):
     return H.astype(np.complex64)
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 @pytest.mark.parametrize("N", list(range(0, 11)))
 def test_small_vs_oracle(algo, N):
     G = workloads.hermitian(N, 700 + N)
@@ -58,7 +58,7 @@ def ref10():
     return _REF10["G"], _REF10["c"]
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 @pytest.mark.parametrize("tile", list(range(1, 16)))
 def test_every_tile_n10(algo, tile):
     p = lib()
@@ -73,7 +73,7 @@ def test_every_tile_n10(algo, tile):
     assert np.all(c.imag == 0)
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 @pytest.mark.parametrize("N", [11, 12, 13])
 def test_vs_binary64_and_sampled_oracle(algo, N):
     """All coefficients against the binary64 fast-transform path (itself
@@ -91,7 +91,7 @@ def test_vs_binary64_and_sampled_oracle(algo, N):
     assert np.abs(c[idx] - ref).max() <= TOL[algo] * np.abs(c64).max()
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 def test_kronecker_exact_n11(algo):
     """G = A (x) B with small-integer Hermitian parts: every partial sum is an
     exact small integer, so the coefficients must equal c(A) (x) c(B)
@@ -154,7 +154,7 @@ def test_requires_grad_refused():
         p.decompose_hermitian(G)
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 def test_complex128_input(algo):
     """complex128 input is read rounded to binary32 (as for every matrix-core
     path): the same coefficients as the complex64 copy of the matrix."""
@@ -191,7 +191,7 @@ def _nan_workspace(p, algo, N, batch=1):
     return torch.full((need,), 0xFF, dtype=torch.uint8, device="cuda")   # NaN in bf16 and binary32
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 @pytest.mark.parametrize("N", [9, 10, 12])
 def test_pack_skips_only_unread_parts(algo, N):
     """The Hermitian pack leaves the K ranges that no tile's half walk reads
@@ -217,7 +217,7 @@ def test_pack_skips_only_unread_parts(algo, N):
         del ws
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 def test_split_passes_any_contraction_tile(algo):
     """pauli_pack mode 3 does not depend on the tile: a contraction with any
     register-ring tile after it equals the one-call Hermitian entry point."""

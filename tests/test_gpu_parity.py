@@ -16,7 +16,7 @@ from tests import pauli_ref as pr
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64_gray": 1e-12, "fp32": 1e-5, "split_bf16": 1e-6}
+TOL = {"fp64_gray": 1e-12, "fp32": 1e-5, "split_bf16": 1e-6, "split_fp16": 1e-6}
 ALGOS = list(TOL)
 
 
@@ -54,7 +54,7 @@ def test_gray_n10_config():
     assert np.array_equal(c, ref)
 
 
-@pytest.mark.parametrize("algo", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("algo", ["fp32", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("N", list(range(0, 10)))
 def test_mfma_small(algo, N):
     G = workloads.iid_complex(N, 600 + N, np.complex64)
@@ -63,7 +63,7 @@ def test_mfma_small(algo, N):
     assert rel_err(c, ref) <= TOL[algo]
 
 
-@pytest.mark.parametrize("algo", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("algo", ["fp32", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("tile", list(range(1, 16)))
 def test_mfma_every_tile_n9(algo, tile):
     p = lib()
@@ -79,7 +79,7 @@ def test_mfma_every_tile_n9(algo, tile):
     assert rel_err(c, ref) <= TOL[algo]
 
 
-@pytest.mark.parametrize("algo", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("algo", ["fp32", "split_bf16", "split_fp16"])
 def test_tiles_bitexact_n10(algo):
     """Every tile shape sums the K slices of an output element in the same
     order, so all of them (register-ring and LDS-staged alike) must agree bit
@@ -90,7 +90,7 @@ def test_tiles_bitexact_n10(algo):
     G = dev(workloads.iid_complex(N, 710, np.complex64))
     c = dev(workloads.iid_complex(N, 711, np.complex64).reshape(-1))
     tiles = [t for t in range(1, 16) if p.tile_valid(t, N, algo)]
-    assert len(tiles) == (15 if algo == "split_bf16" else 10)
+    assert len(tiles) == (10 if algo == "fp32" else 15)
     ref_f = p.decompose(G, algo=algo, tile=tiles[0])
     ref_a = p.reconstruct(c, algo=algo, tile=tiles[0])
     for tile in tiles[1:]:
@@ -145,7 +145,7 @@ def test_backward_vs_oracle_grad(algo, N):
     assert np.abs(got - ref).max() <= TOL[algo] * 4 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("algo", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("algo", ["fp32", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("N", [2, 5, 6, 9])
 def test_adjoint_complex128_coefficients(algo, N):
     """The matrix-core adjoint reads complex128 coefficients rounded to
