@@ -7,17 +7,21 @@
 Workload: one complex64 Hermitian 16384 x 16384 matrix (N = 14 qubits),
 G = (A + A^H)/2 with A iid complex N(0,1) (numpy PCG64, seed 1014), resident in
 HBM before timing.  One step = one full decomposition into all 4^14
-coefficients (complex64 out) with the split-bf16 MFMA path: the pack kernel
-(XOR gather, 3-way bf16 split, operand layout) then the contraction kernel
-(+-1 contraction, binary64 recombination, phase, 2^-N, store).
+coefficients (complex64 out) with a split matrix-core path, by default the
+two-plane fp16 split (--algo split_bf16: the three-plane bf16 split): the
+pack (prescale reduction, XOR gather, split, operand layout) then the
+contraction kernel (+-1 contraction, binary64 recombination, phase, 2^-N,
+store).
 
 Printed: one JSON line with coefficients/s over the whole step, the roofline
-of the contraction kernel (executed bf16 MFMA flops per launch / its mean
-launch time from HIP events on its stream, against the 2.5 PFLOP/s dense
-bf16 peak), the binary64 Gray-code GPU kernel on the same input
-for the speed ratio and the error (max |c - c_fp64| / max |c_fp64|), and the
-CPU oracle timed on a bounded sample of the same coefficients on the host's
-cores (which also checks those coefficients).
+of the contraction kernel (the method's own 4 * 8^N flops per launch / its
+mean launch time from HIP events on its stream, against the 2.5 PFLOP/s
+dense fp16/bf16 peak; the executed matrix-core flops of the split in
+separate fields), the binary64 Gray-code GPU kernel on the same input for
+the speed ratio and the error (max |c - c_fp64| / max |c_fp64|), the other
+split path timed on the same input, and the CPU oracle timed on a bounded
+sample of the same coefficients on the host's cores (which also checks
+those coefficients).
 """
 from __future__ import annotations
 
@@ -335,7 +339,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--N", type=int, default=14)
-    ap.add_argument("--algo", default="split_bf16")
+    ap.add_argument("--algo", default="split_fp16")
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other split path")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -462,6 +467,27 @@ def main():
                     "max_err_vs_fp64": err, "fp64_imag_ratio": im_ratio})
         log("[bench] fp64 gray %.1f ms, ratio %.2f, err %.3g" % (fp64_ms, fp64_ms / ms_step, err))
         del out64
+
+    if a.algo in ("split_bf16", "split_fp16") and not a.no_compare:
+        # the other split path on the same input: its time per step and error
+        other = "split_bf16" if a.algo == "split_fp16" else "split_fp16"
+        ws2 = pauli.workspace(other, N, 1, dev)
+        o2 = pauli._opts(other, 0, 0, 0, ctypes.c_void_p(stream.cuda_stream), ws2)
+        out2 = torch.empty_like(out)
+        dec = lib.pauli_decompose_hermitian if herm else lib.pauli_decompose
+
+        def step2():
+            if dec(Gd.data_ptr(), N, 1, out2.data_ptr(), ctypes.byref(o2)) != 0:
+                raise RuntimeError(pauli.last_error())
+        ms2 = timed(step2, max(3, a.steps // 2), 1, stream)
+        cmp = {"algo": other, "ms_per_step": ms2, "value": float(4 ** N) / (ms2 / 1000.0)}
+        if not a.no_fp64:
+            c2 = out2.cpu().numpy()
+            cmp["max_err_vs_fp64"] = float(np.abs(c2 - c64).max() / np.abs(c64).max())
+        res["other_split"] = cmp
+        log("[bench] %s: %.3f ms/step" % (other, ms2))
+        del out2, ws2
+        pauli.release_workspace()
 
     cpu = None
     if not a.no_cpu:
