@@ -115,6 +115,14 @@ void pauli_opts_default(pauli_opts* o);
  *     c_n = 2^-N sum_i lambda_i^(n) G[i xor m^(n)][i].
  * 0 <= N <= 16 (the coefficient index needs 2N bits, section 2); batch >= 1.
  * The MFMA algorithms read C128 input rounded to binary32.
+ * Input range: FP32 and SPLIT_BF16 accumulate unscaled binary32 partial sums
+ * of up to 2^N terms, so their results are finite for components of
+ * magnitude below 2^(127 - N); SPLIT_FP16 rescales each matrix by a power of
+ * two first and has no limit beyond finite binary32 components; FP64_GRAY
+ * and FWHT sum in binary64.  For such inputs every path scales exactly:
+ * c(2^k G) = 2^k c(G) bit for bit while all operands, split parts and
+ * partial sums stay normal numbers.  Infinite or NaN components give
+ * non-finite outputs (no error is reported).
  * opts may be NULL (defaults).
  */
 int pauli_decompose(const void* G, int N, int batch, void* out, const pauli_opts* opts);
