@@ -43,14 +43,28 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(path: str) -> str:
+    """The same source built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts), for a test run with PAULI_ORACLE_LIB=path and gcc's
+    libasan preloaded."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", "-fPIC", "-shared", "-Wall", "-Wextra",
+                           "-o", path, _SRC])
+    return path
+
+
 def _load():
     global _lib
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("PAULI_ORACLE_LIB")   # a separately built copy (sanitizer runs)
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         up = ctypes.POINTER(ctypes.c_uint64)
         u64, i64, ci = ctypes.c_uint64, ctypes.c_int64, ctypes.c_int

@@ -76,6 +76,9 @@ std::map<std::pair<int, int>, int> g_tune;
 std::map<std::pair<int, std::vector<int>>, int> g_btile;
 bool g_tune_loaded = false;
 
+// Largest batch a tune-file line may describe.
+constexpr size_t TUNE_MAX_COUNT = (size_t)1 << 20;
+
 // The file named by PAULI_TUNE_CACHE, one entry per line:
 //   "algo N tile"                      single matrices
 //   "B planes tile c_1 c_2 ... c_12"   a batch with c_n matrices of order n
@@ -97,7 +100,9 @@ void load_tune_cache_locked() {
             bool ok = true;
             for (int n = 1; n <= N_MAX_BATCHED && ok; ++n) {
                 int c = -1;
-                ok = (bool)(in >> c) && c >= 0;
+                // a count no batch can have marks a damaged line (and would
+                // otherwise make this loop allocate without bound)
+                ok = (bool)(in >> c) && c >= 0 && ns.size() + (size_t)c <= TUNE_MAX_COUNT;
                 if (ok) ns.insert(ns.end(), (size_t)c, n);
             }
             if (ok && !ns.empty()) g_btile[{planes, ns}] = tile;
