@@ -165,9 +165,11 @@ def bench_backward(a):
     wd = torch.from_numpy(w).to(dev).to(torch.float32)
     stream = torch.cuda.current_stream(dev)
 
+    algo = a.algo if a.algo in PLANES else "split_fp16"
+
     def step():
         g = Gd.detach().requires_grad_(True)
-        c = pauli.PauliDecompose.apply(g, "split_bf16")
+        c = pauli.PauliDecompose.apply(g, algo)
         # |c - t|^2 as re^2 + im^2 of a real view: no abs/sgn kernels in its gradient
         d = torch.view_as_real(c - t)
         loss = (wd * (d * d).sum(-1)).sum()
@@ -175,16 +177,17 @@ def bench_backward(a):
         return g.grad
 
     ms = timed(step, a.steps, a.warmup, stream)
-    ms_fwd = timed(lambda: pauli.decompose(Gd), a.steps, a.warmup, stream)
+    ms_fwd = timed(lambda: pauli.decompose(Gd, algo=algo), a.steps, a.warmup, stream)
     g = Gd.detach()
     gc = torch.randn(8, 4 ** 11, dtype=torch.complex64, device=dev)
-    ms_bwd = timed(lambda: pauli.decompose_backward(gc), a.steps, a.warmup, stream)
-    flops = 2 * 8 * 12 * float(8 ** 11)
+    ms_bwd = timed(lambda: pauli.decompose_backward(gc, algo=algo), a.steps, a.warmup, stream)
+    flops = 2 * 8 * 4 * PLANES[algo] * float(8 ** 11)
     line = {"metric": "forward+backward steps/sec, 8 x N=11", "value": 1e3 / ms, "unit": "steps/s",
             "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
-            "config": {"workload": "8 complex64 2048x2048 matrices, L = sum w|c-t|^2 (complex64 / binary32), split_bf16 forward "
-                                   "and adjoint backward through torch.autograd", "batch": 8, "N": 11},
+            "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[algo], "data": "synthetic",
+            "config": {"workload": "8 complex64 2048x2048 matrices, L = sum w|c-t|^2 (complex64 / binary32), %s forward "
+                                   "and adjoint backward through torch.autograd" % algo, "batch": 8, "N": 11,
+                       "algo": algo},
             "forward_ms": ms_fwd, "backward_kernel_ms": ms_bwd,
             "executed_tflops_fwd_bwd_kernels": flops / ((ms_fwd + ms_bwd) / 1e3) / 1e12}
     print(json.dumps(line), flush=True)
@@ -293,6 +296,57 @@ def bench_fwht(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_table(a):
+    """Every single-matrix config of the workload list, every path: median
+    time of `steps` calls (HIP events around each call, input in HBM),
+    coefficients/s, the method's flops (4 * 8^N) and the executed flops as
+    fractions of the matrix-core peak, algorithmic HBM bytes (input read +
+    coefficients written) per second, and the error against the binary64
+    Gray kernel (which the tests hold bit-identical to the oracle).  One JSON
+    line per (config, path) on stdout."""
+    import torch
+    import paper_2401_16378_amd as pauli
+    import workloads
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    configs = [("N=6 complex128 iid", 6, workloads.iid_complex(6, workloads.SEED_N6)),
+               ("N=10 complex128 iid", 10, workloads.iid_complex(10, workloads.SEED_N10)),
+               ("N=12 complex64 Hermitian", 12, workloads.hermitian(12, workloads.SEED_N12)),
+               ("N=14 complex64 Hermitian", 14, workloads.hermitian(14, workloads.SEED_N14))]
+    peak = {"split_fp16": PEAK_BF16_TFLOPS, "split_bf16": PEAK_BF16_TFLOPS, "fp32": 157.3}
+    for name, N, G in configs:
+        Gd = torch.from_numpy(G).to(dev)
+        esz = 16 if Gd.dtype == torch.complex128 else 8
+        ref = pauli.decompose(Gd, algo="fp64_gray", out_dtype=torch.complex128)
+        mref = ref.abs().max().item()
+        for algo in ("split_fp16", "split_bf16", "fp32", "fwht", "fp64_gray"):
+            steps = a.steps if not (algo in ("fp64_gray", "fp32") and N == 14) else 3
+            out = pauli.decompose(Gd, algo=algo)
+            err = ((out.to(torch.complex128) - ref).abs().max().item()) / mref
+            ts = []
+            for _ in range(steps):
+                b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                b.record(stream)
+                pauli.decompose(Gd, algo=algo)
+                e.record(stream)
+                torch.cuda.synchronize()
+                ts.append(b.elapsed_time(e))
+            ms = float(np.median(ts))
+            row = {"config": name, "algo": algo, "ms_median": ms, "steps": steps,
+                   "coeffs_per_s": float(4 ** N) / (ms / 1e3),
+                   "hbm_gbs_algorithmic": 2.0 * esz * float(4 ** N) / (ms / 1e3) / 1e9,
+                   "max_err_vs_fp64_gray": err}
+            if algo in peak:
+                useful = 4.0 * float(8 ** N) / (ms / 1e3) / 1e12
+                row.update({"useful_frac": useful / peak[algo],
+                            "executed_frac": useful * PLANES[algo] / peak[algo], "peak_tflops": peak[algo]})
+            print(json.dumps(row), flush=True)
+            del out
+        del Gd, ref
+        pauli.release_workspace()
+        torch.cuda.empty_cache()
+
+
 def bench_oracle(a):
     """The CPU oracle's own timings on this host (no GPU work): full
     decompositions single-threaded at N=6 and N=10 and on all cores at N=10
@@ -333,7 +387,8 @@ def bench_oracle(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["n14", "hermitian", "batch", "backward", "strings", "fwht", "oracle"],
+    ap.add_argument("--workload", choices=["n14", "hermitian", "batch", "backward", "strings", "fwht", "oracle",
+                                           "table"],
                     default="n14")
     ap.add_argument("--strings", type=int, default=65536, help="list length of the strings workload")
     ap.add_argument("--steps", type=int, default=20)
@@ -379,6 +434,8 @@ def main():
         return bench_strings(a)
     if a.workload == "fwht":
         return bench_fwht(a)
+    if a.workload == "table":
+        return bench_table(a)
     N = a.N
     log("[bench] generating N=%d Hermitian complex64 input (seed %d)" % (N, workloads.SEED_N14))
     t0 = time.perf_counter()
