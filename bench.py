@@ -124,28 +124,30 @@ def bench_batch(a):
     G = [torch.from_numpy(m).to(dev) for m in mats]
     outs = [torch.empty(1 << (2 * n), dtype=torch.complex64, device=dev) for n in Ns]
     stream = torch.cuda.current_stream(dev)
-    tile = pauli.autotune_batched(G, outs=outs)
-    plan = pauli.BatchPlan(G, outs=outs)   # arguments marshalled once, as a serving loop would
+    algo = a.algo if a.algo in PLANES else "split_fp16"
+    tile = pauli.autotune_batched(G, algo=algo, outs=outs)
+    plan = pauli.BatchPlan(G, algo=algo, outs=outs)   # arguments marshalled once, as a serving loop would
     ms = timed(plan.run, a.steps, a.warmup, stream)
-    ws = pauli.workspace("split_bf16", 9, 1, dev)
+    ws = pauli.workspace(algo, 9, 1, dev)
 
     def per_matrix():
         for g, o in zip(G, outs):
             n = g.shape[-1].bit_length() - 1
-            oo = pauli._opts("split_bf16", 0, 0, 0, ctypes.c_void_p(stream.cuda_stream), ws)
+            oo = pauli._opts(algo, 0, 0, 0, ctypes.c_void_p(stream.cuda_stream), ws)
             st = pauli.load_library().pauli_decompose(g.data_ptr(), n, 1, o.data_ptr(), ctypes.byref(oo))
             if st:
                 raise RuntimeError(pauli.last_error())
     ms_each = timed(per_matrix, max(2, a.steps // 4), 1, stream)
     coeffs = float(sum(4 ** n for n in Ns))
-    flops = float(sum(12 * 8 ** n for n in Ns))
+    flops = float(sum(4 * PLANES[algo] * 8 ** n for n in Ns))
     line = {"metric": "Pauli coeffs/sec, uneven batch", "value": coeffs / (ms / 1e3), "unit": "coeffs/s",
             "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[algo], "data": "synthetic",
             "config": {"workload": "512 complex64 matrices, N uniform on 3..9 (seed %d), 20%% Hermitian, "
-                                   "split_bf16, one HIP graph replay per step" % workloads.SEED_BATCH,
-                       "batch": len(Ns), "tile": tile},
+                                   "%s, one HIP graph replay per step" % (workloads.SEED_BATCH, algo),
+                       "batch": len(Ns), "tile": tile, "algo": algo},
             "executed_tflops": flops / (ms / 1e3) / 1e12,
+            "useful_tflops": float(sum(4 * 8 ** n for n in Ns)) / (ms / 1e3) / 1e12,
             "per_matrix_launch_ms": ms_each, "speedup_vs_per_matrix": ms_each / ms}
     print(json.dumps(line), flush=True)
 

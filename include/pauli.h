@@ -170,7 +170,8 @@ int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
  * independent, here also across matrices): G[k] (device pointer) holds a
  * 2^N[k] x 2^N[k] matrix, out[k] receives its 4^N[k] coefficients.  G, N and
  * out are HOST arrays of length count.  1 <= N[k] <= 12, count >= 1; algo
- * SPLIT_BF16 or FP32, C64 in and out.
+ * SPLIT_BF16, SPLIT_FP16 or FP32, C64 in and out (SPLIT_FP16 first finds
+ * every matrix's prescale with two more kernels in the same graph).
  * opts->workspace (required) must hold pauli_batched_workspace_bytes(count,
  * N, algo) bytes of device memory that stays untouched while the work runs.
  * The work is one batched pack launch and one persistent contraction launch
@@ -194,7 +195,7 @@ size_t pauli_batched_workspace_bytes(int count, const int* N, int algo);
 /* Number of persistent-kernel tile shapes for the uneven batch. */
 int pauli_batched_tile_count(void);
 
-/* 1 if batched tile shape `tile` can run `algo` (every shape runs SPLIT_BF16 and FP32). */
+/* 1 if batched tile shape `tile` can run `algo` (every shape runs every matrix-core algo). */
 int pauli_batched_tile_valid(int algo, int tile);
 
 /*
@@ -231,7 +232,8 @@ size_t pauli_workspace_bytes(int algo, int N, int batch);
  * The file, read once per process before the first tile choice, holds one
  * entry per line: "algo N tile" for single matrices and
  * "B planes tile c_1 ... c_12" for a batch of c_n matrices of order n
- * (planes 3 = SPLIT_BF16, 1 = FP32); lines that do not parse are ignored.
+ * (planes 3 = SPLIT_BF16, 2 = SPLIT_FP16, 1 = FP32); lines that do not parse
+ * are ignored.
  */
 int pauli_autotune(int N_min, int N_max, const pauli_opts* opts);
 

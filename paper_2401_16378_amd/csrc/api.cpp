@@ -481,9 +481,10 @@ int pauli_version(void) { return 1; }
 
 // ---------------------------------------------------------------------------
 // Uneven batch: batched pack + persistent contraction behind a cached graph.
-// Workspace layout: [descriptor table, tile slot table | counter | packed
-// operands]; the slot table is sized for the tile shape with the most tiles,
-// so one workspace size serves every shape.
+// Workspace layout: [descriptor table, pack and tile slot tables | counter |
+// (two-plane split: prescale exponents per slot | partial maxima per pack
+// tile) | packed operands]; the tile slot table is sized for the tile shape
+// with the most tiles, so one workspace size serves every shape.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -496,6 +497,7 @@ struct BatchLayout {
     std::vector<uint32_t> tile0;   // per slot
     uint32_t pack_total = 0, tile_total = 0;
     size_t items_bytes = 0, table_bytes = 0, counter_off = 0, packed_off = 0, total_bytes = 0;
+    size_t pe_off = 0, partial_off = 0;   // two-plane split: prescale exponents, partial maxima
     std::vector<uint32_t> pack_slot;   // slot of every pack tile
     std::vector<uint32_t> tile_slot;   // slot of every output tile
 };
@@ -525,7 +527,13 @@ BatchLayout batch_layout(int count, const int* N, int planes, int btile) {
     // descriptors, pack slots, output slots (room for the tile shape with the most tiles)
     L.table_bytes = round256(L.items_bytes + sizeof(uint32_t) * ((size_t)L.pack_total + max_tiles));
     L.counter_off = L.table_bytes;
-    L.packed_off = L.counter_off + 256;
+    size_t next = L.counter_off + 256;
+    if (planes == 2) {
+        L.pe_off = next;
+        L.partial_off = L.pe_off + round256(sizeof(int) * (size_t)count);
+        next = L.partial_off + round256(sizeof(float) * (size_t)L.pack_total);
+    }
+    L.packed_off = next;
     L.total_bytes = L.packed_off + off;
     return L;
 }
@@ -579,8 +587,9 @@ int validate_batch(int count, const void* const* G, const int* N, void* const* o
                    const char* fn) {
     if (count < 1) return fail(PAULI_EINVAL, "%s: count=%d must be >= 1", fn, count);
     if (!G || !N || !out) return fail(PAULI_EINVAL, "%s: NULL array", fn);
-    if (o.algo != PAULI_ALGO_SPLIT_BF16 && o.algo != PAULI_ALGO_FP32)
-        return fail(PAULI_EUNSUPPORTED, "%s: algo %d not available batched (SPLIT_BF16 or FP32)", fn, o.algo);
+    if (!is_mfma(o.algo))
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d not available batched (SPLIT_BF16, SPLIT_FP16 or FP32)", fn,
+                    o.algo);
     if (o.in_dtype != PAULI_C64 || o.out_dtype != PAULI_C64)
         return fail(PAULI_EUNSUPPORTED, "%s: only C64 input and output", fn);
     if (o.tile < 0 || o.tile > batched_tile_count())
@@ -663,8 +672,11 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
+            int* pe_dev = planes == 2 ? (int*)(ws + probe.pe_off) : nullptr;
+            float* partial_dev = planes == 2 ? (float*)(ws + probe.partial_off) : nullptr;
             const hipError_t le = launch_batched(planes, btile, items_dev, pack_slot_dev, tile_slot_dev,
-                                                 probe.pack_total, probe.tile_total, packed, counter_dev, cap);
+                                                 (uint32_t)count, probe.pack_total, probe.tile_total, packed,
+                                                 counter_dev, pe_dev, partial_dev, cap);
             e = hipStreamEndCapture(cap, &graph);
             if (le != hipSuccess) e = le;
         }
@@ -702,7 +714,7 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
 }  // namespace
 
 extern "C" size_t pauli_batched_workspace_bytes(int count, const int* N, int algo) {
-    if (count < 1 || !N || (algo != PAULI_ALGO_SPLIT_BF16 && algo != PAULI_ALGO_FP32)) return 0;
+    if (count < 1 || !N || !is_mfma(algo)) return 0;
     for (int k = 0; k < count; ++k)
         if (N[k] < 1 || N[k] > N_MAX_BATCHED) return 0;
     return batch_layout(count, N, planes_of(algo), 1).total_bytes;
@@ -766,12 +778,12 @@ extern "C" int pauli_autotune_batched(int count, const void* const* G, const int
 extern "C" int pauli_batched_tile_count(void) { return batched_tile_count(); }
 
 extern "C" int pauli_batched_tile_valid(int algo, int tile) {
-    if (algo != PAULI_ALGO_SPLIT_BF16 && algo != PAULI_ALGO_FP32) return 0;
+    if (!is_mfma(algo)) return 0;
     return batched_tile_valid(planes_of(algo), tile) ? 1 : 0;
 }
 
 extern "C" int pauli_batched_tile_selected(int count, const int* N, int algo) {
-    if (count < 1 || !N || (algo != PAULI_ALGO_SPLIT_BF16 && algo != PAULI_ALGO_FP32)) return 0;
+    if (count < 1 || !N || !is_mfma(algo)) return 0;
     return tuned_btile(planes_of(algo), count, N);
 }
 

@@ -16,7 +16,9 @@
 // thread zeroes the counter: the contraction runs after the pack on the same
 // stream, and the previous contraction has finished before the pack starts
 // (no memset node, so the sequence can be captured in a HIP graph and
-// replayed).
+// replayed).  The two-plane split first finds every matrix's prescale: one
+// reduction workgroup per pack tile takes the largest component of an equal
+// share of its matrix, then one workgroup per matrix reduces its shares.
 #include "mfma_tile.hpp"
 
 namespace pauli {
@@ -24,16 +26,50 @@ namespace {
 
 using namespace mfma;
 
+// Share t of its matrix (pack tile t): 4^n / pack_tiles(n) consecutive
+// elements, an integer count (32 x 128 for n >= 7, the whole matrix below 5).
+__global__ __launch_bounds__(256) void absmax_batched_kernel(const BatchItem* __restrict__ items,
+                                                             const uint32_t* __restrict__ pack_slot,
+                                                             float* __restrict__ partial) {
+    __shared__ float red[4];
+    const BatchItem it = items[pack_slot[blockIdx.x]];
+    const size_t n = (size_t)1 << (2 * it.n);
+    const size_t per = n / pack_tiles(it.n);
+    const float2* p = (const float2*)it.in + (size_t)(blockIdx.x - it.pack0) * per;
+    float m = 0.f;
+    for (size_t i = threadIdx.x; i < per; i += 256) {
+        const float2 v = p[i];
+        m = __builtin_fmaxf(m, __builtin_fmaxf(__builtin_fabsf(v.x), __builtin_fabsf(v.y)));
+    }
+    m = block_max256(m, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+// One workgroup per descriptor slot: the matrix's prescale exponent.
+__global__ __launch_bounds__(256) void prescale_batched_kernel(const BatchItem* __restrict__ items,
+                                                               const float* __restrict__ partial,
+                                                               int* __restrict__ pe) {
+    __shared__ float red[4];
+    const BatchItem it = items[blockIdx.x];
+    const uint32_t tiles = pack_tiles(it.n);
+    float m = 0.f;
+    for (uint32_t i = threadIdx.x; i < tiles; i += 256) m = __builtin_fmaxf(m, partial[it.pack0 + i]);
+    m = block_max256(m, red);
+    if (threadIdx.x == 0) pe[blockIdx.x] = prescale_exponent(m);
+}
+
 template <int PLANES>
 __global__ __launch_bounds__(256) void pack_batched_kernel(const BatchItem* __restrict__ items,
                                                            const uint32_t* __restrict__ pack_slot,
                                                            unsigned char* __restrict__ ws,
-                                                           unsigned int* __restrict__ counter) {
+                                                           unsigned int* __restrict__ counter,
+                                                           const int* __restrict__ pe) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[pack_lds_bytes<PLANES>()];
     if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;   // for the contraction that follows
-    const BatchItem it = items[pack_slot[blockIdx.x]];
+    const uint32_t slot = pack_slot[blockIdx.x];
+    const BatchItem it = items[slot];
     pack_tile<PLANES, FORWARD, false>((const unsigned char*)it.in, ws + it.ws_off, it.n,
-                                      blockIdx.x - it.pack0, lds);
+                                      blockIdx.x - it.pack0, lds, PLANES == 2 ? pe[slot] : 0);
 }
 
 // AHEAD > 0: output tiles of matrices with at least MT rows and a whole
@@ -45,6 +81,7 @@ __device__ __attribute__((always_inline)) inline void batched_loop(const BatchIt
                                                                    const uint32_t* __restrict__ tile_slot,
                                                                    uint32_t total, const unsigned char* __restrict__ ws,
                                                                    unsigned int* __restrict__ counter,
+                                                                   const int* __restrict__ pe,
                                                                    unsigned char* lds, uint32_t& next) {
     static_assert(AHEAD == 0 || WAVES == 4, "the LDS-staged contraction runs four waves per workgroup");
     constexpr int MT = WAVES * RB * 32;
@@ -55,11 +92,13 @@ __device__ __attribute__((always_inline)) inline void batched_loop(const BatchIt
     while (t < total) {                // uniform: every workgroup leaves once the list is done
         uint32_t claimed = 0;
         if (threadIdx.x == 0) claimed = atomicAdd(counter, 1u);   // read only after this tile
-        const BatchItem it = items[tile_slot[t]];
+        const uint32_t slot = tile_slot[t];
+        const BatchItem it = items[slot];
         const uint32_t Dp = padded_dim(it.n);
         const uint32_t nMB = Dp > (uint32_t)MT ? Dp / MT : 1u;
         const uint32_t local = t - it.tile0;
-        const double sc = 1.0 / (double)(1u << it.n);
+        double sc = 1.0 / (double)(1u << it.n);
+        if constexpr (PLANES == 2) sc = __builtin_ldexp(sc, -pe[slot]);
         bool staged = false;
         if constexpr (AHEAD > 0) {
             constexpr uint32_t GP = 32 * RB / Pack<PLANES>::SK / 2;   // slice pairs per sign group
@@ -87,10 +126,11 @@ __global__ __launch_bounds__(WAVES * 64) void contract_batched_kernel(const Batc
                                                                       const uint32_t* __restrict__ tile_slot,
                                                                       uint32_t total,
                                                                       const unsigned char* __restrict__ ws,
-                                                                      unsigned int* __restrict__ counter) {
+                                                                      unsigned int* __restrict__ counter,
+                                                                      const int* __restrict__ pe) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     __shared__ uint32_t next;
-    batched_loop<PLANES, RB, WAVES, PF, AHEAD>(items, tile_slot, total, ws, counter, lds, next);
+    batched_loop<PLANES, RB, WAVES, PF, AHEAD>(items, tile_slot, total, ws, counter, pe, lds, next);
 }
 
 // The same loop with the registers budgeted for two waves per SIMD, so that
@@ -100,10 +140,11 @@ __global__ __launch_bounds__(WAVES * 64, 2) void contract_batched2_kernel(const 
                                                                           const uint32_t* __restrict__ tile_slot,
                                                                           uint32_t total,
                                                                           const unsigned char* __restrict__ ws,
-                                                                          unsigned int* __restrict__ counter) {
+                                                                          unsigned int* __restrict__ counter,
+                                                                          const int* __restrict__ pe) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     __shared__ uint32_t next;
-    batched_loop<PLANES, RB, WAVES, PF, AHEAD>(items, tile_slot, total, ws, counter, lds, next);
+    batched_loop<PLANES, RB, WAVES, PF, AHEAD>(items, tile_slot, total, ws, counter, pe, lds, next);
 }
 
 // Tile shapes the persistent kernel can run with: (RB, WAVES, PF, waves per
@@ -124,7 +165,7 @@ constexpr int NBTILES = sizeof(BTILES) / sizeof(BTILES[0]);
 
 template <int PLANES, int RB, int WAVES, int PF, int OCC, int AHEAD = 0>
 hipError_t launch_contract_batched(const BatchItem* items, const uint32_t* tile_slot, uint32_t total,
-                                   const unsigned char* ws, unsigned int* counter, hipStream_t s) {
+                                   const unsigned char* ws, unsigned int* counter, const int* pe, hipStream_t s) {
     if constexpr (!ring_tile_ok(PLANES, RB)) {
         return hipErrorInvalidValue;
     } else {
@@ -144,7 +185,7 @@ hipError_t launch_contract_batched(const BatchItem* items, const uint32_t* tile_
             if (per_cu < 1) per_cu = 1;
             uint32_t grid = (uint32_t)cus * (uint32_t)per_cu;
             if (grid > total) grid = total;   // never more workgroups than tiles
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES * 64), lds, s, items, tile_slot, total, ws, counter);
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVES * 64), lds, s, items, tile_slot, total, ws, counter, pe);
             return hipGetLastError();
         };
         if constexpr (OCC == 2) return launch(contract_batched2_kernel<PLANES, RB, WAVES, PF, AHEAD>);
@@ -154,13 +195,13 @@ hipError_t launch_contract_batched(const BatchItem* items, const uint32_t* tile_
 
 template <int PLANES>
 hipError_t launch_contract_btile(int btile, const BatchItem* items, const uint32_t* tile_slot, uint32_t total,
-                                 const unsigned char* ws, unsigned int* counter, hipStream_t s) {
+                                 const unsigned char* ws, unsigned int* counter, const int* pe, hipStream_t s) {
     switch (btile) {
-        case 1: return launch_contract_batched<PLANES, 2, 4, 4, 1>(items, tile_slot, total, ws, counter, s);
-        case 2: return launch_contract_batched<PLANES, 1, 4, 2, 1>(items, tile_slot, total, ws, counter, s);
-        case 3: return launch_contract_batched<PLANES, 1, 2, 2, 1>(items, tile_slot, total, ws, counter, s);
-        case 4: return launch_contract_batched<PLANES, 2, 4, 2, 2>(items, tile_slot, total, ws, counter, s);
-        case 5: return launch_contract_batched<PLANES, 2, 4, 2, 1, 3>(items, tile_slot, total, ws, counter, s);
+        case 1: return launch_contract_batched<PLANES, 2, 4, 4, 1>(items, tile_slot, total, ws, counter, pe, s);
+        case 2: return launch_contract_batched<PLANES, 1, 4, 2, 1>(items, tile_slot, total, ws, counter, pe, s);
+        case 3: return launch_contract_batched<PLANES, 1, 2, 2, 1>(items, tile_slot, total, ws, counter, pe, s);
+        case 4: return launch_contract_batched<PLANES, 2, 4, 2, 2>(items, tile_slot, total, ws, counter, pe, s);
+        case 5: return launch_contract_batched<PLANES, 2, 4, 2, 1, 3>(items, tile_slot, total, ws, counter, pe, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -184,24 +225,38 @@ uint32_t batched_pack_tiles(int n) { return mfma::pack_tiles(n); }
 
 size_t batched_packed_bytes(int planes, int n) {
     const size_t Dp = mfma::padded_dim(n);
-    return Dp * Dp * (size_t)(planes == 3 ? mfma::Pack<3>::EB : mfma::Pack<1>::EB);
+    const size_t eb = planes == 3 ? mfma::Pack<3>::EB : (planes == 2 ? mfma::Pack<2>::EB : mfma::Pack<1>::EB);
+    return Dp * Dp * eb;
 }
 
 hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, const uint32_t* pack_slot_dev,
-                          const uint32_t* tile_slot_dev, uint32_t pack_total, uint32_t tile_total,
-                          unsigned char* packed, unsigned int* counter_dev, hipStream_t stream) {
-    if (!batched_tile_valid(planes, btile) || pack_total == 0) return hipErrorInvalidValue;
-    if (planes == 3)
+                          const uint32_t* tile_slot_dev, uint32_t count, uint32_t pack_total, uint32_t tile_total,
+                          unsigned char* packed, unsigned int* counter_dev, int* pe_dev, float* partial_dev,
+                          hipStream_t stream) {
+    if (!batched_tile_valid(planes, btile) || pack_total == 0 || count == 0) return hipErrorInvalidValue;
+    if (planes == 2 && (!pe_dev || !partial_dev)) return hipErrorInvalidValue;
+    if (planes == 3) {
         hipLaunchKernelGGL((pack_batched_kernel<3>), dim3(pack_total), dim3(256), 0, stream, items_dev, pack_slot_dev,
-                           packed, counter_dev);
-    else
+                           packed, counter_dev, (const int*)nullptr);
+    } else if (planes == 2) {
+        hipLaunchKernelGGL(absmax_batched_kernel, dim3(pack_total), dim3(256), 0, stream, items_dev, pack_slot_dev,
+                           partial_dev);
+        hipLaunchKernelGGL(prescale_batched_kernel, dim3(count), dim3(256), 0, stream, items_dev,
+                           (const float*)partial_dev, pe_dev);
+        hipLaunchKernelGGL((pack_batched_kernel<2>), dim3(pack_total), dim3(256), 0, stream, items_dev, pack_slot_dev,
+                           packed, counter_dev, (const int*)pe_dev);
+    } else {
         hipLaunchKernelGGL((pack_batched_kernel<1>), dim3(pack_total), dim3(256), 0, stream, items_dev, pack_slot_dev,
-                           packed, counter_dev);
+                           packed, counter_dev, (const int*)nullptr);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return planes == 3
-               ? launch_contract_btile<3>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, stream)
-               : launch_contract_btile<1>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, stream);
+    const int* pe = pe_dev;
+    if (planes == 3)
+        return launch_contract_btile<3>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, pe, stream);
+    if (planes == 2)
+        return launch_contract_btile<2>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, pe, stream);
+    return launch_contract_btile<1>(btile, items_dev, tile_slot_dev, tile_total, packed, counter_dev, pe, stream);
 }
 
 }  // namespace pauli

@@ -16,7 +16,7 @@ enum Dir { FORWARD = 0, ADJOINT = 1 };
 hipError_t launch_gray(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N,
                        int batch, double scale, hipStream_t stream);
 
-// Matrix-core contraction.  planes = 3 (split bf16) or 1 (fp32).
+// Matrix-core contraction.  planes = 3 (split bf16), 2 (split fp16) or 1 (fp32).
 // tile = 1-based tile id (0 = default for N).  ws = device scratch of
 // mfma_workspace_bytes(planes, N, batch) bytes for the packed operand.
 hipError_t launch_mfma(Dir dir, int planes, const void* in, bool in_c128, void* out,
@@ -58,9 +58,12 @@ uint32_t batched_pack_tiles(int n);
 size_t batched_packed_bytes(int planes, int n);
 // pack_slot_dev[t] / tile_slot_dev[t] = descriptor slot of the matrix owning
 // pack tile t / output tile t.  The pack launch also zeroes *counter_dev.
+// planes = 2 also needs pe_dev (count ints: each slot's prescale exponent)
+// and partial_dev (pack_total floats), both written before they are read.
 hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, const uint32_t* pack_slot_dev,
-                          const uint32_t* tile_slot_dev, uint32_t pack_total, uint32_t tile_total,
-                          unsigned char* packed, unsigned int* counter_dev, hipStream_t stream);
+                          const uint32_t* tile_slot_dev, uint32_t count, uint32_t pack_total, uint32_t tile_total,
+                          unsigned char* packed, unsigned int* counter_dev, int* pe_dev, float* partial_dev,
+                          hipStream_t stream);
 
 // Pauli-string list: the host sorts the strings into chunks of at most 256
 // strings sharing a line group (flip masks equal above bit 3); chunk k covers

@@ -37,14 +37,6 @@ __global__ __launch_bounds__(256) void pack_herm_kernel(const void* __restrict__
 // 4^N elements of matrix blockIdx.y to R partial maxima, prescale_kernel
 // reduces those and stores the matrix's prescale exponent.  Both write every
 // value they produce, so the workspace needs no clearing.
-__device__ inline float block_max256(float m, float* red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = __builtin_fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    return __builtin_fmaxf(__builtin_fmaxf(red[0], red[1]), __builtin_fmaxf(red[2], red[3]));
-}
-
 template <bool IN128>
 __global__ __launch_bounds__(256) void absmax_kernel(const void* __restrict__ in, int N, float* __restrict__ partial,
                                                      uint32_t R) {

@@ -160,6 +160,16 @@ __host__ __device__ inline int prescale_exponent(float maxabs) {
     return 15 - e;
 }
 
+// Largest of m over a 256-thread workgroup (red: 4 floats of LDS); every
+// thread gets the result.
+__device__ inline float block_max256(float m, float* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = __builtin_fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    return __builtin_fmaxf(__builtin_fmaxf(red[0], red[1]), __builtin_fmaxf(red[2], red[3]));
+}
+
 template <bool IN128>
 __device__ inline f32x2 load_elem(const unsigned char* base, size_t idx) {
     if constexpr (IN128) {
@@ -210,7 +220,7 @@ constexpr int pack_lds_bytes() {
     return DIR == FORWARD || stage >= adj ? stage : adj;
 }
 
-inline uint32_t pack_tiles(int N) {
+__host__ __device__ inline uint32_t pack_tiles(int N) {
     const uint32_t Dp = padded_dim(N);
     const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
     return (Dp / XT) * (Dp / KT);

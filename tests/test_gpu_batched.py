@@ -37,10 +37,11 @@ def batch():
     return Ns, mats, herm, dev
 
 
-def test_batch_vs_oracle(batch):
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16"])
+def test_batch_vs_oracle(batch, algo):
     p = lib()
     Ns, mats, herm, dev = batch
-    outs = p.decompose_batched(dev)
+    outs = p.decompose_batched(dev, algo=algo)
     torch.cuda.synchronize()
     worst = 0.0
     for k, (N, G) in enumerate(zip(Ns, mats)):
@@ -60,21 +61,23 @@ def test_batch_vs_oracle(batch):
     assert worst > 0.0
 
 
-def test_batch_bitexact_vs_single(batch):
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16"])
+def test_batch_bitexact_vs_single(batch, algo):
     p = lib()
     Ns, mats, herm, dev = batch
-    outs = p.decompose_batched(dev)
+    outs = p.decompose_batched(dev, algo=algo)
     for k in range(0, len(dev), 7):
-        single = p.decompose(dev[k])
+        single = p.decompose(dev[k], algo=algo)
         assert torch.equal(outs[k], single), k
 
 
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16"])
 @pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
-def test_every_tile_shape(batch, tile):
+def test_every_tile_shape(batch, tile, algo):
     p = lib()
     Ns, mats, herm, dev = batch
-    ref = p.decompose_batched(dev, tile=1)
-    got = p.decompose_batched(dev, tile=tile)
+    ref = p.decompose_batched(dev, algo=algo, tile=1)
+    got = p.decompose_batched(dev, algo=algo, tile=tile)
     for a, b in zip(ref, got):
         assert torch.equal(a, b)
 
@@ -221,7 +224,7 @@ def test_autotune_batched_writes_tune_cache(tmp_path):
     assert "B 3 %d 0 0 1 1 2 2 0 0 0 0 0 0" % tuned in lines, lines
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
 def test_large_members(algo):
     """Members up to the batched limit N = 12 next to small ones: every
     member equals its single-matrix decomposition bit for bit, for every
@@ -237,7 +240,7 @@ def test_large_members(algo):
         outs = p.decompose_batched(dev, algo=algo, tile=tile)
         for k in range(len(Ns)):
             assert torch.equal(outs[k], singles[k]), (tile, k, Ns[k])
-    tol = 1e-6 if algo == "split_bf16" else 1e-5
+    tol = 1e-5 if algo == "fp32" else 1e-6
     for k, (n, G) in enumerate(zip(Ns, mats)):
         if n < 10:
             continue
