@@ -500,7 +500,39 @@ struct BatchLayout {
     size_t pe_off = 0, partial_off = 0;   // two-plane split: prescale exponents, partial maxima
     std::vector<uint32_t> pack_slot;   // slot of every pack tile
     std::vector<uint32_t> tile_slot;   // slot of every output tile
+    std::vector<uint32_t> queues;      // [nq | nq + 1 offsets | output tile ids], see launch_batched
+    size_t staged_bytes = 0;           // descriptors + pack slots + tile slots + queues
 };
+
+// Deal the flip-mask slabs of the batch (every row block of a slab together)
+// to nq queues, each slab to the least loaded queue, in slot order (largest
+// matrices first).  A slab's estimated cost is its D x D multiply-adds per
+// row-block tile plus a fixed per-tile overhead.
+std::vector<uint32_t> batch_queues(const BatchLayout& L, const int* N, int btile) {
+    const uint32_t nq = std::min<uint32_t>(MAX_QUEUES, L.tile_total);
+    std::vector<std::vector<uint32_t>> q(nq);
+    std::vector<double> load(nq, 0.0);
+    for (size_t slot = 0; slot < L.order.size(); ++slot) {
+        const int n = N[L.order[slot]];
+        const uint32_t Dp = n < 5 ? 32u : (1u << n), nXB = Dp / 32u;
+        const uint32_t nMB = batched_output_tiles(btile, n) / nXB;
+        const double cost = (double)nMB * ((double)Dp * (double)Dp + 16384.0);
+        for (uint32_t xb = 0; xb < nXB; ++xb) {
+            const uint32_t k = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (uint32_t mb = 0; mb < nMB; ++mb) q[k].push_back(L.tile0[slot] + xb * nMB + mb);
+            load[k] += cost;
+        }
+    }
+    std::vector<uint32_t> out{nq};
+    uint32_t off = 0;
+    for (uint32_t k = 0; k < nq; ++k) {
+        out.push_back(off);
+        off += (uint32_t)q[k].size();
+    }
+    out.push_back(off);
+    for (uint32_t k = 0; k < nq; ++k) out.insert(out.end(), q[k].begin(), q[k].end());
+    return out;
+}
 
 BatchLayout batch_layout(int count, const int* N, int planes, int btile) {
     BatchLayout L;
@@ -524,8 +556,12 @@ BatchLayout batch_layout(int count, const int* N, int planes, int btile) {
         max_tiles += most;
     }
     L.items_bytes = sizeof(BatchItem) * (size_t)count;
-    // descriptors, pack slots, output slots (room for the tile shape with the most tiles)
-    L.table_bytes = round256(L.items_bytes + sizeof(uint32_t) * ((size_t)L.pack_total + max_tiles));
+    L.queues = batch_queues(L, N, btile);
+    L.staged_bytes = L.items_bytes + sizeof(uint32_t) * ((size_t)L.pack_total + L.tile_total + L.queues.size());
+    // descriptors, pack slots, output slots and queues (room for the tile
+    // shape with the most tiles)
+    L.table_bytes =
+        round256(L.items_bytes + sizeof(uint32_t) * ((size_t)L.pack_total + 2 * max_tiles + 2 + MAX_QUEUES));
     L.counter_off = L.table_bytes;
     size_t next = L.counter_off + 256;
     if (planes == 2) {
@@ -646,7 +682,8 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
     BatchItem* items_dev = (BatchItem*)ws;
     const uint32_t* pack_slot_dev = (const uint32_t*)(ws + probe.items_bytes);
     const uint32_t* tile_slot_dev = pack_slot_dev + probe.pack_total;
-    const size_t staged = probe.items_bytes + sizeof(uint32_t) * ((size_t)probe.pack_total + probe.tile_total);
+    const uint32_t* queues_dev = tile_slot_dev + probe.tile_total;
+    const size_t staged = probe.staged_bytes;
     unsigned int* counter_dev = (unsigned int*)(ws + probe.counter_off);
     unsigned char* packed = ws + probe.packed_off;
     if (found == g_graphs.end() && g_graphs.size() >= MAX_GRAPHS) evict_lru_locked();
@@ -664,9 +701,11 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
         memcpy(ge.pinned + probe.items_bytes, probe.pack_slot.data(), sizeof(uint32_t) * probe.pack_total);
         memcpy(ge.pinned + probe.items_bytes + sizeof(uint32_t) * probe.pack_total, probe.tile_slot.data(),
                sizeof(uint32_t) * probe.tile_total);
+        memcpy(ge.pinned + probe.items_bytes + sizeof(uint32_t) * ((size_t)probe.pack_total + probe.tile_total),
+               probe.queues.data(), sizeof(uint32_t) * probe.queues.size());
         if ((e = hipEventCreateWithFlags(&ge.copied, hipEventDisableTiming)) != hipSuccess) return discard(e);
         if ((e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming)) != hipSuccess) return discard(e);
-        // Capture on a private stream: batched pack (which zeroes the counter), persistent contraction.
+        // Capture on a private stream: batched pack (which zeroes the queue counters), persistent contraction.
         hipStream_t cap;
         if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return discard(e);
         hipGraph_t graph = nullptr;
@@ -674,7 +713,7 @@ int run_batched(int count, const void* const* G, const int* N, void* const* out,
         if (e == hipSuccess) {
             int* pe_dev = planes == 2 ? (int*)(ws + probe.pe_off) : nullptr;
             float* partial_dev = planes == 2 ? (float*)(ws + probe.partial_off) : nullptr;
-            const hipError_t le = launch_batched(planes, btile, items_dev, pack_slot_dev, tile_slot_dev,
+            const hipError_t le = launch_batched(planes, btile, items_dev, pack_slot_dev, tile_slot_dev, queues_dev,
                                                  (uint32_t)count, probe.pack_total, probe.tile_total, packed,
                                                  counter_dev, pe_dev, partial_dev, cap);
             e = hipStreamEndCapture(cap, &graph);

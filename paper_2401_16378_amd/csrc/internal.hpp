@@ -57,13 +57,17 @@ uint32_t batched_output_tiles(int btile, int n);
 uint32_t batched_pack_tiles(int n);
 size_t batched_packed_bytes(int planes, int n);
 // pack_slot_dev[t] / tile_slot_dev[t] = descriptor slot of the matrix owning
-// pack tile t / output tile t.  The pack launch also zeroes *counter_dev.
+// pack tile t / output tile t.  queues_dev = [nq | nq + 1 offsets | output
+// tile ids] with 1 <= nq <= MAX_QUEUES and nq <= tile_total: queue q's tiles
+// are claimed, through counter_dev[q], by the workgroups whose index is q
+// modulo nq.  The pack launch also zeroes counter_dev[0 .. MAX_QUEUES).
 // planes = 2 also needs pe_dev (count ints: each slot's prescale exponent)
 // and partial_dev (pack_total floats), both written before they are read.
+constexpr uint32_t MAX_QUEUES = 8;   // one per XCD
 hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, const uint32_t* pack_slot_dev,
-                          const uint32_t* tile_slot_dev, uint32_t count, uint32_t pack_total, uint32_t tile_total,
-                          unsigned char* packed, unsigned int* counter_dev, int* pe_dev, float* partial_dev,
-                          hipStream_t stream);
+                          const uint32_t* tile_slot_dev, const uint32_t* queues_dev, uint32_t count,
+                          uint32_t pack_total, uint32_t tile_total, unsigned char* packed, unsigned int* counter_dev,
+                          int* pe_dev, float* partial_dev, hipStream_t stream);
 
 // Pauli-string list: the host sorts the strings into chunks of at most 256
 // strings sharing a line group (flip masks equal above bit 3); chunk k covers

@@ -258,6 +258,94 @@ __device__ inline uint32_t herm_pack_tile(int N, uint32_t hmin, uint32_t t) {
     return xb * nKT + kt;
 }
 
+// Split one thread's 4x4 micro-block v (forward: v[a * 4 + b] = G[row a][col
+// b]; adjoint: 16 consecutive phased coefficients) into the operand format
+// and store it in the LDS staging tile at flip-mask group xh (x_l / 4) and K
+// slot kh: plane-major, 32 flip masks per plane, pitch bytes per mask.
+// pe: the prescale exponent of the two-plane split (unused otherwise).
+template <int PLANES, int DIR>
+__device__ __attribute__((always_inline)) inline void stage_block(f32x2 (&v)[16], int xh, int kh, int pe,
+                                                                  unsigned char* lds, uint32_t pitch) {
+    using P = Pack<PLANES>;
+    float gu = 1.f, ginv = 1.f;
+    if constexpr (PLANES == 2) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = f32x2{__builtin_ldexpf(v[r].x, pe), __builtin_ldexpf(v[r].y, pe)};
+    }
+    if constexpr (PLANES >= 2) {
+        float mx = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            mx = __builtin_fmaxf(mx, __builtin_fmaxf(__builtin_fabsf(v[r].x), __builtin_fabsf(v[r].y)));
+        if constexpr (PLANES == 3) block_grid(mx, gu, ginv);
+        else block_grid16(mx, gu, ginv);
+    }
+#pragma unroll
+    for (int x2 = 0; x2 < 4; ++x2) {
+        f32x2 e[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if constexpr (DIR == FORWARD) {
+                e[b] = v[((x2 ^ b) << 2) | b];  // row a = x2 ^ b, column b
+            } else {
+                const int d = x2 ^ b;             // (x ^ z) low bits
+                e[b] = v[(d & 1) | ((b & 1) << 1) | ((d >> 1) << 2) | ((b >> 1) << 3)];
+            }
+        }
+        unsigned char* cbase = lds + (xh * 4 + x2) * pitch + kh * P::ESZ;
+        const uint32_t PS = XT * pitch;  // plane stride
+        if constexpr (PLANES == 3) {
+            uint32_t hr0, mr0, lr0, hr1, mr1, lr1, hi0, mi0, li0, hi1, mi1, li1;
+            split3(e[0].x, e[1].x, gu, ginv, hr0, mr0, lr0);
+            split3(e[2].x, e[3].x, gu, ginv, hr1, mr1, lr1);
+            split3(e[0].y, e[1].y, gu, ginv, hi0, mi0, li0);
+            split3(e[2].y, e[3].y, gu, ginv, hi1, mi1, li1);
+            *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
+            *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
+            *(u32x2*)(cbase + 2 * PS) = u32x2{mr0, mr1};
+            *(u32x2*)(cbase + 3 * PS) = u32x2{mi0, mi1};
+            *(u32x2*)(cbase + 4 * PS) = u32x2{lr0, lr1};
+            *(u32x2*)(cbase + 5 * PS) = u32x2{li0, li1};
+        } else if constexpr (PLANES == 2) {
+            uint32_t hr0, lr0, hr1, lr1, hi0, li0, hi1, li1;
+            split2(e[0].x, e[1].x, gu, ginv, hr0, lr0);
+            split2(e[2].x, e[3].x, gu, ginv, hr1, lr1);
+            split2(e[0].y, e[1].y, gu, ginv, hi0, li0);
+            split2(e[2].y, e[3].y, gu, ginv, hi1, li1);
+            *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
+            *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
+            *(u32x2*)(cbase + 2 * PS) = u32x2{lr0, lr1};
+            *(u32x2*)(cbase + 3 * PS) = u32x2{li0, li1};
+        } else {
+            *(f32x4*)(cbase) = f32x4{e[0].x, e[1].x, e[2].x, e[3].x};
+            *(f32x4*)(cbase + PS) = f32x4{e[0].y, e[1].y, e[2].y, e[3].y};
+        }
+    }
+}
+
+// The 4x4 micro-block of G that thread (square g, block w6) of a pack tile
+// with flip masks X0.. and K values Q0.. gathers: rows ((Q0 + 32 g) ^ X0) &
+// ~31 + 4 (w6 >> 3) .., columns Q0 + 32 g + 4 (w6 & 7) .., zero outside a
+// matrix of order D < 32 (`full`: D >= 32).  Returns its staging slots.
+template <bool IN128>
+__device__ __attribute__((always_inline)) inline void load_block_fwd(const unsigned char* __restrict__ src, uint32_t D,
+                                                                     bool full, uint32_t X0, uint32_t Q0, int g, int w6,
+                                                                     f32x2 (&v)[16], int& xh, int& kh) {
+    const int mr = w6 >> 3, mc = w6 & 7;
+    const uint32_t q0 = Q0 + 32 * g + 4 * mc;
+    const uint32_t r0 = (((Q0 + 32 * g) ^ X0) & ~31u) + 4 * mr;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t r = r0 + a, q = q0 + b;
+            v[a * 4 + b] = (full || (r < D && q < D)) ? load_elem<IN128>(src, (size_t)r * D + q) : f32x2{0.f, 0.f};
+        }
+    xh = mr ^ mc;
+    kh = 32 * g + 4 * mc;
+}
+
 // Pack tile t (of pack_tiles(N)) of one matrix: 32 flip masks x KT values of
 // q.  256 threads; src = the matrix (or coefficient vector), ws = its packed
 // operand; lds holds pack_lds_bytes<PLANES, DIR>() bytes.
@@ -314,19 +402,7 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
     if (active) {
         int xh, kh;                              // column group (x_l / 4), first K slot
         if constexpr (DIR == FORWARD) {
-            const int mr = w6 >> 3, mc = w6 & 7;
-            const uint32_t q0 = Q0 + 32 * g + 4 * mc;
-            const uint32_t r0 = (((Q0 + 32 * g) ^ X0) & ~31u) + 4 * mr;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const uint32_t r = r0 + a, q = q0 + b;
-                    v[a * 4 + b] = (full || (r < D && q < D)) ? load_elem<IN128>(src, (size_t)r * D + q)
-                                                              : f32x2{0.f, 0.f};
-                }
-            xh = mr ^ mc;
-            kh = 32 * g + 4 * mc;
+            load_block_fwd<IN128>(src, D, full, X0, Q0, g, w6, v, xh, kh);
         } else {
             const uint32_t zb = Q0 + 32 * g;
             const uint32_t nb = pauli_index(X0, zb);
@@ -348,61 +424,7 @@ __device__ inline void pack_tile(const unsigned char* __restrict__ src, unsigned
             xh = xl >> 2;
             kh = 32 * g + zl;
         }
-        float gu = 1.f, ginv = 1.f;
-        if constexpr (PLANES == 2) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                v[r] = f32x2{__builtin_ldexpf(v[r].x, pe), __builtin_ldexpf(v[r].y, pe)};
-        }
-        if constexpr (PLANES >= 2) {
-            float mx = 0.f;
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                mx = __builtin_fmaxf(mx, __builtin_fmaxf(__builtin_fabsf(v[r].x), __builtin_fabsf(v[r].y)));
-            if constexpr (PLANES == 3) block_grid(mx, gu, ginv);
-            else block_grid16(mx, gu, ginv);
-        }
-#pragma unroll
-        for (int x2 = 0; x2 < 4; ++x2) {
-            f32x2 e[4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if constexpr (DIR == FORWARD) {
-                    e[b] = v[((x2 ^ b) << 2) | b];  // row a = x2 ^ b, column b
-                } else {
-                    const int d = x2 ^ b;             // (x ^ z) low bits
-                    e[b] = v[(d & 1) | ((b & 1) << 1) | ((d >> 1) << 2) | ((b >> 1) << 3)];
-                }
-            }
-            unsigned char* cbase = lds + (xh * 4 + x2) * pitch + kh * P::ESZ;
-            const uint32_t PS = XT * pitch;  // plane stride
-            if constexpr (PLANES == 3) {
-                uint32_t hr0, mr0, lr0, hr1, mr1, lr1, hi0, mi0, li0, hi1, mi1, li1;
-                split3(e[0].x, e[1].x, gu, ginv, hr0, mr0, lr0);
-                split3(e[2].x, e[3].x, gu, ginv, hr1, mr1, lr1);
-                split3(e[0].y, e[1].y, gu, ginv, hi0, mi0, li0);
-                split3(e[2].y, e[3].y, gu, ginv, hi1, mi1, li1);
-                *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
-                *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
-                *(u32x2*)(cbase + 2 * PS) = u32x2{mr0, mr1};
-                *(u32x2*)(cbase + 3 * PS) = u32x2{mi0, mi1};
-                *(u32x2*)(cbase + 4 * PS) = u32x2{lr0, lr1};
-                *(u32x2*)(cbase + 5 * PS) = u32x2{li0, li1};
-            } else if constexpr (PLANES == 2) {
-                uint32_t hr0, lr0, hr1, lr1, hi0, li0, hi1, li1;
-                split2(e[0].x, e[1].x, gu, ginv, hr0, lr0);
-                split2(e[2].x, e[3].x, gu, ginv, hr1, lr1);
-                split2(e[0].y, e[1].y, gu, ginv, hi0, li0);
-                split2(e[2].y, e[3].y, gu, ginv, hi1, li1);
-                *(u32x2*)(cbase + 0 * PS) = u32x2{hr0, hr1};
-                *(u32x2*)(cbase + 1 * PS) = u32x2{hi0, hi1};
-                *(u32x2*)(cbase + 2 * PS) = u32x2{lr0, lr1};
-                *(u32x2*)(cbase + 3 * PS) = u32x2{li0, li1};
-            } else {
-                *(f32x4*)(cbase) = f32x4{e[0].x, e[1].x, e[2].x, e[3].x};
-                *(f32x4*)(cbase + PS) = f32x4{e[0].y, e[1].y, e[2].y, e[3].y};
-            }
-        }
+        stage_block<PLANES, DIR>(v, xh, kh, pe, lds, pitch);
     }
     __syncthreads();
 

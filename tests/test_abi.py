@@ -119,8 +119,12 @@ def test_tiles(lib):
     assert lib.pauli_tile_valid(2, 0, 10) == 0 and lib.pauli_tile_valid(2, n + 1, 10) == 0
     assert lib.pauli_batched_tile_count() >= 1
     nb = lib.pauli_batched_tile_count()
-    assert all(lib.pauli_batched_tile_valid(a, t) == 1 for a in (1, 2) for t in range(1, nb + 1))
+    assert nb == 9
+    # every shape runs split-fp16; the 512-row fused shape (7) only it
+    assert all(lib.pauli_batched_tile_valid(4, t) == 1 for t in range(1, nb + 1))
+    assert all(lib.pauli_batched_tile_valid(a, t) == (t != 7) for a in (1, 2) for t in range(1, nb + 1))
     assert lib.pauli_batched_tile_valid(2, nb + 1) == 0 and lib.pauli_batched_tile_valid(1, 0) == 0
+    assert lib.pauli_batched_tile_valid(0, 1) == 0 and lib.pauli_batched_tile_valid(3, 1) == 0
     assert lib.pauli_batched_tile_valid(1, 1) == 1 and lib.pauli_batched_tile_valid(0, 1) == 0
 
 

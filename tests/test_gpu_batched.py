@@ -72,9 +72,12 @@ def test_batch_bitexact_vs_single(batch, algo):
 
 
 @pytest.mark.parametrize("algo", ["split_bf16", "split_fp16"])
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_every_tile_shape(batch, tile, algo):
     p = lib()
+    if not p.batched_tile_valid(tile, algo):
+        assert tile == 7 and algo == "split_bf16"
+        return
     Ns, mats, herm, dev = batch
     ref = p.decompose_batched(dev, algo=algo, tile=1)
     got = p.decompose_batched(dev, algo=algo, tile=tile)
@@ -146,7 +149,7 @@ def test_small_mixed_batch_fp32():
     mats = [workloads.iid_complex(n, 40 + n, np.complex64) for n in Ns]
     dev_m = [torch.from_numpy(m).to("cuda") for m in mats]
     tiles = [t for t in range(1, p.load_library().pauli_batched_tile_count() + 1) if p.batched_tile_valid(t, "fp32")]
-    assert len(tiles) == p.load_library().pauli_batched_tile_count()   # every shape runs binary32
+    assert len(tiles) == p.load_library().pauli_batched_tile_count() - 1   # all but the 512-row fused shape
     for tile in tiles:
         outs = p.decompose_batched(dev_m, algo="fp32", tile=tile)
         for m, o in zip(mats, outs):
@@ -237,6 +240,8 @@ def test_large_members(algo):
     singles = [p.decompose(d, algo=algo) for d in dev]
     nb = p.load_library().pauli_batched_tile_count()
     for tile in range(1, nb + 1):
+        if not p.batched_tile_valid(tile, algo):
+            continue
         outs = p.decompose_batched(dev, algo=algo, tile=tile)
         for k in range(len(Ns)):
             assert torch.equal(outs[k], singles[k]), (tile, k, Ns[k])
