@@ -183,8 +183,11 @@ int pauli_decompose_backward(const void* grad_c, int N, int batch, void* grad_G,
  * captures (with their pinned host staging) and releases the least recently
  * used one, after its last replay has finished, to make room for a new one.
  * opts->tile: 0 = the tuned or default shape, 1..
- * pauli_batched_tile_count() forces one.  Calls sharing a workspace must be
- * ordered on one stream.
+ * pauli_batched_tile_count() forces one.  Shapes 1-5 read an operand packed
+ * by a separate kernel; shapes 6-9 gather and split it from G inside the
+ * contraction (no pack kernel); the default is shape 8 (9 for SPLIT_BF16).
+ * Every shape gives the same result bit for bit.  Calls sharing a workspace
+ * must be ordered on one stream.
  */
 int pauli_decompose_batched(int count, const void* const* G, const int* N, void* const* out,
                             const pauli_opts* opts);
@@ -195,7 +198,7 @@ size_t pauli_batched_workspace_bytes(int count, const int* N, int algo);
 /* Number of persistent-kernel tile shapes for the uneven batch. */
 int pauli_batched_tile_count(void);
 
-/* 1 if batched tile shape `tile` can run `algo` (every shape runs every matrix-core algo). */
+/* 1 if batched tile shape `tile` can run `algo` (shape 7, 512 rows fused, runs SPLIT_FP16 only). */
 int pauli_batched_tile_valid(int algo, int tile);
 
 /*

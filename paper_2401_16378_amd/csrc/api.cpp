@@ -652,8 +652,8 @@ int tuned_btile(int planes, int count, const int* N) {
     load_tune_cache_locked();
     auto it = g_btile.find({planes, ns});
     // a cached shape that is out of range or not built for these planes (a
-    // hand-edited or stale file) falls back to shape 1, which every algo has
-    if (it == g_btile.end() || !batched_tile_valid(planes, it->second)) return 1;
+    // hand-edited or stale file) falls back to the default shape
+    if (it == g_btile.end() || !batched_tile_valid(planes, it->second)) return batched_default_tile(planes);
     return it->second;
 }
 
@@ -780,7 +780,7 @@ extern "C" int pauli_autotune_batched(int count, const void* const* G, const int
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    int best = 1;
+    int best = batched_default_tile(planes);
     float best_ms = 1e30f;
     for (int t = 1; t <= batched_tile_count() && e == hipSuccess; ++t) {
         if (!batched_tile_valid(planes, t)) continue;

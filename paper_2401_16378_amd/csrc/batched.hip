@@ -61,11 +61,15 @@ __global__ __launch_bounds__(256) void absmax_batched_kernel(const BatchItem* __
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
-// One workgroup per descriptor slot: the matrix's prescale exponent.
+// One workgroup per descriptor slot: the matrix's prescale exponent.  With
+// `counter` set (a fused contraction follows, with no pack kernel) the first
+// workgroup also clears the queue counters.
 __global__ __launch_bounds__(256) void prescale_batched_kernel(const BatchItem* __restrict__ items,
                                                                const float* __restrict__ partial,
-                                                               int* __restrict__ pe) {
+                                                               int* __restrict__ pe,
+                                                               unsigned int* __restrict__ counter) {
     __shared__ float red[4];
+    if (counter && blockIdx.x == 0 && threadIdx.x < MAX_QUEUES) counter[threadIdx.x] = 0u;
     const BatchItem it = items[blockIdx.x];
     const uint32_t tiles = pack_tiles(it.n);
     float m = 0.f;
@@ -396,6 +400,10 @@ hipError_t launch_contract_btile(int btile, const BatchItem* items, const uint32
 
 int batched_tile_count() { return NBTILES; }
 
+// Untuned shape: fused, registers for two workgroups per CU; the three-plane
+// split needs the 64-value chunks for its staging to fit twice in LDS.
+int batched_default_tile(int planes) { return planes == 3 ? 9 : 8; }
+
 bool batched_tile_valid(int planes, int btile) {
     if (btile < 1 || btile > NBTILES) return false;
     const BTile t = BTILES[btile - 1];
@@ -428,10 +436,12 @@ hipError_t launch_batched(int planes, int btile, const BatchItem* items_dev, con
         hipLaunchKernelGGL(absmax_batched_kernel, dim3(pack_total), dim3(256), 0, stream, items_dev, pack_slot_dev,
                            partial_dev);
         hipLaunchKernelGGL(prescale_batched_kernel, dim3(count), dim3(256), 0, stream, items_dev,
-                           (const float*)partial_dev, pe_dev);
+                           (const float*)partial_dev, pe_dev, fused ? counter_dev : nullptr);
     }
-    if (fused) {
+    if (fused && planes != 2) {
         hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(64), 0, stream, counter_dev);
+    } else if (fused) {
+        // the prescale kernel cleared the counters
     } else if (planes == 3) {
         hipLaunchKernelGGL((pack_batched_kernel<3>), dim3(pack_total), dim3(256), 0, stream, items_dev, pack_slot_dev,
                            packed, counter_dev, (const int*)nullptr);

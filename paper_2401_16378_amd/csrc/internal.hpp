@@ -53,6 +53,7 @@ struct BatchItem {
 };
 int batched_tile_count();
 bool batched_tile_valid(int planes, int btile);
+int batched_default_tile(int planes);
 uint32_t batched_output_tiles(int btile, int n);
 uint32_t batched_pack_tiles(int n);
 size_t batched_packed_bytes(int planes, int n);

@@ -308,7 +308,7 @@ def test_tune_cache_file_is_read(tmp_path):
     assert r.returncode == 0, r.stderr
     tile, btile, btile_fp32 = map(int, r.stdout.split())
     assert (tile, btile) == (3, 4)
-    assert btile_fp32 == 1                       # binary32 has no entry: the default shape
+    assert btile_fp32 == 8                       # binary32 has no entry: the default shape
 
 
 def test_tune_cache_invalid_tiles_fall_back(tmp_path):
@@ -338,7 +338,7 @@ def test_tune_cache_invalid_tiles_fall_back(tmp_path):
     assert r.returncode == 0, r.stderr
     t_bf16, t_fp32, b_bf16, b_fp32, b_one = map(int, r.stdout.split())
     assert t_bf16 == 1 and t_fp32 == 15          # the defaults at N=10
-    assert (b_bf16, b_fp32, b_one) == (1, 1, 1)
+    assert (b_bf16, b_fp32, b_one) == (9, 8, 9)   # the default shapes
 
 
 def test_noalloc_validation(lib, pauli):
