@@ -203,7 +203,11 @@ def _prep(t: torch.Tensor) -> torch.Tensor:
         raise ValueError("tensor must be on a GPU device")
     if t.dtype not in _DT:
         raise TypeError("tensor must be complex64 or complex128, got %s" % t.dtype)
-    return t.contiguous()
+    t = t.contiguous()
+    # The C ABI takes 16-byte aligned pointers only (the matrix-core paths
+    # read complex64 input in 16-byte pairs); a view starting at an odd
+    # complex64 element is copied into a fresh (aligned) allocation.
+    return t if t.data_ptr() % 16 == 0 else t.clone()
 
 
 def decompose(G: torch.Tensor, algo: str = "split_bf16", out_dtype=None, tile: int = 0) -> torch.Tensor:
