@@ -52,6 +52,7 @@ STRINGS_SOURCES = ["paper_2401_16378_amd/csrc/strings.hip", "paper_2401_16378_am
 STRINGS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_strings_n14.json")
 FWHT_SOURCES = ["paper_2401_16378_amd/csrc/fwht.hip", "paper_2401_16378_amd/csrc/common.hpp"]
 FWHT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwht_n14.json")
+FWHT_F32_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwht_f32_n14.json")
 HERM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hermitian_n14.json")
 
 
@@ -252,8 +253,10 @@ def bench_strings(a):
 
 
 def bench_fwht(a):
-    """All 4^N coefficients of the N=14 matrix by the binary64 fast
-    Walsh-Hadamard algorithm (not the paper's O(8^N) evaluation)."""
+    """All 4^N coefficients of the N=14 matrix by the fast Walsh-Hadamard
+    algorithm (not the paper's O(8^N) evaluation): `--algo fwht` (binary64
+    intermediate, the default here) or `--algo fwht_f32` (binary32
+    intermediate)."""
     import torch
     import paper_2401_16378_amd as pauli
     import workloads
@@ -265,33 +268,40 @@ def bench_fwht(a):
     out = torch.empty(1 << (2 * N), dtype=torch.complex64, device=dev)
     lib = pauli.load_library()
     stream = torch.cuda.current_stream(dev)
-    ws = pauli.workspace("fwht", N, 1, dev)
-    o = pauli._opts("fwht", 0, 0, 0, ctypes.c_void_p(stream.cuda_stream), ws)
+    algo = a.algo if a.algo in ("fwht", "fwht_f32") else "fwht"
+    narrow = algo == "fwht_f32"
+    ws = pauli.workspace(algo, N, 1, dev)
+    o = pauli._opts(algo, 0, 0, 0, ctypes.c_void_p(stream.cuda_stream), ws)
 
     def step():
         if lib.pauli_decompose(Gd.data_ptr(), N, 1, out.data_ptr(), ctypes.byref(o)) != 0:
             raise RuntimeError(pauli.last_error())
     ms = timed(step, a.steps, a.warmup, stream)
-    c128 = pauli.decompose(Gd, algo="fwht", out_dtype=torch.complex128)
+    c128 = pauli.decompose(Gd, algo=algo, out_dtype=torch.complex128)
     ref = pauli.decompose(Gd, algo="fp64_gray", out_dtype=torch.complex128)
     err = ((c128 - ref).abs().max() / ref.abs().max()).item()
+    err64 = ((out.to(torch.complex128) - ref).abs().max() / ref.abs().max()).item()
     # the method's own minimum: read G once, write the coefficients once
     alg_bytes = float(4 ** N) * (8 + 8)
     achieved = alg_bytes / (ms / 1e3) / 1e9
-    line = {"metric": "Pauli coeffs/sec at N=%d, binary64 fast Walsh-Hadamard (not the paper's O(8^N) method)" % N,
+    ub = 8 if narrow else 16
+    line = {"metric": "Pauli coeffs/sec at N=%d, %s fast Walsh-Hadamard (not the paper's O(8^N) method)"
+                      % (N, "binary32-intermediate" if narrow else "binary64"),
             "value": 4 ** N / (ms / 1e3), "unit": "coeffs/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
             "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
             "config": {"workload": "dense Pauli decomposition, N=%d (%dx%d complex64 Hermitian, seed %d), all 4^%d "
-                                   "coefficients, algo fwht (two binary64 passes through a 16 B/element "
-                                   "intermediate)" % (N, 1 << N, 1 << N, workloads.SEED_N14, N), "N": N, "algo": "fwht"},
+                                   "coefficients, algo %s (two passes through a %d B/element %s intermediate)"
+                                   % (N, 1 << N, 1 << N, workloads.SEED_N14, N, algo, ub,
+                                      "binary32" if narrow else "binary64"), "N": N, "algo": algo},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": measured_traffic(FWHT_TRAFFIC_FILE, FWHT_SOURCES) if N == 14 else None,
+                         "traffic": measured_traffic(FWHT_F32_TRAFFIC_FILE if narrow else FWHT_TRAFFIC_FILE,
+                                                     FWHT_SOURCES) if N == 14 else None,
                          "note": "achieved counts 16 B per element (G read once, coefficients written once); the "
-                                 "two-pass design also writes and reads a 16 B/element intermediate, and traffic "
-                                 "is the measured HBM bytes of both passes of one decomposition"},
-            "max_err_vs_fp64_gray": err}
+                                 "two-pass design also writes and reads a %d B/element intermediate, and traffic "
+                                 "is the measured HBM bytes of both passes of one decomposition" % ub},
+            "max_err_vs_fp64_gray": err, "max_err_complex64_out": err64}
     if not a.no_cpu:
         line["cpu_baseline"], line["max_err_vs_oracle_sample"] = cpu_baseline(
             G.astype(np.complex128), c128.cpu().numpy(), min(a.cpu_sample, 65536))
@@ -321,7 +331,7 @@ def bench_table(a):
         esz = 16 if Gd.dtype == torch.complex128 else 8
         ref = pauli.decompose(Gd, algo="fp64_gray", out_dtype=torch.complex128)
         mref = ref.abs().max().item()
-        for algo in ("split_fp16", "split_bf16", "fp32", "fwht", "fp64_gray"):
+        for algo in ("split_fp16", "split_bf16", "fp32", "fwht", "fwht_f32", "fp64_gray"):
             steps = a.steps if not (algo in ("fp64_gray", "fp32") and N == 14) else 3
             out = pauli.decompose(Gd, algo=algo)
             err = ((out.to(torch.complex128) - ref).abs().max().item()) / mref

@@ -90,7 +90,18 @@ typedef enum pauli_algo {
      * recombined in binary64 (hi + 2^-11 lo) with 2^-pe folded into the
      * output scale.  Two thirds of SPLIT_BF16's matrix-core work; finite
      * inputs only (an infinite or NaN component gives unspecified output). */
-    PAULI_ALGO_SPLIT_FP16 = 4
+    PAULI_ALGO_SPLIT_FP16 = 4,
+    /* FWHT with a binary32 intermediate (8 bytes per matrix element of
+     * workspace, N >= 9): every butterfly still adds in binary64, but the
+     * partial transforms between the two passes are rounded to binary32
+     * (once more after each extra top pass at N = 15, 16), so each
+     * coefficient c(x, 32 z_h + z_l) is off by at most 2^-24 times the
+     * 2-norm of the 2^(N-5) coefficients c(x, 32 k + z_l), k < 2^(N-5), per
+     * rounding (plus the output's own rounding): at most 2^-24 2^((N-5)/2)
+     * max|c|; 2.6e-8 of max|c| measured at N = 14.  Up to N = 8
+     * it is the binary64 one-kernel path.  Same directions and range as
+     * PAULI_ALGO_FWHT. */
+    PAULI_ALGO_FWHT_F32 = 5
 } pauli_algo;
 
 typedef struct pauli_opts {

@@ -50,8 +50,11 @@ size_t elem_bytes(int dtype) { return dtype == PAULI_C128 ? 16 : 8; }
 bool valid_dtype(int d) { return d == PAULI_C64 || d == PAULI_C128; }
 bool valid_algo(int a) {
     return a == PAULI_ALGO_FP64_GRAY || a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16 || a == PAULI_ALGO_FWHT ||
-           a == PAULI_ALGO_SPLIT_FP16;
+           a == PAULI_ALGO_SPLIT_FP16 || a == PAULI_ALGO_FWHT_F32;
 }
+
+// Fast Walsh-Hadamard algorithms (binary64 or binary32 intermediate).
+bool is_fwht(int a) { return a == PAULI_ALGO_FWHT || a == PAULI_ALGO_FWHT_F32; }
 
 // Matrix-core algorithms (packed operand, tile shapes, separate passes).
 bool is_mfma(int a) { return a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16 || a == PAULI_ALGO_SPLIT_FP16; }
@@ -160,7 +163,7 @@ int check_common(const void* in, int N, int batch, const void* out, const pauli_
     if (overlaps(in, count * elem_bytes(o.in_dtype), out, count * elem_bytes(o.out_dtype)))
         return fail(PAULI_EINVAL, "%s: input and output overlap", fn);
     if (o.tile < 0) return fail(PAULI_EINVAL, "%s: tile=%d must be >= 0", fn, o.tile);
-    if (o.algo == PAULI_ALGO_FWHT && !fwht_supported(N))
+    if (is_fwht(o.algo) && !fwht_supported(N))
         return fail(PAULI_EUNSUPPORTED, "%s: the FWHT algorithm covers %d <= N <= %d, not N=%d", fn, FWHT_N_MIN,
                     FWHT_N_MAX, N);
     if (o.workspace && o.algo != PAULI_ALGO_FP64_GRAY) {
@@ -227,21 +230,22 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
     const bool in128 = o.in_dtype == PAULI_C128, out128 = o.out_dtype == PAULI_C128;
     if (o.algo == PAULI_ALGO_FP64_GRAY) {
         e = launch_gray(dir, in, in128, out, out128, N, batch, scale, s);
-    } else if (o.algo == PAULI_ALGO_FWHT) {
-        const size_t need = fwht_workspace_bytes(N, batch);
+    } else if (is_fwht(o.algo)) {
+        const bool narrow = o.algo == PAULI_ALGO_FWHT_F32;
+        const size_t need = fwht_workspace_bytes(N, batch, narrow);
         void* ws = o.workspace;
         if (need == 0) {
-            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, nullptr, s);
+            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, narrow, nullptr, s);
         } else if (ws) {
             if (o.workspace_bytes < need)
                 return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
                             o.workspace_bytes);
-            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, ws, s);
+            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, narrow, ws, s);
         } else {
             hipMemPool_t pool;
             if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
             if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
-            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, ws, s);
+            e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, narrow, ws, s);
             const hipError_t ef = hipFreeAsync(ws, s);
             if (e == hipSuccess) e = ef;
         }
@@ -331,7 +335,7 @@ int pauli_decompose_noalloc(const void* G, int N, int batch, void* out, const pa
     int st = check_common(G, N, batch, out, o, fn);
     if (st != PAULI_OK) return st;
     size_t need = 0;
-    if (o.algo == PAULI_ALGO_FWHT) need = fwht_workspace_bytes(N, batch);
+    if (is_fwht(o.algo)) need = fwht_workspace_bytes(N, batch, o.algo == PAULI_ALGO_FWHT_F32);
     else if (is_mfma(o.algo)) need = mfma_workspace_bytes(planes_of(o.algo), N, batch);
     if (need > NOALLOC_SCRATCH_BYTES)
         return fail(PAULI_ENOMEM, "%s: algo %d at N=%d, batch %d needs %zu bytes of scratch; the fixed scratch holds %zu",
@@ -446,19 +450,19 @@ int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts
 size_t pauli_workspace_bytes(int algo, int N, int batch) {
     if (!valid_algo(algo) || N < 0 || N > N_MAX || batch < 1) return 0;
     if (algo == PAULI_ALGO_FP64_GRAY) return 0;
-    if (algo == PAULI_ALGO_FWHT) return fwht_supported(N) ? fwht_workspace_bytes(N, batch) : 0;
+    if (is_fwht(algo)) return fwht_supported(N) ? fwht_workspace_bytes(N, batch, algo == PAULI_ALGO_FWHT_F32) : 0;
     return mfma_workspace_bytes(planes_of(algo), N, batch);
 }
 
 int pauli_tile_count(int algo) {
-    if (algo == PAULI_ALGO_FP64_GRAY || algo == PAULI_ALGO_FWHT) return 1;
+    if (algo == PAULI_ALGO_FP64_GRAY || is_fwht(algo)) return 1;
     if (!valid_algo(algo)) return 0;
     return mfma_tile_count(planes_of(algo));
 }
 
 int pauli_tile_valid(int algo, int tile, int N) {
     if (algo == PAULI_ALGO_FP64_GRAY) return tile == 1 && N >= 0 && N <= N_MAX ? 1 : 0;
-    if (algo == PAULI_ALGO_FWHT) return tile == 1 && fwht_supported(N) ? 1 : 0;
+    if (is_fwht(algo)) return tile == 1 && fwht_supported(N) ? 1 : 0;
     if (!valid_algo(algo) || N < 0 || N > N_MAX) return 0;
     return mfma_tile_valid(planes_of(algo), tile, N) ? 1 : 0;
 }

@@ -31,7 +31,20 @@
 // over k in the thread and over lanes q ^ 1, 2, ..., TPV / 2.  For each z_h the 16 results are
 // the 16 consecutive coefficients n with fixed high bits (n's low four bits
 // are (x^z)_0, z_0, (x^z)_1, z_1), so they are staged in LDS and stored as one
-// contiguous 128-byte (complex64) or 256-byte (complex128) run.
+// contiguous 128-byte (complex64) or 256-byte (complex128) run.  For vectors
+// of 512 (N >= 14) lane exchanges would dominate, so that pass runs 4 bits in
+// the thread, one bit between lane pairs and, after a transpose through LDS,
+// the last 4 bits in the thread again.
+//
+// Butterflies across lanes use DPP moves (partners 1 and 2 lanes apart, and 8
+// within a row of 16) or ds_swizzle (4 and 16 apart), with the sum or the
+// difference picked by one fma with a +-1 factor: the same rounding as an add
+// or a subtract.
+//
+// The intermediate is binary64 (PAULI_ALGO_FWHT) or binary32
+// (PAULI_ALGO_FWHT_F32: half the bytes; U is rounded once to binary32 after
+// pass 1, and once more after each extra top pass at N = 15, 16, while every
+// sum is still formed in binary64).
 #include <type_traits>
 
 #include "common.hpp"
@@ -48,15 +61,63 @@ typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 __device__ inline double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 sub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-__device__ inline double2 shfl_xor2(double2 v, int m) {
-    return make_double2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+// Value of lane ^ M (M < 32): DPP quad permutations for 1 and 2, a rotation
+// by 8 within the row of 16 for 8, ds_swizzle (xor mode, 32-lane groups) for
+// 4 and 16.
+template <int M>
+__device__ inline int lane_xor(int v) {
+    static_assert(M == 1 || M == 2 || M == 4 || M == 8 || M == 16, "lane distance");
+    if constexpr (M == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    else if constexpr (M == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    else if constexpr (M == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror 8
+    else return __builtin_amdgcn_ds_swizzle(v, 0x1F | (M << 10));
 }
 
-// Butterfly across lanes on index bit owned by lane mask m: the lane whose
-// m-bit is clear keeps a + b, its partner keeps a - b.
-__device__ inline double2 lane_butterfly(double2 v, int lane, int m) {
-    const double2 p = shfl_xor2(v, m);
-    return (lane & m) ? sub2(p, v) : add2(v, p);
+template <int M>
+__device__ inline double lane_xor_f64(double v) {
+    return __hiloint2double(lane_xor<M>(__double2hiint(v)), lane_xor<M>(__double2loint(v)));
+}
+
+// Butterfly across lanes on the index bit owned by lane bit M: the lane whose
+// M-bit is clear keeps a + b, its partner keeps a - b.
+template <int M>
+__device__ inline double2 lane_butterfly(double2 v, int lane) {
+    const double sg = (lane & M) ? -1.0 : 1.0;
+    const double px = lane_xor_f64<M>(v.x), py = lane_xor_f64<M>(v.y);
+    return make_double2(__fma_rn(sg, v.x, px), __fma_rn(sg, v.y, py));
+}
+
+// The butterflies over lane bits 1 .. TPV / 2 of every value a thread holds.
+template <int TPV, int EPT>
+__device__ inline void lane_stages(double2 (&v)[EPT], int lane) {
+    if constexpr (TPV > 1) {
+        lane_stages<TPV / 2, EPT>(v, lane);
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) v[k] = lane_butterfly<TPV / 2>(v[k], lane);
+    }
+}
+
+// In-thread butterflies over all log2(EPT) bits of k.
+template <int EPT>
+__device__ inline void thread_stages(double2 (&v)[EPT]) {
+#pragma unroll
+    for (int s = 1; s < EPT; s <<= 1)
+#pragma unroll
+        for (int k = 0; k < EPT; ++k)
+            if ((k & s) == 0) {
+                const double2 p = v[k], r = v[k + s];
+                v[k] = add2(p, r);
+                v[k + s] = sub2(p, r);
+            }
+}
+
+// The intermediate U (or W): binary64 or binary32 pairs, summed in binary64.
+__device__ inline void put_u(double2* p, double2 v) { *p = v; }
+__device__ inline void put_u(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+__device__ inline double2 get_u(const double2* p) { return *p; }
+__device__ inline double2 get_u(const float2* p) {
+    const float2 f = *p;
+    return make_double2((double)f.x, (double)f.y);
 }
 
 template <bool IN128>
@@ -69,8 +130,8 @@ __device__ inline double2 load_g(const void* G, size_t idx) {
     }
 }
 
-template <bool IN128>
-__global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall, double2* __restrict__ Uall, int N) {
+template <bool IN128, typename UT>
+__global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall, UT* __restrict__ Uall, int N) {
     using InT = typename std::conditional<IN128, double2, float2>::type;
     constexpr int PF = IN128 ? 4 : 8;    // tiles whose loads are issued together (32 or 64 KiB per workgroup)
     __shared__ double2 tile[32 * 33];    // [row][column], padded row
@@ -78,7 +139,7 @@ __global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall,
     const uint32_t x0 = blockIdx.y * 32u, h0 = blockIdx.x * HB;
     const size_t mat = (size_t)D * D;
     const InT* G = (const InT*)Gall + (size_t)blockIdx.z * mat;
-    double2* U = Uall + (size_t)blockIdx.z * mat;
+    UT* U = Uall + (size_t)blockIdx.z * mat;
     const int t = threadIdx.x, lane = t & 63;
     const int lr = t >> 3, lc = (t & 7) * 4;       // load: row, first column of 4
     const int xl = t >> 3, il0 = (t & 7) * 4;      // transform: flip mask, first i_l of 4
@@ -120,10 +181,7 @@ __global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall,
                 v[3] = sub2(a1, a3);
             }
             // i_l bits 2, 3, 4: lanes t ^ 1, t ^ 2, t ^ 4
-#pragma unroll
-            for (int m = 1; m <= 4; m <<= 1)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) v[k] = lane_butterfly(v[k], lane, m);
+            lane_stages<8, 4>(v, lane);
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[k][h1 + h] = v[k];
         }
@@ -132,22 +190,41 @@ __global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall,
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t zl = il0 + k;
-        double2* dst = U + (((size_t)(x0 + xl) * (M / HB) + blockIdx.x) * 32u + zl) * HB;
+        UT* dst = U + (((size_t)(x0 + xl) * (M / HB) + blockIdx.x) * 32u + zl) * HB;
 #pragma unroll
-        for (int h = 0; h < HB; ++h) dst[h] = acc[k][h];
+        for (int h = 0; h < HB; ++h) put_u(dst + h, acc[k][h]);
     }
 }
 
-// TPV threads per vector (16, 32 or 64), EPT elements per thread: the
+// TPV threads per vector (16 or 32), EPT elements per thread: the
 // workgroup transforms ML = TPV EPT values of i_h per vector (all 2^(N-5)
 // of them up to N = 14; above, each of the 2^(N-14) blocks of 512 whose top
 // bits fwht_top has already transformed, selected by blockIdx.x >> 6); the
 // workgroup has 16 TPV threads.
+//
+// ML < 512: thread q holds i_h = q + TPV k; butterflies over k in the thread,
+// then over lanes q ^ 1, ..., TPV / 2.
+// ML = 512 (TPV = 32, EPT = 16): thread q first holds i_h = (q >> 1) +
+// 16 (q & 1) + 32 k: bits 5..8 (k) in the thread, bit 4 between lanes q and
+// q ^ 1; an LDS transpose (real parts, then imaginary parts, rows padded by
+// one double per 16) then gives it i_h = 16 (q & 1) + 32 (q >> 1) + j for
+// bits 0..3 (j) in the thread.
+constexpr uint32_t TR_PITCH = 512 + 32;   // doubles per vector row of the transpose
+
 template <int TPV, int EPT, bool OUT128>
-__global__ __launch_bounds__(16 * TPV) void fwht_pass2(const double2* __restrict__ Uall, void* __restrict__ outall,
+constexpr size_t pass2_lds_bytes() {
+    const size_t stage = (size_t)TPV * EPT * 16u * (OUT128 ? 16u : 8u);
+    const size_t tr = TPV * EPT == 512 ? 16u * TR_PITCH * 8u : 0u;
+    return stage > tr ? stage : tr;
+}
+
+template <int TPV, int EPT, bool OUT128, typename UT>
+__global__ __launch_bounds__(16 * TPV) void fwht_pass2(const UT* __restrict__ Uall, void* __restrict__ outall,
                                                        int N, double scale) {
     extern __shared__ __attribute__((aligned(16))) unsigned char stage[];   // [z_h][16] coefficients
     constexpr uint32_t ML = (uint32_t)TPV * EPT;
+    constexpr bool TRANSPOSE = ML == 512;
+    static_assert(!TRANSPOSE || (TPV == 32 && EPT == 16), "transposing shape");
     constexpr int ESZ = OUT128 ? 16 : 8;
     constexpr uint32_t NT = 16u * TPV;
     const uint32_t D = 1u << N, M = D >> 5;
@@ -155,42 +232,57 @@ __global__ __launch_bounds__(16 * TPV) void fwht_pass2(const double2* __restrict
     const uint32_t x0 = blockIdx.y * 32u;
     const uint32_t a = blockIdx.x & 7u, b = (blockIdx.x >> 3) & 7u;   // x_l quad, z_l quad
     const uint32_t h0 = (blockIdx.x >> 6) * ML;                       // first i_h (and z_h) of this block
-    const double2* U = Uall + (size_t)blockIdx.z * mat;
+    const UT* U = Uall + (size_t)blockIdx.z * mat;
     unsigned char* out = (unsigned char*)outall + (size_t)blockIdx.z * mat * ESZ;
     const int t = threadIdx.x, lane = t & 63;
     const int vec = t / TPV, q = t % TPV;
     const uint32_t xl = 4u * a + (uint32_t)(vec & 3), zl = 4u * b + (uint32_t)(vec >> 2);
     const uint32_t x = x0 + xl;
+    // i_h (relative to h0) of value k in the thread: before (first) and after (second) the transform
+    const uint32_t q0 = TRANSPOSE ? ((uint32_t)q >> 1) + 16u * ((uint32_t)q & 1u) : (uint32_t)q;
+    const uint32_t jb = 16u * ((uint32_t)q & 1u) + 32u * ((uint32_t)q >> 1);
 
     double2 v[EPT];
-    const double2* src = U + (size_t)x * 32u * M + zl * HB;
+    const UT* src = U + (size_t)x * 32u * M + zl * HB;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const uint32_t ih = h0 + (uint32_t)q + (uint32_t)TPV * k;
-        v[k] = src[(size_t)(ih / HB) * 32u * HB + ih % HB];
+        const uint32_t ih = h0 + q0 + (uint32_t)TPV * k;
+        v[k] = get_u(src + (size_t)(ih / HB) * 32u * HB + ih % HB);
     }
-
-    // high i_h bits: over k inside the thread
+    thread_stages<EPT>(v);   // high i_h bits: over k inside the thread
+    if constexpr (TRANSPOSE) {
+        // bit 4: lane pairs
 #pragma unroll
-    for (int s = 1; s < EPT; s <<= 1)
+        for (int k = 0; k < EPT; ++k) v[k] = lane_butterfly<1>(v[k], lane);
+        double* row = (double*)stage + (uint32_t)vec * TR_PITCH;
 #pragma unroll
-        for (int k = 0; k < EPT; ++k)
-            if ((k & s) == 0) {
-                const double2 p = v[k], r = v[k + s];
-                v[k] = add2(p, r);
-                v[k + s] = sub2(p, r);
+        for (int part = 0; part < 2; ++part) {
+            if (part) __syncthreads();            // real parts read back before the imaginary ones land
+#pragma unroll
+            for (int k = 0; k < EPT; ++k) {
+                const uint32_t ih = q0 + 32u * k;
+                row[ih + (ih >> 4)] = part ? v[k].y : v[k].x;
             }
-    // low i_h bits: lanes q ^ 1, 2, ..., TPV / 2 (a vector's threads are consecutive lanes of one wave)
+            __syncthreads();
 #pragma unroll
-    for (int m = 1; m < TPV; m <<= 1)
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) v[k] = lane_butterfly(v[k], lane, m);
+            for (int j = 0; j < EPT; ++j) {
+                const uint32_t ih = jb + j;
+                if (part) v[j].y = row[ih + (ih >> 4)];
+                else v[j].x = row[ih + (ih >> 4)];
+            }
+        }
+        thread_stages<EPT>(v);   // bits 0..3
+        __syncthreads();          // transpose reads done before the stage reuses the LDS
+    } else {
+        // low i_h bits: lanes q ^ 1, 2, ..., TPV / 2 (a vector's threads are consecutive lanes of one wave)
+        lane_stages<TPV, EPT>(v, lane);
+    }
 
     // phase, scale, stage: slot = (x^z)_0 | z_0 << 1 | (x^z)_1 << 2 | z_1 << 3
     const uint32_t slot = ((xl ^ zl) & 1u) | ((zl & 1u) << 1) | (((xl ^ zl) & 2u) << 1) | ((zl & 2u) << 2);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const uint32_t zh = (uint32_t)q + (uint32_t)TPV * k;      // row of the stage
+        const uint32_t zh = TRANSPOSE ? jb + (uint32_t)k : (uint32_t)q + (uint32_t)TPV * k;   // row of the stage
         const uint32_t z = ((h0 + zh) << 5) + zl;
         double re = v[k].x * scale, im = v[k].y * scale;
         rotate_minus_i(re, im, (uint32_t)__popc(x & z));
@@ -214,9 +306,8 @@ __global__ __launch_bounds__(16 * TPV) void fwht_pass2(const double2* __restrict
 // read into LDS, phased by i^{popc(x&z)}, transformed over z_h (H is
 // symmetric, so the same butterflies map z_h to i_h) and stored as
 // W(x, z_l, i_h) in U's blocked layout.
-template <int TPV, int EPT, bool IN128>
-__global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ inall, double2* __restrict__ Wall,
-                                                       int N) {
+template <int TPV, int EPT, bool IN128, typename UT>
+__global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ inall, UT* __restrict__ Wall, int N) {
     extern __shared__ __attribute__((aligned(16))) unsigned char stage[];   // [z_h][16] coefficients
     constexpr uint32_t ML = (uint32_t)TPV * EPT;
     constexpr int ESZ = IN128 ? 16 : 8;
@@ -227,7 +318,7 @@ __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ 
     const uint32_t a = blockIdx.x & 7u, b = (blockIdx.x >> 3) & 7u;
     const uint32_t h0 = (blockIdx.x >> 6) * ML;
     const unsigned char* in = (const unsigned char*)inall + (size_t)blockIdx.z * mat * ESZ;
-    double2* W = Wall + (size_t)blockIdx.z * mat;
+    UT* W = Wall + (size_t)blockIdx.z * mat;
     const int t = threadIdx.x, lane = t & 63;
     const int vec = t / TPV, q = t % TPV;
     const uint32_t xl = 4u * a + (uint32_t)(vec & 3), zl = 4u * b + (uint32_t)(vec >> 2);
@@ -261,24 +352,13 @@ __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ 
         rotate_minus_i(re, im, 3u * (uint32_t)__popc(x & z));   // i^{popc(x&z)}
         v[k] = make_double2(re, im);
     }
-#pragma unroll
-    for (int s = 1; s < EPT; s <<= 1)
-#pragma unroll
-        for (int k = 0; k < EPT; ++k)
-            if ((k & s) == 0) {
-                const double2 p = v[k], r = v[k + s];
-                v[k] = add2(p, r);
-                v[k + s] = sub2(p, r);
-            }
-#pragma unroll
-    for (int m = 1; m < TPV; m <<= 1)
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) v[k] = lane_butterfly(v[k], lane, m);
-    double2* dst = W + (size_t)x * 32u * M + zl * HB;
+    thread_stages<EPT>(v);
+    lane_stages<TPV, EPT>(v, lane);
+    UT* dst = W + (size_t)x * 32u * M + zl * HB;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
         const uint32_t ih = h0 + (uint32_t)q + (uint32_t)TPV * k;
-        dst[(size_t)(ih / HB) * 32u * HB + ih % HB] = v[k];
+        put_u(dst + (size_t)(ih / HB) * 32u * HB + ih % HB, v[k]);
     }
 }
 
@@ -287,14 +367,14 @@ __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ 
 // which an LDS tile turns back into the 32 x 32 block of G at rows
 // (32 i_h ^ x0) .. +31, columns 32 i_h .. +31 (entry (r, c) holds x_l = r ^ c,
 // i_l = c), written row by row.
-template <bool OUT128>
-__global__ __launch_bounds__(256) void fwht_adj_b(const double2* __restrict__ Wall, void* __restrict__ Gall, int N,
+template <bool OUT128, typename UT>
+__global__ __launch_bounds__(256) void fwht_adj_b(const UT* __restrict__ Wall, void* __restrict__ Gall, int N,
                                                   double scale) {
     __shared__ double2 tile[32 * 33];
     const uint32_t D = 1u << N, M = D >> 5;
     const uint32_t x0 = blockIdx.y * 32u, h0 = blockIdx.x * HB;
     const size_t mat = (size_t)D * D;
-    const double2* W = Wall + (size_t)blockIdx.z * mat;
+    const UT* W = Wall + (size_t)blockIdx.z * mat;
     unsigned char* G = (unsigned char*)Gall + (size_t)blockIdx.z * mat * (OUT128 ? 16 : 8);
     const int t = threadIdx.x, lane = t & 63;
     const int xl = t >> 3, zl0 = (t & 7) * 4;      // transform: flip mask, first z_l of 4
@@ -303,9 +383,9 @@ __global__ __launch_bounds__(256) void fwht_adj_b(const double2* __restrict__ Wa
     double2 w[4][HB];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double2* src = W + (((size_t)(x0 + xl) * (M / HB) + blockIdx.x) * 32u + zl0 + k) * HB;
+        const UT* src = W + (((size_t)(x0 + xl) * (M / HB) + blockIdx.x) * 32u + zl0 + k) * HB;
 #pragma unroll
-        for (int h = 0; h < HB; ++h) w[k][h] = src[h];
+        for (int h = 0; h < HB; ++h) w[k][h] = get_u(src + h);
     }
 #pragma unroll
     for (int h = 0; h < HB; ++h) {
@@ -318,10 +398,7 @@ __global__ __launch_bounds__(256) void fwht_adj_b(const double2* __restrict__ Wa
             v[1] = add2(a1, a3);
             v[3] = sub2(a1, a3);
         }
-#pragma unroll
-        for (int m = 1; m <= 4; m <<= 1)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = lane_butterfly(v[k], lane, m);
+        lane_stages<8, 4>(v, lane);
         if (h > 0) __syncthreads();              // previous tile fully written out
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -340,44 +417,44 @@ __global__ __launch_bounds__(256) void fwht_adj_b(const double2* __restrict__ Wa
     }
 }
 
-template <int TPV, int EPT>
-hipError_t launch_adj_a(const void* in, bool in128, double2* W, int N, int batch, uint32_t nxb,
-                        hipStream_t s) {
+template <int TPV, int EPT, typename UT>
+hipError_t launch_adj_a(const void* in, bool in128, UT* W, int N, int batch, uint32_t nxb, hipStream_t s) {
     const uint32_t ntop = ((1u << N) >> 5) / (uint32_t)(TPV * EPT);
     const dim3 grid(64u * ntop, nxb, (uint32_t)batch);
     const size_t lds = (size_t)TPV * EPT * 16u * (in128 ? 16u : 8u);
     hipError_t e;
     if (in128) {
-        e = hipFuncSetAttribute((const void*)fwht_adj_a<TPV, EPT, true>,
+        e = hipFuncSetAttribute((const void*)fwht_adj_a<TPV, EPT, true, UT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fwht_adj_a<TPV, EPT, true>), grid, dim3(16 * TPV), lds, s, in, W, N);
+        hipLaunchKernelGGL((fwht_adj_a<TPV, EPT, true, UT>), grid, dim3(16 * TPV), lds, s, in, W, N);
     } else {
-        e = hipFuncSetAttribute((const void*)fwht_adj_a<TPV, EPT, false>,
+        e = hipFuncSetAttribute((const void*)fwht_adj_a<TPV, EPT, false, UT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fwht_adj_a<TPV, EPT, false>), grid, dim3(16 * TPV), lds, s, in, W, N);
+        hipLaunchKernelGGL((fwht_adj_a<TPV, EPT, false, UT>), grid, dim3(16 * TPV), lds, s, in, W, N);
     }
     return hipGetLastError();
 }
 
-template <int TPV, int EPT>
-hipError_t launch_pass2(const double2* U, void* out, bool out128, int N, int batch, double scale, uint32_t nxb,
+template <int TPV, int EPT, typename UT>
+hipError_t launch_pass2(const UT* U, void* out, bool out128, int N, int batch, double scale, uint32_t nxb,
                         hipStream_t s) {
     const uint32_t ntop = ((1u << N) >> 5) / (uint32_t)(TPV * EPT);
     const dim3 grid(64u * ntop, nxb, (uint32_t)batch);   // the 64 quads of a mask block back to back
-    const size_t lds = (size_t)TPV * EPT * 16u * (out128 ? 16u : 8u);
     hipError_t e;
     if (out128) {
-        e = hipFuncSetAttribute((const void*)fwht_pass2<TPV, EPT, true>,
+        constexpr size_t lds = pass2_lds_bytes<TPV, EPT, true>();
+        e = hipFuncSetAttribute((const void*)fwht_pass2<TPV, EPT, true, UT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fwht_pass2<TPV, EPT, true>), grid, dim3(16 * TPV), lds, s, U, out, N, scale);
+        hipLaunchKernelGGL((fwht_pass2<TPV, EPT, true, UT>), grid, dim3(16 * TPV), lds, s, U, out, N, scale);
     } else {
-        e = hipFuncSetAttribute((const void*)fwht_pass2<TPV, EPT, false>,
+        constexpr size_t lds = pass2_lds_bytes<TPV, EPT, false>();
+        e = hipFuncSetAttribute((const void*)fwht_pass2<TPV, EPT, false, UT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fwht_pass2<TPV, EPT, false>), grid, dim3(16 * TPV), lds, s, U, out, N, scale);
+        hipLaunchKernelGGL((fwht_pass2<TPV, EPT, false, UT>), grid, dim3(16 * TPV), lds, s, U, out, N, scale);
     }
     return hipGetLastError();
 }
@@ -388,36 +465,29 @@ hipError_t launch_pass2(const double2* U, void* out, bool out128, int N, int bat
 // of an element lie D / 2^T apart; each thread does one 2^T-point
 // butterfly in place (a pure streaming pass).  Pass 2 (or adjoint pass A)
 // then handles the remaining 9 bits of each sub-block.
-template <int T>
-__global__ __launch_bounds__(256) void fwht_top(double2* __restrict__ Uall, int N) {
+template <int T, typename UT>
+__global__ __launch_bounds__(256) void fwht_top(UT* __restrict__ Uall, int N) {
     const uint32_t D = 1u << N;
     const size_t mat = (size_t)D * D;
-    double2* U = Uall + (size_t)blockIdx.y * mat;
+    UT* U = Uall + (size_t)blockIdx.y * mat;
     const uint32_t lgS = (uint32_t)N - T;                  // sub-block length 2^lgS
     const size_t S = (size_t)1 << lgS, total = (size_t)D << lgS;
     for (size_t f = (size_t)blockIdx.x * 256u + threadIdx.x; f < total; f += (size_t)gridDim.x * 256u) {
-        double2* p = U + ((f >> lgS) << N) + (f & (S - 1));
+        UT* p = U + ((f >> lgS) << N) + (f & (S - 1));
         double2 v[1 << T];
 #pragma unroll
-        for (int k = 0; k < (1 << T); ++k) v[k] = p[(size_t)k << lgS];
+        for (int k = 0; k < (1 << T); ++k) v[k] = get_u(p + ((size_t)k << lgS));
+        thread_stages<(1 << T)>(v);
 #pragma unroll
-        for (int m = 1; m < (1 << T); m <<= 1)
-#pragma unroll
-            for (int k = 0; k < (1 << T); ++k)
-                if ((k & m) == 0) {
-                    const double2 a = v[k], b = v[k + m];
-                    v[k] = add2(a, b);
-                    v[k + m] = sub2(a, b);
-                }
-#pragma unroll
-        for (int k = 0; k < (1 << T); ++k) p[(size_t)k << lgS] = v[k];
+        for (int k = 0; k < (1 << T); ++k) put_u(p + ((size_t)k << lgS), v[k]);
     }
 }
 
-hipError_t launch_top(double2* U, int N, int batch, hipStream_t s) {
+template <typename UT>
+hipError_t launch_top(UT* U, int N, int batch, hipStream_t s) {
     const dim3 grid(8192u, (uint32_t)batch);
-    if (N == 15) hipLaunchKernelGGL(fwht_top<1>, grid, dim3(256), 0, s, U, N);
-    else if (N == 16) hipLaunchKernelGGL(fwht_top<2>, grid, dim3(256), 0, s, U, N);
+    if (N == 15) hipLaunchKernelGGL((fwht_top<1, UT>), grid, dim3(256), 0, s, U, N);
+    else if (N == 16) hipLaunchKernelGGL((fwht_top<2, UT>), grid, dim3(256), 0, s, U, N);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -527,30 +597,16 @@ hipError_t launch_small(Dir dir, const void* in, void* out, int N, int batch, do
     return hipGetLastError();
 }
 
-}  // namespace
-
-bool fwht_supported(int N) { return N >= FWHT_N_MIN && N <= FWHT_N_MAX; }
-
-size_t fwht_workspace_bytes(int N, int batch) {
-    return N <= FWHT_SMALL_N_MAX ? 0 : ((size_t)1 << (2 * N)) * 16u * (size_t)batch;
-}
-
-hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N, int batch,
-                       double scale, void* ws, hipStream_t s) {
-    if (!fwht_supported(N)) return hipErrorInvalidValue;
-    if (N <= FWHT_SMALL_N_MAX) {
-        if (in_c128) return out_c128 ? launch_small<true, true>(dir, in, out, N, batch, scale, s)
-                                     : launch_small<true, false>(dir, in, out, N, batch, scale, s);
-        return out_c128 ? launch_small<false, true>(dir, in, out, N, batch, scale, s)
-                        : launch_small<false, false>(dir, in, out, N, batch, scale, s);
-    }
+// The two-pass path with intermediate U of type UT (double2 or float2).
+template <typename UT>
+hipError_t launch_two_pass(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N, int batch,
+                           double scale, UT* U, hipStream_t s) {
     const uint32_t D = 1u << N, M = D >> 5, nxb = D / 32u;
-    double2* U = (double2*)ws;
     const dim3 gt(M / HB, nxb, (uint32_t)batch);   // consecutive i_h groups back to back
     hipError_t e = hipSuccess;
     if (dir == FORWARD) {
-        if (in_c128) hipLaunchKernelGGL(fwht_pass1<true>, gt, dim3(256), 0, s, in, U, N);
-        else hipLaunchKernelGGL(fwht_pass1<false>, gt, dim3(256), 0, s, in, U, N);
+        if (in_c128) hipLaunchKernelGGL((fwht_pass1<true, UT>), gt, dim3(256), 0, s, in, U, N);
+        else hipLaunchKernelGGL((fwht_pass1<false, UT>), gt, dim3(256), 0, s, in, U, N);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         switch (N) {   // (threads per vector, elements per thread)
             case 9: return launch_pass2<16, 1>(U, out, out_c128, N, batch, scale, nxb, s);
@@ -581,9 +637,30 @@ hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool ou
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    if (out_c128) hipLaunchKernelGGL(fwht_adj_b<true>, gt, dim3(256), 0, s, U, out, N, scale);
-    else hipLaunchKernelGGL(fwht_adj_b<false>, gt, dim3(256), 0, s, U, out, N, scale);
+    if (out_c128) hipLaunchKernelGGL((fwht_adj_b<true, UT>), gt, dim3(256), 0, s, U, out, N, scale);
+    else hipLaunchKernelGGL((fwht_adj_b<false, UT>), gt, dim3(256), 0, s, U, out, N, scale);
     return hipGetLastError();
+}
+
+}  // namespace
+
+bool fwht_supported(int N) { return N >= FWHT_N_MIN && N <= FWHT_N_MAX; }
+
+size_t fwht_workspace_bytes(int N, int batch, bool narrow) {
+    return N <= FWHT_SMALL_N_MAX ? 0 : ((size_t)1 << (2 * N)) * (narrow ? 8u : 16u) * (size_t)batch;
+}
+
+hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N, int batch,
+                       double scale, bool narrow, void* ws, hipStream_t s) {
+    if (!fwht_supported(N)) return hipErrorInvalidValue;
+    if (N <= FWHT_SMALL_N_MAX) {
+        if (in_c128) return out_c128 ? launch_small<true, true>(dir, in, out, N, batch, scale, s)
+                                     : launch_small<true, false>(dir, in, out, N, batch, scale, s);
+        return out_c128 ? launch_small<false, true>(dir, in, out, N, batch, scale, s)
+                        : launch_small<false, false>(dir, in, out, N, batch, scale, s);
+    }
+    if (narrow) return launch_two_pass(dir, in, in_c128, out, out_c128, N, batch, scale, (float2*)ws, s);
+    return launch_two_pass(dir, in, in_c128, out, out_c128, N, batch, scale, (double2*)ws, s);
 }
 
 }  // namespace pauli

@@ -95,15 +95,16 @@ hipError_t launch_strings(const void* G, bool in_c128, int N, const StringChunk*
 hipError_t launch_strings_adjoint(const void* grad, bool grad_c128, const StringEntry* entries,
                                   const uint32_t* first, void* out, bool out_c128, int N, hipStream_t stream);
 
-// All coefficients by two fast Walsh-Hadamard passes through a binary64
-// intermediate of fwht_workspace_bytes(N, batch) bytes (16 per element).
+// All coefficients by two fast Walsh-Hadamard passes through an intermediate
+// of fwht_workspace_bytes(N, batch, narrow) bytes: binary64 pairs (16 bytes
+// per element), or binary32 pairs (8 bytes) when narrow.
 constexpr int FWHT_N_MIN = 0, FWHT_N_MAX = 16;
 constexpr int FWHT_SMALL_N_MAX = 8;   // up to here one kernel works in LDS and needs no workspace
 bool fwht_supported(int N);
-size_t fwht_workspace_bytes(int N, int batch);
+size_t fwht_workspace_bytes(int N, int batch, bool narrow);
 // FORWARD: in = matrices, out = coefficients; ADJOINT: in = coefficients,
 // out = matrices.  scale multiplies the result as for launch_gray.
 hipError_t launch_fwht(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N, int batch,
-                       double scale, void* ws, hipStream_t stream);
+                       double scale, bool narrow, void* ws, hipStream_t stream);
 
 }  // namespace pauli

@@ -223,6 +223,26 @@ def test_fwht_algo_queries(lib, pauli):
     assert lib.pauli_autotune(9, 10, ctypes.byref(o)) == EUNSUPPORTED
 
 
+def test_fwht_f32_algo_queries(lib, pauli):
+    """The binary32-intermediate FWHT: half the workspace, the same range,
+    tile and refusals as the binary64 one."""
+    assert pauli.ALGOS["fwht_f32"] == 5
+    assert lib.pauli_workspace_bytes(5, 14, 1) == 8 * 4 ** 14
+    assert lib.pauli_workspace_bytes(5, 9, 3) == 3 * 8 * 4 ** 9
+    assert lib.pauli_workspace_bytes(5, 8, 1) == 0
+    assert lib.pauli_tile_count(5) == 1
+    assert all(lib.pauli_tile_valid(5, 1, N) == 1 for N in range(0, 17))
+    assert lib.pauli_tile_valid(5, 1, 17) == 0
+    o = opts(pauli, algo="fwht_f32")
+    assert lib.pauli_decompose(FAKE_IN, 17, 1, FAKE_OUT, ctypes.byref(o)) == EINVAL
+    small = opts(pauli, algo="fwht_f32", ws=0x30000000, ws_bytes=8 * 4 ** 10 - 1)
+    assert lib.pauli_decompose(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
+    assert lib.pauli_pack(FAKE_IN, 10, 1, 0, ctypes.byref(o)) == EUNSUPPORTED
+    assert lib.pauli_autotune(9, 10, ctypes.byref(o)) == EUNSUPPORTED
+    assert lib.pauli_decompose_hermitian(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
+    assert lib.pauli_workspace_bytes(6, 10, 1) == 0            # no algo 6
+
+
 def test_hermitian_queries_and_validation(lib, pauli):
     """The Hermitian variant runs on the matrix-core algorithms' register-ring
     tiles only; the other algorithms and the LDS-staged tiles are refused

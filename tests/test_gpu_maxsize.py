@@ -49,7 +49,7 @@ def kron_case():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fwht"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fwht", "fwht_f32"])
 def test_n16_decompose_exact(kron_case, algo):
     p, G, ns, ref = kron_case
     print("N=16 decompose", algo, flush=True)
