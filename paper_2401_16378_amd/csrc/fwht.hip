@@ -211,10 +211,28 @@ __global__ __launch_bounds__(256) void fwht_pass1(const void* __restrict__ Gall,
 // bits 0..3 (j) in the thread.
 constexpr uint32_t TR_PITCH = 512 + 32;   // doubles per vector row of the transpose
 
+// The output stage holds one row of 16 coefficients per z_h (16 ESZ bytes).
+// The threads writing one stage instruction hold rows 16 apart (transposing
+// shape) or consecutive rows (the others), which would all fall on the same
+// LDS banks; 16 bytes of padding after every PADR rows spread them.
+template <bool TRANSPOSE, int ESZ>
+constexpr uint32_t stage_pad_rows() { return TRANSPOSE ? 16u : (ESZ == 16 ? 1u : 2u); }
+
+template <bool TRANSPOSE, int ESZ>
+__device__ inline uint32_t stage_row(uint32_t zh) {
+    return zh * 16u * ESZ + (zh / stage_pad_rows<TRANSPOSE, ESZ>()) * 16u;
+}
+
+template <bool TRANSPOSE, int ESZ>
+constexpr size_t stage_bytes(uint32_t ML) {
+    return (size_t)ML * 16u * ESZ + (size_t)(ML / stage_pad_rows<TRANSPOSE, ESZ>()) * 16u;
+}
+
 template <int TPV, int EPT, bool OUT128>
 constexpr size_t pass2_lds_bytes() {
-    const size_t stage = (size_t)TPV * EPT * 16u * (OUT128 ? 16u : 8u);
-    const size_t tr = TPV * EPT == 512 ? 16u * TR_PITCH * 8u : 0u;
+    constexpr bool T = TPV * EPT == 512;
+    const size_t stage = stage_bytes<T, OUT128 ? 16 : 8>(TPV * EPT);
+    const size_t tr = T ? 16u * TR_PITCH * 8u : 0u;
     return stage > tr ? stage : tr;
 }
 
@@ -286,7 +304,7 @@ __global__ __launch_bounds__(16 * TPV) void fwht_pass2(const UT* __restrict__ Ua
         const uint32_t z = ((h0 + zh) << 5) + zl;
         double re = v[k].x * scale, im = v[k].y * scale;
         rotate_minus_i(re, im, (uint32_t)__popc(x & z));
-        unsigned char* dstl = stage + ((size_t)zh * 16u + slot) * ESZ;
+        unsigned char* dstl = stage + stage_row<TRANSPOSE, ESZ>(zh) + slot * ESZ;
         if constexpr (OUT128) *(double2*)dstl = make_double2(re, im);
         else *(float2*)dstl = make_float2((float)re, (float)im);
     }
@@ -297,7 +315,8 @@ __global__ __launch_bounds__(16 * TPV) void fwht_pass2(const UT* __restrict__ Ua
     for (uint32_t j = (uint32_t)t; j < ML * CH; j += NT) {
         const uint32_t zh = j / CH, part = j % CH;
         const uint32_t base = pauli_index(xb4, ((h0 + zh) << 5) + zb4);   // low four bits are zero
-        *(u32x4_t*)(out + (size_t)base * ESZ + part * 16u) = *(const u32x4_t*)(stage + ((size_t)zh * CH + part) * 16u);
+        *(u32x4_t*)(out + (size_t)base * ESZ + part * 16u) =
+            *(const u32x4_t*)(stage + stage_row<TRANSPOSE, ESZ>(zh) + part * 16u);
     }
 }
 
@@ -329,7 +348,8 @@ __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ 
     for (uint32_t j = (uint32_t)t; j < ML * CH; j += NT) {
         const uint32_t zh = j / CH, part = j % CH;
         const uint32_t base = pauli_index(xb4, ((h0 + zh) << 5) + zb4);
-        *(u32x4_t*)(stage + ((size_t)zh * CH + part) * 16u) = *(const u32x4_t*)(in + (size_t)base * ESZ + part * 16u);
+        *(u32x4_t*)(stage + stage_row<false, ESZ>(zh) + part * 16u) =
+            *(const u32x4_t*)(in + (size_t)base * ESZ + part * 16u);
     }
     __syncthreads();
     const uint32_t slot = ((xl ^ zl) & 1u) | ((zl & 1u) << 1) | (((xl ^ zl) & 2u) << 1) | ((zl & 2u) << 2);
@@ -338,7 +358,7 @@ __global__ __launch_bounds__(16 * TPV) void fwht_adj_a(const void* __restrict__ 
     for (int k = 0; k < EPT; ++k) {
         const uint32_t zh = (uint32_t)q + (uint32_t)TPV * k;
         const uint32_t z = ((h0 + zh) << 5) + zl;
-        const unsigned char* src = stage + ((size_t)zh * 16u + slot) * ESZ;
+        const unsigned char* src = stage + stage_row<false, ESZ>(zh) + slot * ESZ;
         double re, im;
         if constexpr (IN128) {
             const double2 c = *(const double2*)src;
@@ -421,7 +441,7 @@ template <int TPV, int EPT, typename UT>
 hipError_t launch_adj_a(const void* in, bool in128, UT* W, int N, int batch, uint32_t nxb, hipStream_t s) {
     const uint32_t ntop = ((1u << N) >> 5) / (uint32_t)(TPV * EPT);
     const dim3 grid(64u * ntop, nxb, (uint32_t)batch);
-    const size_t lds = (size_t)TPV * EPT * 16u * (in128 ? 16u : 8u);
+    const size_t lds = in128 ? stage_bytes<false, 16>(TPV * EPT) : stage_bytes<false, 8>(TPV * EPT);
     hipError_t e;
     if (in128) {
         e = hipFuncSetAttribute((const void*)fwht_adj_a<TPV, EPT, true, UT>,
