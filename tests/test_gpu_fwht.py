@@ -161,6 +161,26 @@ def test_f32_n14_vs_gray():
     p.release_workspace()
 
 
+def test_f32_n15_vs_binary64():
+    """N = 15, random data: the binary32 intermediate is rounded twice (after
+    pass 1 and after the top pass); every coefficient within twice its
+    rounding bound of the binary64-intermediate result (itself held to the
+    oracle by the exact Kronecker case and the sampled checks)."""
+    p = lib()
+    N = 15
+    gen = torch.Generator(device="cuda").manual_seed(1515)
+    G = torch.randn((1 << N, 1 << N), dtype=torch.complex64, device="cuda", generator=gen)
+    ref = p.decompose(G, algo="fwht", out_dtype=torch.complex128)
+    p.release_workspace()
+    got = p.decompose(G, algo="fwht_f32", out_dtype=torch.complex128)
+    del G
+    p.release_workspace()
+    check_f32_bound(got, ref, N)
+    assert ((got - ref).abs().max() / ref.abs().max()).item() <= 2e-7
+    del got, ref
+    torch.cuda.empty_cache()
+
+
 def test_reconstruct_vs_oracle_full_n9():
     p = lib()
     N = 9
