@@ -501,10 +501,11 @@ def main():
     flops_exec = 2.0 * 2.0 * planes * float(8 ** N)   # 2 (re,im) x 2 flop/MAC x planes x D^3
     flops_useful = 4.0 * float(8 ** N)                 # the method's own work (section 3)
     if herm:
-        # the Hermitian variant's algorithmic work: half of K for every flip mask
-        # (the first few flip-mask tiles walk all of K, so this undercounts)
-        flops_exec /= 2.0
-        flops_useful /= 2.0
+        # the Hermitian variant's algorithmic work: half of K and half of the
+        # rows z for every flip mask (the first few flip-mask tiles walk more,
+        # so this undercounts what they execute)
+        flops_exec /= 4.0
+        flops_useful /= 4.0
     achieved = flops_useful / (mean_launch / 1000.0) / 1e12
     executed = flops_exec / (mean_launch / 1000.0) / 1e12
     peak = 157.3 if a.algo == "fp32" else PEAK_BF16_TFLOPS   # bf16 and fp16 share the dense peak
@@ -584,13 +585,14 @@ def main():
         "config": {"workload": "dense Pauli decomposition, N=%d (%dx%d complex64 Hermitian, "
                                "G=(A+A^H)/2, A iid N(0,1)), all 4^%d coefficients, %s%s"
                                % (N, 1 << N, 1 << N, N, a.algo,
-                                  ", Hermitian variant (half of K per flip mask, pauli_decompose_hermitian)"
+                                  ", Hermitian variant (half of K and of the rows per flip mask, "
+                                  "pauli_decompose_hermitian)"
                                   if herm else ""), "N": N, "batch": 1,
                    "algo": a.algo, "tile": tile_used},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "counts": "the method's own flops, 4*8^N (re, im x 2 flop per term)%s; executed "
-                               "matrix-core flops (%d planes) in executed_*" % (", halved" if herm else "", planes),
+                               "matrix-core flops (%d planes) in executed_*" % (", quartered" if herm else "", planes),
                      "flops_per_launch": flops_useful,
                      "executed_tflops": executed, "executed_frac": executed / peak,
                      "executed_flops_per_launch": flops_exec,

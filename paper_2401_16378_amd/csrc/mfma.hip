@@ -180,7 +180,8 @@ hipError_t launch_contract(const Params& p, int batch, hipStream_t s) {
         const uint32_t Dp = padded_dim(p.N);
         const uint32_t nMB = Dp / MT, nXB = Dp / XT;
         auto kern = contract_kernel<PLANES, RB, WAVES, DIR, PF, HERM>;
-        const int lds = WAVES * 1024 * (p.out128 ? 16 : 8);
+        // Hermitian: a second output stage for the partner rows, where it fits
+        const int lds = WAVES * 1024 * (p.out128 ? 16 : 8) * (HERM && herm_pair_stage_fits(WAVES, p.out128) ? 2 : 1);
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(WAVES * 64), lds, s, p);

@@ -453,6 +453,17 @@ constexpr uint32_t herm_half_from(int planes, int rb, int pf) {
     return (uint32_t)ring_step_slices(planes, rb, pf) * (uint32_t)slice_k(planes);
 }
 
+// Hermitian tiles that also halve the rows: a half walk (X0 >= hf) whose
+// skipped bit 2^b (the top bit of X0) spans whole workgroup tiles of mt rows,
+// when the LDS holds two output stages of `waves` x 1024 coefficients.
+constexpr uint32_t LDS_BYTES_MAX = 160u * 1024u;
+__host__ __device__ constexpr bool herm_pair_stage_fits(int waves, int out128) {
+    return (uint32_t)waves * 2u * 1024u * (out128 ? 16u : 8u) <= LDS_BYTES_MAX;
+}
+__host__ __device__ inline bool herm_pair_rows(uint32_t X0, uint32_t hf, uint32_t mt, int waves, int out128) {
+    return X0 >= hf && X0 != 0 && (1u << (31 - __builtin_clz(X0))) >= mt && herm_pair_stage_fits(waves, out128);
+}
+
 // Binary32 plane: an MFMA accumulator chain adds at most FLUSH_SLICES slices
 // (256 K values) before it is added into a running binary32 total and
 // restarted from zero.  The boundary is a fixed K offset, the same for every
@@ -488,9 +499,20 @@ __device__ inline void flush_into(f32x16 (&tot)[1][RB][2], f32x16 (&acc)[1][RB][
 // input is Hermitian, so the sum is real when popc(x&z) is even and
 // imaginary when it is odd; the other component, zero in exact arithmetic,
 // is dropped before the phase, which leaves every coefficient exactly real.
-template <int PLANES, int RB, int DIR, bool HERM = false>
+// HERM with HF > 0: a tile of MT rows whose flip masks start at X0 >= HF was
+// a half walk over K (bit b = the top bit of X0 skipped); when 2^b >= MT (and
+// the workgroup's LDS has room for a second stage) the rows Pw ^ 2^b hold the
+// same sums, so each value is staged a second time for them, with the other
+// component (the parity of popc(x&z) flips), and both runs are stored.  The
+// condition is re-derived here from X0 rather than carried through the
+// contraction in a register.
+template <int PLANES, int RB, int DIR, bool HERM = false, uint32_t HF = 0, uint32_t MT = 0>
 __device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&acc)[Pack<PLANES>::ACC][RB][2], unsigned char* __restrict__ dst,
                                   int N, uint32_t X0, uint32_t Pw, double scale, int out128, unsigned char* lds) {
+    uint32_t pair = 0;
+    if constexpr (HERM && HF > 0) {
+        if (herm_pair_rows(X0, HF, MT, (int)(MT / (32 * RB)), out128)) pair = 1u << (31 - __builtin_clz(X0));
+    }
     constexpr int ACC = Pack<PLANES>::ACC;
     constexpr double LOW = PLANES == 2 ? 1.0 / 2048.0 : 1.0;   // weight of the second accumulator
     const uint32_t D = 1u << N;
@@ -505,6 +527,7 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&
     const int l32 = lane & 31, h = lane >> 5;
     const int esz = out128 ? 16 : 8;
     unsigned char* stage = lds + wave * 1024 * esz;
+    unsigned char* stage2 = lds + ((HF > 0 ? MT / (32 * RB) : 0) + wave) * 1024 * esz;   // the partner rows' stage
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
         const uint32_t pb = Pw + 32 * rb;   // first row of this 32x32 block
@@ -522,12 +545,23 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&
             uint32_t slot;
             if constexpr (DIR == FORWARD) {
                 const uint32_t ny = (uint32_t)__popc((X0 + l32) & (pb + pl));
+                slot = pauli_index((uint32_t)l32, pl);           // offset inside the 1024-run
                 if constexpr (HERM) {
-                    if (ny & 1) re = 0.0;
-                    else im = 0.0;
+                    double qr = re, qi = im;                      // row pb + pl ^ pair: the other component
+                    if (ny & 1) {
+                        re = 0.0;
+                        qi = 0.0;
+                    } else {
+                        im = 0.0;
+                        qr = 0.0;
+                    }
+                    if (pair) {
+                        rotate_minus_i(qr, qi, ny + 1u);
+                        if (out128) *(double2*)(stage2 + slot * 16) = make_double2(qr, qi);
+                        else *(float2*)(stage2 + slot * 8) = make_float2((float)qr, (float)qi);
+                    }
                 }
                 rotate_minus_i(re, im, ny);
-                slot = pauli_index((uint32_t)l32, pl);           // offset inside the 1024-run
             } else {
                 slot = ((pl ^ (uint32_t)l32) << 5) | pl;        // (row, col) inside the 32x32 square
             }
@@ -545,6 +579,13 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&
                         *(u32x4*)(o + b) = *(const u32x4*)(stage + b);
                 } else if (lane == 0) {
                     *(u32x2*)o = *(const u32x2*)stage;   // N = 0, binary32 output
+                }
+            }
+            if constexpr (HERM) {
+                if (pair) {   // 1024-runs only: 2^b >= MT >= 32 rows, so N >= 6
+                    unsigned char* o2 = dst + (size_t)pauli_index(X0, pb ^ pair) * esz;
+                    for (uint32_t b = lane * 16; b < run * esz; b += 64 * 16)
+                        *(u32x4*)(o2 + b) = *(const u32x4*)(stage2 + b);
                 }
             }
         } else {
@@ -608,8 +649,15 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
     if constexpr (HERM) {
         if (X0 >= herm_half_from(PLANES, RB, PF)) {
             half = true;
-            beta = (uint32_t)(31 - __builtin_clz(X0)) - (uint32_t)P::LOG_SK;
+            const uint32_t tb = (uint32_t)(31 - __builtin_clz(X0));   // bit b, set in every flip mask of the tile
+            beta = tb - (uint32_t)P::LOG_SK;
             nK = nS >> 1;
+            // The half walk never reads bit b of i, so rows z and z ^ 2^b get
+            // the same sums; the tile with bit b of its rows clear stores both
+            // (store_tile), and the tile with it set has nothing left to do.
+            if (herm_pair_rows(X0, herm_half_from(PLANES, RB, PF), (uint32_t)MT, WAVES, out128) &&
+                (((mb * (uint32_t)MT) >> tb) & 1u))
+                return;
         }
     }
     auto slice_of = [&](uint32_t c) -> uint32_t {
@@ -806,9 +854,9 @@ __device__ __attribute__((always_inline)) inline void contract_tile(const unsign
     const double sc = half ? 2.0 * scale : scale;   // a half walk sums one member of each pair
     if constexpr (PLANES == 1) {
         flush_into<RB>(tot, acc);
-        store_tile<PLANES, RB, DIR, HERM>(tot, dst, N, X0, Pw, sc, out128, lds);
+        store_tile<PLANES, RB, DIR, HERM, herm_half_from(PLANES, RB, PF), (uint32_t)MT>(tot, dst, N, X0, Pw, sc, out128, lds);
     } else {
-        store_tile<PLANES, RB, DIR, HERM>(acc, dst, N, X0, Pw, sc, out128, lds);
+        store_tile<PLANES, RB, DIR, HERM, herm_half_from(PLANES, RB, PF), (uint32_t)MT>(acc, dst, N, X0, Pw, sc, out128, lds);
     }
 }
 
