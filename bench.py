@@ -53,7 +53,8 @@ STRINGS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_strings_n14.json"
 FWHT_SOURCES = ["paper_2401_16378_amd/csrc/fwht.hip", "paper_2401_16378_amd/csrc/common.hpp"]
 FWHT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwht_n14.json")
 FWHT_F32_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwht_f32_n14.json")
-HERM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hermitian_n14.json")
+HERM_TRAFFIC_FILES = {"split_bf16": os.path.join(ROOT, "profiles", "traffic_hermitian_n14.json"),
+                      "split_fp16": os.path.join(ROOT, "profiles", "traffic_hermitian_fp16_n14.json")}
 
 
 def source_hash(sources=KERNEL_SOURCES) -> str:
@@ -566,11 +567,12 @@ def main():
         res["max_err_vs_oracle_sample"] = err_cpu
         log("[bench] oracle %.0f coeffs/s on %d cores, sample err %.3g" % (cpu["value"], cpu["cores"], err_cpu))
 
-    # committed counter summaries cover the split-bf16 kernels at N=14 only
-    tile_used = a.tile if a.tile else pauli.tile_selected(N, a.algo)   # the general path's choice
+    # committed counter summaries cover the split kernels at N=14 only
+    tile_used = a.tile if a.tile else (pauli.tile_selected_hermitian(N, a.algo) if herm
+                                       else pauli.tile_selected(N, a.algo))
     traffic = None
-    if N == 14 and herm and a.algo == "split_bf16":
-        traffic = measured_traffic(HERM_TRAFFIC_FILE)
+    if N == 14 and herm and a.algo in HERM_TRAFFIC_FILES:
+        traffic = measured_traffic(HERM_TRAFFIC_FILES[a.algo])
     elif N == 14 and not herm and a.algo in TRAFFIC_FILES:
         traffic = measured_traffic(TRAFFIC_FILES[a.algo])
     if herm:

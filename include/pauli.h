@@ -146,11 +146,16 @@ int pauli_decompose(const void* G, int N, int batch, void* out, const pauli_opts
  * v_x[i xor x] = conj(v_x[i]) in Eq. (c_def_in_terms_of_fn), so the sum over
  * half of the i, doubled, gives the sum over all: the matrix-core contraction
  * walks half of its K range for every block of 32 flip masks whose common
- * high bits are large enough (all blocks but the first few), and every
- * coefficient's imaginary part is written as exactly zero.
- * algo SPLIT_BF16 or FP32 (others: PAULI_EUNSUPPORTED); register-ring tiles
- * only (pauli_tile_valid_hermitian; a forced LDS-staged tile fails with
- * PAULI_EINVAL).  Limits, layouts, workspace and stream as pauli_decompose.
+ * high bits are large enough (all blocks but the first few).  That half sum
+ * does not see bit b of z either (b = the block's top flip-mask bit), so
+ * rows z and z xor 2^b share it: one gives the real part (popc(x&z) even),
+ * the other the imaginary part, and where 2^b spans whole workgroup tiles
+ * only one of the two row tiles is computed (a quarter of the general
+ * work).  Every coefficient's imaginary part is written as exactly zero.
+ * algo SPLIT_FP16, SPLIT_BF16 or FP32 (others: PAULI_EUNSUPPORTED);
+ * register-ring tiles only (pauli_tile_valid_hermitian; a forced LDS-staged
+ * tile fails with PAULI_EINVAL); pauli_tile_selected_hermitian gives the
+ * tile it uses.  Limits, layouts, workspace and stream as pauli_decompose.
  * The Hermitian property is the caller's promise and is not checked: the
  * kernel reads only one entry of most pairs (G[i xor x][i], G[i][i xor x]),
  * so for a non-Hermitian G the result is unspecified (finite input still
@@ -268,6 +273,10 @@ int pauli_tile_valid_hermitian(int algo, int tile, int N);
 
 /* Tile id pauli_decompose would use for (algo, N) right now. */
 int pauli_tile_selected(int algo, int N);
+
+/* Tile id pauli_decompose_hermitian would use for (algo, N) right now (0 if
+ * the algorithm has no Hermitian variant or N is out of range). */
+int pauli_tile_selected_hermitian(int algo, int N);
 
 /*
  * Coefficients of a caller-chosen list of Pauli strings (the paper's inner

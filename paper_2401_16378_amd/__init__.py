@@ -53,7 +53,7 @@ EXPORTS = ["pauli_opts_default", "pauli_decompose", "pauli_reconstruct", "pauli_
            "pauli_tile_selected", "pauli_pack", "pauli_contract", "pauli_coeffs_at", "pauli_coeffs_at_backward",
            "pauli_decompose_hermitian", "pauli_tile_valid_hermitian",
            "pauli_coeffs_at_workspace_bytes", "pauli_last_error", "pauli_version",
-           "pauli_decompose_noalloc", "pauli_noalloc_scratch_bytes"]
+           "pauli_decompose_noalloc", "pauli_noalloc_scratch_bytes", "pauli_tile_selected_hermitian"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH):
         lib.pauli_tile_valid_hermitian.restype = ci
         lib.pauli_tile_selected.argtypes = [ci, ci]
         lib.pauli_tile_selected.restype = ci
+        lib.pauli_tile_selected_hermitian.argtypes = [ci, ci]
+        lib.pauli_tile_selected_hermitian.restype = ci
         lib.pauli_pack.argtypes = [vp, ci, ci, ci, op]
         lib.pauli_pack.restype = ci
         lib.pauli_contract.argtypes = [ci, ci, ci, vp, op]
@@ -453,6 +455,10 @@ def batched_tile_valid(tile: int, algo: str = "split_bf16") -> bool:
 
 def tile_selected(N: int, algo: str = "split_bf16") -> int:
     return load_library().pauli_tile_selected(ALGOS[algo], N)
+
+
+def tile_selected_hermitian(N: int, algo: str = "split_bf16") -> int:
+    return load_library().pauli_tile_selected_hermitian(ALGOS[algo], N)
 
 
 from .autograd import PauliCoeffsAt, PauliDecompose  # noqa: E402

@@ -213,14 +213,11 @@ hipError_t pool_for_current_device(hipMemPool_t* pool) {
 
 // Tile for the Hermitian forward contraction: forced, else the tuned tile of
 // the general path when it is a register-ring tile, else the default.
+// The Hermitian contraction has its own defaults: the tune table holds tiles
+// timed on the general contraction, whose work per tile differs.
 int pick_tile_hermitian(int algo, int N, int forced) {
-    const int planes = planes_of(algo);
     if (forced > 0) return forced;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    load_tune_cache_locked();
-    auto it = g_tune.find({algo, N});
-    if (it != g_tune.end() && mfma_tile_valid_hermitian(planes, it->second, N)) return it->second;
-    return mfma_default_tile_hermitian(planes, N);
+    return mfma_default_tile_hermitian(planes_of(algo), N);
 }
 
 int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& o, double scale,
@@ -475,6 +472,11 @@ int pauli_tile_valid_hermitian(int algo, int tile, int N) {
 int pauli_tile_selected(int algo, int N) {
     if (!valid_algo(algo) || N < 0 || N > N_MAX) return 0;
     return pick_tile(algo, N, 0);
+}
+
+int pauli_tile_selected_hermitian(int algo, int N) {
+    if (!is_mfma(algo) || N < 0 || N > N_MAX) return 0;
+    return pick_tile_hermitian(algo, N, 0);
 }
 
 const char* pauli_last_error(void) { return g_last_error.c_str(); }

@@ -262,6 +262,14 @@ def test_hermitian_queries_and_validation(lib, pauli):
         assert lib.pauli_tile_valid_hermitian(1, t, 12) == 1
     assert lib.pauli_tile_valid_hermitian(0, 1, 10) == 0 and lib.pauli_tile_valid_hermitian(3, 1, 10) == 0
     assert lib.pauli_tile_valid_hermitian(2, 1, 8) == 0 and lib.pauli_tile_valid_hermitian(2, 1, 17) == 0
+    # the Hermitian defaults: one wave of 4 x 32 rows for the split paths from N = 12
+    for algo in (2, 4):
+        assert lib.pauli_tile_selected_hermitian(algo, 14) == lib.pauli_tile_selected_hermitian(algo, 12) == 7
+        assert lib.pauli_tile_valid_hermitian(algo, 7, 12) == 1
+        assert lib.pauli_tile_selected_hermitian(algo, 11) == lib.pauli_tile_selected(algo, 11)
+    assert lib.pauli_tile_selected_hermitian(1, 14) == 3
+    assert lib.pauli_tile_selected_hermitian(0, 14) == lib.pauli_tile_selected_hermitian(3, 14) == 0
+    assert lib.pauli_tile_selected_hermitian(2, 17) == 0
     assert f(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(opts(pauli, tile=-1))) == EINVAL
 
 
