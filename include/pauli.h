@@ -130,7 +130,7 @@ void pauli_opts_default(pauli_opts* o);
  * of up to 2^N terms, so their results are finite for components of
  * magnitude below 2^(127 - N); SPLIT_FP16 rescales each matrix by a power of
  * two first and has no limit beyond finite binary32 components; FP64_GRAY
- * and FWHT sum in binary64.  For such inputs every path scales exactly:
+ * and both FWHT algorithms sum in binary64.  For such inputs every path scales exactly:
  * c(2^k G) = 2^k c(G) bit for bit while all operands, split parts and
  * partial sums stay normal numbers.  Infinite or NaN components give
  * non-finite outputs (no error is reported).
@@ -234,8 +234,11 @@ int pauli_batched_tile_selected(int count, const int* N, int algo);
  * Device scratch bytes pauli_decompose, pauli_reconstruct and
  * pauli_decompose_backward need for (algo, N, batch) when the caller supplies
  * opts->workspace: 12 bytes per matrix element for SPLIT_BF16 (six bf16
- * planes), 8 for FP32, 0 for FP64_GRAY; N < 5 counts as N = 5.  A smaller
- * workspace fails with PAULI_ENOMEM.  Returns 0 for invalid arguments.
+ * planes), 8 for SPLIT_FP16 (four fp16 planes) plus its prescale exponent and
+ * partial maxima, 8 for FP32 (N < 5 counts as N = 5 for these three);
+ * 16 for FWHT and 8 for FWHT_F32 from N = 9 on, none below; 0 for FP64_GRAY.
+ * A smaller workspace fails with PAULI_ENOMEM.  Returns 0 for invalid
+ * arguments.
  */
 size_t pauli_workspace_bytes(int algo, int N, int batch);
 
@@ -349,8 +352,9 @@ int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.
  * pauli_decompose with every argument, limit and result as there, except
- * that the device scratch of the algorithm (the packed operand of SPLIT_BF16
- * and FP32, the binary64 intermediate of FWHT; FP64_GRAY needs none) is a
+ * that the device scratch of the algorithm (the packed operand of the
+ * matrix-core algorithms, the intermediate of the two FWHT algorithms;
+ * FP64_GRAY needs none) is a
  * fixed array of pauli_noalloc_scratch_bytes() bytes (64 MiB) that the
  * library holds on each GPU it runs on until the process ends, so the call
  * itself allocates nothing (no hipMalloc, no pool, no host allocation of
