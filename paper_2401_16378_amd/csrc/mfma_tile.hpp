@@ -527,7 +527,8 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x16 (&
     const int l32 = lane & 31, h = lane >> 5;
     const int esz = out128 ? 16 : 8;
     unsigned char* stage = lds + wave * 1024 * esz;
-    unsigned char* stage2 = lds + ((HF > 0 ? MT / (32 * RB) : 0) + wave) * 1024 * esz;   // the partner rows' stage
+    // the partner rows' stage, after the WAVES stages (allocated only where pairing can happen)
+    unsigned char* stage2 = HERM && HF > 0 ? lds + (MT / (32 * RB) + wave) * 1024 * esz : stage;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
         const uint32_t pb = Pw + 32 * rb;   // first row of this 32x32 block
