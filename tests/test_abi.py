@@ -387,3 +387,15 @@ def test_noalloc_validation(lib, pauli):
     # a workspace in the options is ignored, not checked against the buffers
     ws = opts(pauli, ws=FAKE_IN, ws_bytes=1 << 30)
     assert f(FAKE_IN, 12, 1, FAKE_OUT, ctypes.byref(ws)) == ENOMEM
+
+
+def test_entry_points_compile():
+    """The driver-facing scripts at the repository root parse and define
+    their entry points (nothing is built or run here)."""
+    import importlib
+    import py_compile
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for name in ("__graft_entry__.py", "bench.py"):
+        py_compile.compile(os.path.join(root, name), doraise=True)
+    g = importlib.import_module("__graft_entry__")
+    assert callable(g.build) and callable(g.smoke)
