@@ -237,3 +237,26 @@ def test_split_passes_any_contraction_tile(algo):
         assert lib_.pauli_pack(G.data_ptr(), N, 1, 3, ctypes.byref(pack_o)) == 0
         assert lib_.pauli_contract(N, 1, 3, out.data_ptr(), ctypes.byref(cont_o)) == 0
         assert torch.equal(out, want), (algo, tile)
+
+
+@pytest.mark.parametrize("algo", ["split_fp16", "split_bf16"])
+def test_row_pairs_complex128_every_tile_n11(algo):
+    """The row-halved tiles (2^b >= the tile's rows) with complex128 output,
+    whose second output stage doubles a larger LDS area (and the 8-wave tile,
+    where two stages of 16-byte values do not fit and no rows are paired):
+    every register-ring tile at N = 11 gives complex64 output equal to its
+    complex128 output rounded, and the complex128 output within the split
+    tolerance of the binary64 fast transform, with zero imaginary parts."""
+    p = lib()
+    N = 11
+    Gd = torch.from_numpy(workloads.hermitian(N, 1111)).cuda()
+    ref = p.decompose(Gd, algo="fwht", out_dtype=torch.complex128)
+    m = ref.abs().max().item()
+    for tile in range(1, 13):
+        if not p.tile_valid_hermitian(tile, N, algo):
+            continue
+        c128 = p.decompose_hermitian(Gd, algo=algo, tile=tile, out_dtype=torch.complex128)
+        c64 = p.decompose_hermitian(Gd, algo=algo, tile=tile)
+        assert torch.equal(c64, c128.to(torch.complex64)), tile
+        assert torch.all(c128.imag == 0), tile
+        assert (c128 - ref).abs().max().item() <= TOL[algo] * m, tile
