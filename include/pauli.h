@@ -255,7 +255,11 @@ size_t pauli_workspace_bytes(int algo, int N, int batch);
  * entry per line: "algo N tile" for single matrices and
  * "B planes tile c_1 ... c_12" for a batch of c_n matrices of order n
  * (planes 3 = SPLIT_BF16, 2 = SPLIT_FP16, 1 = FP32); lines that do not parse
- * are ignored.
+ * are ignored.  The table applies to pauli_decompose, pauli_reconstruct,
+ * pauli_decompose_backward and the two-pass entry points;
+ * pauli_decompose_hermitian keeps its own defaults (its tiles do a quarter
+ * of the work with twice the stores, so the general timings do not carry
+ * over).
  */
 int pauli_autotune(int N_min, int N_max, const pauli_opts* opts);
 
