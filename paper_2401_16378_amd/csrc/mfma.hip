@@ -69,6 +69,39 @@ __global__ __launch_bounds__(256) void absmax_kernel(const void* __restrict__ in
     if (threadIdx.x == 0) partial[(size_t)blockIdx.y * R + blockIdx.x] = m;
 }
 
+// Hermitian input: |G[c][r]| = |G[r][c]|, so the largest component lies in
+// the lower triangle (diagonal included).  Block b reads, for each of its
+// row pairs (r, D-1-r), the D + 1 elements G[r][0..r] and G[D-1-r][0..D-1-r]:
+// half of G, the same maximum.  Needs D >= 2; R divides D / 2.
+template <bool IN128>
+__global__ __launch_bounds__(256) void absmax_lower_kernel(const void* __restrict__ in, int N,
+                                                           float* __restrict__ partial, uint32_t R) {
+    __shared__ float red[4];
+    const uint32_t D = 1u << N;
+    const uint32_t ppb = (D / 2u) / R;                 // row pairs per block
+    const size_t mat = (size_t)D * D;
+    float m = 0.f;
+    for (uint32_t pp = 0; pp < ppb; ++pp) {
+        const uint32_t r = blockIdx.x * ppb + pp;      // rows r and D-1-r: r + 1 and D - r elements
+        for (uint32_t e = threadIdx.x; e <= D; e += 256) {
+            const size_t idx = e <= r ? (size_t)r * D + e : (size_t)(D - 1u - r) * D + (e - r - 1u);
+            float a, b;
+            if constexpr (IN128) {
+                const double2 v = ((const double2*)in)[(size_t)blockIdx.y * mat + idx];
+                a = (float)v.x;
+                b = (float)v.y;
+            } else {
+                const float2 v = ((const float2*)in)[(size_t)blockIdx.y * mat + idx];
+                a = v.x;
+                b = v.y;
+            }
+            m = __builtin_fmaxf(m, __builtin_fmaxf(__builtin_fabsf(a), __builtin_fabsf(b)));
+        }
+    }
+    m = block_max256(m, red);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * R + blockIdx.x] = m;
+}
+
 __global__ __launch_bounds__(256) void prescale_kernel(const float* __restrict__ partial, uint32_t R,
                                                        int* __restrict__ pe) {
     __shared__ float red[4];
@@ -252,6 +285,20 @@ hipError_t launch_prescale(const void* in, bool in128, void* ws, int N, int batc
     return hipGetLastError();
 }
 
+// The same exponents for Hermitian G from the lower triangle only.
+hipError_t launch_prescale_hermitian(const void* in, bool in128, void* ws, int N, int batch, hipStream_t s) {
+    const uint32_t D = 1u << N;
+    if (D < 2u) return launch_prescale(in, in128, ws, N, batch, s);
+    uint32_t R = absmax_blocks(N);                     // a power of two, as is D / 2
+    if (R > D / 2u) R = D / 2u;
+    float* partial = prescale_partials(ws, N, batch);
+    if (in128) hipLaunchKernelGGL((absmax_lower_kernel<true>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+    else hipLaunchKernelGGL((absmax_lower_kernel<false>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+    hipLaunchKernelGGL(prescale_kernel, dim3(batch), dim3(256), 0, s, (const float*)partial, R,
+                       prescale_exponents(ws, N, batch));
+    return hipGetLastError();
+}
+
 template <int PLANES, int DIR>
 hipError_t launch_pack(const void* in, bool in128, void* ws, int N, int batch, hipStream_t s) {
     const int* pe = nullptr;
@@ -382,7 +429,7 @@ hipError_t launch_mfma_pack_hermitian(int planes, const void* in, bool in_c128, 
         if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<3, true>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
         else hipLaunchKernelGGL((pack_herm_kernel<3, false>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
     } else if (planes == 2) {
-        const hipError_t e = launch_prescale(in, in_c128, ws, N, batch, stream);
+        const hipError_t e = launch_prescale_hermitian(in, in_c128, ws, N, batch, stream);
         if (e != hipSuccess) return e;
         pe = prescale_exponents(ws, N, batch);
         if (in_c128) hipLaunchKernelGGL((pack_herm_kernel<2, true>), grid, dim3(256), 0, stream, in, ws, N, hmin, pe);
