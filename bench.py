@@ -40,14 +40,28 @@ METRIC = "Pauli coeffs/sec + % MFMA peak at N=14, split-BF16 vs FP64 at err≤1e
 METRIC_HERM = ("Pauli coeffs/sec at N=14, Hermitian-aware split-BF16 (not the paper's general method), "
                "err<=1e-6")
 PEAK_BF16_TFLOPS = 2500.0
+PEAK_I8_TOPS = 5000.0   # dense int8 matrix-core peak
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2401_16378_amd/csrc/mfma_tile.hpp", "paper_2401_16378_amd/csrc/mfma.hip",
                   "paper_2401_16378_amd/csrc/common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_bf16_n14.json")
 TRAFFIC_FILES = {"split_bf16": TRAFFIC_FILE,
-                 "split_fp16": os.path.join(ROOT, "profiles", "traffic_split_fp16_n14.json")}
-PLANES = {"split_bf16": 3, "split_fp16": 2, "fp32": 1}
-DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "fp32": "f32"}
+                 "split_fp16": os.path.join(ROOT, "profiles", "traffic_split_fp16_n14.json"),
+                 "split_i8": os.path.join(ROOT, "profiles", "traffic_split_i8_n14.json")}
+I8_SOURCES = ["paper_2401_16378_amd/csrc/mfma_i8.hip", "paper_2401_16378_amd/csrc/mfma_tile.hpp",
+              "paper_2401_16378_amd/csrc/common.hpp"]
+TRAFFIC_SOURCES = {"split_i8": I8_SOURCES}
+PLANES = {"split_bf16": 3, "split_fp16": 2, "fp32": 1, "split_i8": 3}
+DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "fp32": "f32", "split_i8": "i8"}
+SPLITS = ("split_bf16", "split_fp16", "split_i8")
+OTHER_SPLIT = {"split_fp16": "split_bf16", "split_bf16": "split_fp16", "split_i8": "split_fp16"}
+
+
+def peak_of(algo):
+    """(dense matrix-core peak, unit) of the algorithm's MFMA data type."""
+    if algo == "split_i8":
+        return PEAK_I8_TOPS, "TOP/s"
+    return (157.3 if algo == "fp32" else PEAK_BF16_TFLOPS), "TFLOP/s"   # bf16 and fp16 share the dense peak
 STRINGS_SOURCES = ["paper_2401_16378_amd/csrc/strings.hip", "paper_2401_16378_amd/csrc/common.hpp"]
 STRINGS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_strings_n14.json")
 FWHT_SOURCES = ["paper_2401_16378_amd/csrc/fwht.hip", "paper_2401_16378_amd/csrc/common.hpp"]
@@ -313,7 +327,8 @@ def bench_table(a):
     """Every single-matrix config of the workload list, every path: median
     time of `steps` calls (HIP events around each call, input in HBM),
     coefficients/s, the method's flops (4 * 8^N) and the executed flops as
-    fractions of the matrix-core peak, algorithmic HBM bytes (input read +
+    fractions of the matrix-core peak of the path's data type (int8 ops for
+    split_i8), algorithmic HBM bytes (input read +
     coefficients written) per second, and the error against the binary64
     Gray kernel (which the tests hold bit-identical to the oracle).  One JSON
     line per (config, path) on stdout."""
@@ -326,13 +341,13 @@ def bench_table(a):
                ("N=10 complex128 iid", 10, workloads.iid_complex(10, workloads.SEED_N10)),
                ("N=12 complex64 Hermitian", 12, workloads.hermitian(12, workloads.SEED_N12)),
                ("N=14 complex64 Hermitian", 14, workloads.hermitian(14, workloads.SEED_N14))]
-    peak = {"split_fp16": PEAK_BF16_TFLOPS, "split_bf16": PEAK_BF16_TFLOPS, "fp32": 157.3}
+    peak = {algo: peak_of(algo)[0] for algo in ("split_i8", "split_fp16", "split_bf16", "fp32")}
     for name, N, G in configs:
         Gd = torch.from_numpy(G).to(dev)
         esz = 16 if Gd.dtype == torch.complex128 else 8
         ref = pauli.decompose(Gd, algo="fp64_gray", out_dtype=torch.complex128)
         mref = ref.abs().max().item()
-        for algo in ("split_fp16", "split_bf16", "fp32", "fwht", "fwht_f32", "fp64_gray"):
+        for algo in ("split_i8", "split_fp16", "split_bf16", "fp32", "fwht", "fwht_f32", "fp64_gray"):
             steps = a.steps if not (algo in ("fp64_gray", "fp32") and N == 14) else 3
             out = pauli.decompose(Gd, algo=algo)
             err = ((out.to(torch.complex128) - ref).abs().max().item()) / mref
@@ -352,7 +367,8 @@ def bench_table(a):
             if algo in peak:
                 useful = 4.0 * float(8 ** N) / (ms / 1e3) / 1e12
                 row.update({"useful_frac": useful / peak[algo],
-                            "executed_frac": useful * PLANES[algo] / peak[algo], "peak_tflops": peak[algo]})
+                            "executed_frac": useful * PLANES[algo] / peak[algo], "peak": peak[algo],
+                            "peak_unit": peak_of(algo)[1]})
             print(json.dumps(row), flush=True)
             del out
         del Gd, ref
@@ -465,6 +481,8 @@ def main():
     if a.algo not in PLANES:
         raise SystemExit("bench.py: the n14 and hermitian workloads time a matrix-core algorithm (%s)"
                          % ", ".join(PLANES))
+    if herm and a.algo == "split_i8":
+        raise SystemExit("bench.py: split_i8 has no Hermitian variant")
     mode = 3 if herm else 0   # 3: pauli_decompose_hermitian split at the kernel boundary
 
     def step(mid=None):
@@ -499,7 +517,7 @@ def main():
     coeffs = float(4 ** N)
     value = coeffs / (ms_step / 1000.0)
     planes = PLANES[a.algo]
-    flops_exec = 2.0 * 2.0 * planes * float(8 ** N)   # 2 (re,im) x 2 flop/MAC x planes x D^3
+    flops_exec = 2.0 * 2.0 * planes * float(8 ** N)   # 2 (re,im) x 2 op/MAC x planes x D^3
     flops_useful = 4.0 * float(8 ** N)                 # the method's own work (section 3)
     if herm:
         # the Hermitian variant's algorithmic work: half of K and half of the
@@ -509,7 +527,7 @@ def main():
         flops_useful /= 4.0
     achieved = flops_useful / (mean_launch / 1000.0) / 1e12
     executed = flops_exec / (mean_launch / 1000.0) / 1e12
-    peak = 157.3 if a.algo == "fp32" else PEAK_BF16_TFLOPS   # bf16 and fp16 share the dense peak
+    peak, peak_unit = peak_of(a.algo)
     log("[bench] %.3f ms/step (median %.3f), pack %.3f ms, contraction %.3f ms (median %.3f), "
         "%.1f TFLOP/s useful, %.1f executed"
         % (ms_step, float(np.median(step_ms)), pack_ms, mean_launch, float(np.median(launch_ms)), achieved,
@@ -539,9 +557,9 @@ def main():
         log("[bench] fp64 gray %.1f ms, ratio %.2f, err %.3g" % (fp64_ms, fp64_ms / ms_step, err))
         del out64
 
-    if a.algo in ("split_bf16", "split_fp16") and not a.no_compare:
-        # the other split path on the same input: its time per step and error
-        other = "split_bf16" if a.algo == "split_fp16" else "split_fp16"
+    if a.algo in SPLITS and not a.no_compare:
+        # another split path on the same input: its time per step and error
+        other = OTHER_SPLIT[a.algo]
         ws2 = pauli.workspace(other, N, 1, dev)
         o2 = pauli._opts(other, 0, 0, 0, ctypes.c_void_p(stream.cuda_stream), ws2)
         out2 = torch.empty_like(out)
@@ -570,15 +588,17 @@ def main():
     # committed counter summaries cover the split kernels at N=14 only
     tile_used = a.tile if a.tile else (pauli.tile_selected_hermitian(N, a.algo) if herm
                                        else pauli.tile_selected(N, a.algo))
+    if a.algo == "split_i8":
+        tile_used = 1   # its one tile shape
     traffic = None
     if N == 14 and herm and a.algo in HERM_TRAFFIC_FILES:
         traffic = measured_traffic(HERM_TRAFFIC_FILES[a.algo])
     elif N == 14 and not herm and a.algo in TRAFFIC_FILES:
-        traffic = measured_traffic(TRAFFIC_FILES[a.algo])
+        traffic = measured_traffic(TRAFFIC_FILES[a.algo], TRAFFIC_SOURCES.get(a.algo, KERNEL_SOURCES))
     if herm:
         res["imag_exactly_zero"] = bool(np.all(c_bf16.imag == 0))
     line = {
-        "metric": METRIC_HERM if herm else (METRIC if a.algo in ("split_bf16", "split_fp16") else
+        "metric": METRIC_HERM if herm else (METRIC if a.algo in SPLITS else
                                             "Pauli coeffs/sec + %% MFMA peak at N=%d, %s matrix-core path"
                                             % (N, a.algo)), "value": value, "unit": "coeffs/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_step, "ms_per_step_median": float(np.median(step_ms)),
@@ -591,16 +611,19 @@ def main():
                                   "pauli_decompose_hermitian)"
                                   if herm else ""), "N": N, "batch": 1,
                    "algo": a.algo, "tile": tile_used},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": peak_unit,
                      "frac": achieved / peak, "traffic": traffic,
                      "counts": "the method's own flops, 4*8^N (re, im x 2 flop per term)%s; executed "
-                               "matrix-core flops (%d planes) in executed_*" % (", quartered" if herm else "", planes),
+                               "matrix-core %s (%d %s planes) in executed_*"
+                               % (", quartered" if herm else "", "int8 ops" if a.algo == "split_i8" else "flops",
+                                  planes, "int8 digit" if a.algo == "split_i8" else DTYPE[a.algo]),
                      "flops_per_launch": flops_useful,
                      "executed_tflops": executed, "executed_frac": executed / peak,
                      "executed_flops_per_launch": flops_exec,
                      "launch_ms": mean_launch, "launch_ms_median": float(np.median(launch_ms)),
-                     "kernel": "%s%s (%s, tile %d)" % ("contract_lds_kernel" if tile_used >= 13 else "contract_kernel",
-                                                      " <..., HERM=true>" if herm else "", a.algo, tile_used),
+                     "kernel": ("i8_contract_kernel (split_i8, two walks over K)" if a.algo == "split_i8" else
+                                "%s%s (%s, tile %d)" % ("contract_lds_kernel" if tile_used >= 13 else "contract_kernel",
+                                                        " <..., HERM=true>" if herm else "", a.algo, tile_used)),
                      "pack_ms": pack_ms},
         "cpu_baseline": cpu,
     }

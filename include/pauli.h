@@ -101,7 +101,28 @@ typedef enum pauli_algo {
      * max|c|; 2.6e-8 of max|c| measured at N = 14.  Up to N = 8
      * it is the binary64 one-kernel path.  Same directions and range as
      * PAULI_ALGO_FWHT. */
-    PAULI_ALGO_FWHT_F32 = 5
+    PAULI_ALGO_FWHT_F32 = 5,
+    /* Fixed point on int8 matrix cores, the same contraction as the splits
+     * (section 2, Eq. (c_def_in_terms_of_fn)): a reduction pass finds the
+     * largest |re|, |im| of each input, m = mm 2^e (1 <= mm < 2); every
+     * component g becomes the integer q = rint(g 2^-e 8355711 / mm),
+     * |q| <= 8355711, split into three balanced base-256 digits (the top one
+     * at most 127 in magnitude); int8 MFMA sums +-1 times each digit exactly
+     * in int32 (two walks over K: the two upper digit planes, then the
+     * lowest), and the digit sums are combined exactly in binary64 and
+     * scaled by 2^(e-N) mm / 8355711.  The contraction rounds nothing: each
+     * coefficient is off by at most m / (2 * 8355711) (6.0e-8 m) per
+     * component from the quantisation, plus the output's own rounding.
+     * The bound is relative to the largest entry of the matrix, not to each
+     * entry (fixed point); for iid inputs the error is about 2e-7 of
+     * max|c| (2.2e-7 at N = 14).  Three quarters of SPLIT_FP16's
+     * matrix-core time at int8's doubled rate.  pauli_decompose and
+     * pauli_decompose_noalloc only (forward, equal-order batches, one tile
+     * shape), also split into pauli_pack / pauli_contract mode 0; the
+     * other entry points and modes return PAULI_EUNSUPPORTED.  An infinite
+     * or NaN component makes every coefficient of that matrix NaN; an
+     * all-zero matrix gives zeros. */
+    PAULI_ALGO_SPLIT_I8 = 6
 } pauli_algo;
 
 typedef struct pauli_opts {
@@ -235,7 +256,8 @@ int pauli_batched_tile_selected(int count, const int* N, int algo);
  * pauli_decompose_backward need for (algo, N, batch) when the caller supplies
  * opts->workspace: 12 bytes per matrix element for SPLIT_BF16 (six bf16
  * planes), 8 for SPLIT_FP16 (four fp16 planes) plus its prescale exponent and
- * partial maxima, 8 for FP32 (N < 5 counts as N = 5 for these three);
+ * partial maxima, 8 for FP32, 6 for SPLIT_I8 (six int8 planes) plus its
+ * scale record and partial maxima (N < 5 counts as N = 5 for these four);
  * 16 for FWHT and 8 for FWHT_F32 from N = 9 on, none below; 0 for FP64_GRAY.
  * A smaller workspace fails with PAULI_ENOMEM.  Returns 0 for invalid
  * arguments.
@@ -263,7 +285,8 @@ size_t pauli_workspace_bytes(int algo, int N, int batch);
  */
 int pauli_autotune(int N_min, int N_max, const pauli_opts* opts);
 
-/* Number of tile configurations for `algo` (ids 1..count). */
+/* Number of tile configurations for `algo` (ids 1..count; 1 for FP64_GRAY,
+ * FWHT, FWHT_F32 and SPLIT_I8, which have one shape each). */
 int pauli_tile_count(int algo);
 
 /*
@@ -278,7 +301,8 @@ int pauli_tile_valid(int algo, int tile, int N);
  * N: a valid tile of pauli_tile_valid that is not LDS-staged (ids 1..12). */
 int pauli_tile_valid_hermitian(int algo, int tile, int N);
 
-/* Tile id pauli_decompose would use for (algo, N) right now. */
+/* Tile id pauli_decompose would use for (algo, N) right now; 0 for the
+ * algorithms without a tile choice (FP64_GRAY, FWHT, FWHT_F32, SPLIT_I8). */
 int pauli_tile_selected(int algo, int N);
 
 /* Tile id pauli_decompose_hermitian would use for (algo, N) right now (0 if
@@ -331,9 +355,11 @@ size_t pauli_coeffs_at_workspace_bytes(int N, int count);
 const char* pauli_last_error(void);
 
 /*
- * The two passes of the matrix-core algorithms (SPLIT_BF16, FP32), for
- * callers that schedule or time them separately; opts->workspace is required
- * (pauli_workspace_bytes).  mode: 0 = decompose, 1 = reconstruct,
+ * The two passes of the matrix-core algorithms (SPLIT_BF16, SPLIT_FP16,
+ * FP32, and SPLIT_I8 for mode 0 only: its pack is the scale reduction, the
+ * quantisation and the digit split), for callers that schedule or time them
+ * separately; opts->workspace is required (pauli_workspace_bytes).  mode:
+ * 0 = decompose, 1 = reconstruct,
  * 2 = backward, 3 = decompose a Hermitian matrix (pauli_decompose_hermitian;
  * its pack writes only the parts of the operand that the half walk of any
  * tile reads, its contraction takes the register-ring tiles of

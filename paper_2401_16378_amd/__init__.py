@@ -25,7 +25,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpauli.so")
 
-ALGOS = {"fp64_gray": 0, "fp32": 1, "split_bf16": 2, "fwht": 3, "split_fp16": 4, "fwht_f32": 5}
+ALGOS = {"fp64_gray": 0, "fp32": 1, "split_bf16": 2, "fwht": 3, "split_fp16": 4, "fwht_f32": 5, "split_i8": 6}
 _DT = {torch.complex64: 0, torch.complex128: 1}
 _TORCH_DT = {0: torch.complex64, 1: torch.complex128}
 _STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSUPPORTED", 3: "EHIP", 4: "ENOMEM"}

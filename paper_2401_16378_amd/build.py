@@ -25,7 +25,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpauli.so")
 ARCH = "gfx950"
-SOURCES = ["api.cpp", "gray_fp64.hip", "mfma.hip", "batched.hip", "strings.hip", "fwht.hip"]
+SOURCES = ["api.cpp", "gray_fp64.hip", "mfma.hip", "mfma_i8.hip", "batched.hip", "strings.hip", "fwht.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(HERE, "..", "include")]

@@ -50,8 +50,11 @@ size_t elem_bytes(int dtype) { return dtype == PAULI_C128 ? 16 : 8; }
 bool valid_dtype(int d) { return d == PAULI_C64 || d == PAULI_C128; }
 bool valid_algo(int a) {
     return a == PAULI_ALGO_FP64_GRAY || a == PAULI_ALGO_FP32 || a == PAULI_ALGO_SPLIT_BF16 || a == PAULI_ALGO_FWHT ||
-           a == PAULI_ALGO_SPLIT_FP16 || a == PAULI_ALGO_FWHT_F32;
+           a == PAULI_ALGO_SPLIT_FP16 || a == PAULI_ALGO_FWHT_F32 || a == PAULI_ALGO_SPLIT_I8;
 }
+
+// Fixed-point int8 algorithm: forward decomposition only, one tile shape.
+bool is_i8(int a) { return a == PAULI_ALGO_SPLIT_I8; }
 
 // Fast Walsh-Hadamard algorithms (binary64 or binary32 intermediate).
 bool is_fwht(int a) { return a == PAULI_ALGO_FWHT || a == PAULI_ALGO_FWHT_F32; }
@@ -173,6 +176,8 @@ int check_common(const void* in, int N, int batch, const void* out, const pauli_
             overlaps(o.workspace, o.workspace_bytes, out, count * elem_bytes(o.out_dtype)))
             return fail(PAULI_EINVAL, "%s: workspace overlaps input or output", fn);
     }
+    if (o.tile > 1 && is_i8(o.algo))
+        return fail(PAULI_EINVAL, "%s: tile %d not valid for algo %d (one tile shape)", fn, o.tile, o.algo);
     if (o.tile > 0 && is_mfma(o.algo) && !mfma_tile_valid(planes_of(o.algo), o.tile, N))
         return fail(PAULI_EINVAL, "%s: tile %d not valid for algo %d at N=%d", fn, o.tile, o.algo, N);
     return PAULI_OK;
@@ -243,6 +248,24 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
             if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
             if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
             e = launch_fwht(dir, in, in128, out, out128, N, batch, scale, narrow, ws, s);
+            const hipError_t ef = hipFreeAsync(ws, s);
+            if (e == hipSuccess) e = ef;
+        }
+    } else if (is_i8(o.algo)) {
+        if (dir != FORWARD || herm)
+            return fail(PAULI_EUNSUPPORTED, "%s: algo %d computes the forward decomposition only", fn, o.algo);
+        const size_t need = i8_workspace_bytes(N, batch);
+        void* ws = o.workspace;
+        if (ws) {
+            if (o.workspace_bytes < need)
+                return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
+                            o.workspace_bytes);
+            e = launch_i8(in, in128, out, out128, N, batch, scale, ws, s);
+        } else {
+            hipMemPool_t pool;
+            if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
+            if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
+            e = launch_i8(in, in128, out, out128, N, batch, scale, ws, s);
             const hipError_t ef = hipFreeAsync(ws, s);
             if (e == hipSuccess) e = ef;
         }
@@ -334,6 +357,7 @@ int pauli_decompose_noalloc(const void* G, int N, int batch, void* out, const pa
     size_t need = 0;
     if (is_fwht(o.algo)) need = fwht_workspace_bytes(N, batch, o.algo == PAULI_ALGO_FWHT_F32);
     else if (is_mfma(o.algo)) need = mfma_workspace_bytes(planes_of(o.algo), N, batch);
+    else if (is_i8(o.algo)) need = i8_workspace_bytes(N, batch);
     if (need > NOALLOC_SCRATCH_BYTES)
         return fail(PAULI_ENOMEM, "%s: algo %d at N=%d, batch %d needs %zu bytes of scratch; the fixed scratch holds %zu",
                     fn, o.algo, N, batch, need, NOALLOC_SCRATCH_BYTES);
@@ -387,16 +411,20 @@ static int stage_check(int N, int batch, int mode, const pauli_opts& o, const ch
     if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
     if (batch < 1) return fail(PAULI_EINVAL, "%s: batch=%d must be >= 1", fn, batch);
     if (mode < 0 || mode > 3) return fail(PAULI_EINVAL, "%s: mode %d not in {0, 1, 2, 3}", fn, mode);
-    if (!is_mfma(o.algo)) return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes", fn, o.algo);
+    if (!is_mfma(o.algo) && !(is_i8(o.algo) && mode == 0))
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes%s", fn, o.algo,
+                    is_i8(o.algo) ? " except for mode 0" : "");
     if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
         return fail(PAULI_EINVAL, "%s: unknown dtype (in %d, out %d)", fn, o.in_dtype, o.out_dtype);
-    const size_t need = mfma_workspace_bytes(planes_of(o.algo), N, batch);
+    const size_t need = is_i8(o.algo) ? i8_workspace_bytes(N, batch) : mfma_workspace_bytes(planes_of(o.algo), N, batch);
     if (!o.workspace || o.workspace_bytes < need)
         return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
                     o.workspace ? o.workspace_bytes : (size_t)0);
     if ((uintptr_t)o.workspace % 256) return fail(PAULI_EINVAL, "%s: workspace must be 256-byte aligned", fn);
-    if (o.tile < 0 || (o.tile > 0 && !(mode == 3 ? mfma_tile_valid_hermitian(planes_of(o.algo), o.tile, N)
-                                                 : mfma_tile_valid(planes_of(o.algo), o.tile, N))))
+    if (is_i8(o.algo)) {
+        if (o.tile < 0 || o.tile > 1) return fail(PAULI_EINVAL, "%s: tile %d not valid at N=%d", fn, o.tile, N);
+    } else if (o.tile < 0 || (o.tile > 0 && !(mode == 3 ? mfma_tile_valid_hermitian(planes_of(o.algo), o.tile, N)
+                                                        : mfma_tile_valid(planes_of(o.algo), o.tile, N))))
         return fail(PAULI_EINVAL, "%s: tile %d not valid at N=%d", fn, o.tile, N);
     return PAULI_OK;
 }
@@ -412,7 +440,8 @@ int pauli_pack(const void* in, int N, int batch, int mode, const pauli_opts* opt
     if (overlaps(in, bytes, o.workspace, o.workspace_bytes))
         return fail(PAULI_EINVAL, "%s: workspace overlaps the input", fn);
     const hipError_t e =
-        mode == 3 ? launch_mfma_pack_hermitian(planes_of(o.algo), in, o.in_dtype == PAULI_C128, N, batch, o.workspace,
+        is_i8(o.algo) ? launch_i8_pack(in, o.in_dtype == PAULI_C128, N, batch, o.workspace, (hipStream_t)o.stream)
+        : mode == 3 ? launch_mfma_pack_hermitian(planes_of(o.algo), in, o.in_dtype == PAULI_C128, N, batch, o.workspace,
                                                (hipStream_t)o.stream)
                   : launch_mfma_pack(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), in, o.in_dtype == PAULI_C128, N,
                                      batch, o.workspace, (hipStream_t)o.stream);
@@ -433,7 +462,9 @@ int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts
         return fail(PAULI_EINVAL, "%s: workspace overlaps the output", fn);
     const double scale = mode == 1 ? 1.0 : 1.0 / (double)(1u << N);
     const hipError_t e =
-        mode == 3 ? launch_mfma_contract_hermitian(planes_of(o.algo), o.workspace, out, o.out_dtype == PAULI_C128, N,
+        is_i8(o.algo) ? launch_i8_contract(o.workspace, out, o.out_dtype == PAULI_C128, N, batch, scale,
+                                           (hipStream_t)o.stream)
+        : mode == 3 ? launch_mfma_contract_hermitian(planes_of(o.algo), o.workspace, out, o.out_dtype == PAULI_C128, N,
                                                    batch, scale, pick_tile_hermitian(o.algo, N, o.tile),
                                                    (hipStream_t)o.stream)
                   : launch_mfma_contract(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), o.workspace, out,
@@ -448,11 +479,12 @@ size_t pauli_workspace_bytes(int algo, int N, int batch) {
     if (!valid_algo(algo) || N < 0 || N > N_MAX || batch < 1) return 0;
     if (algo == PAULI_ALGO_FP64_GRAY) return 0;
     if (is_fwht(algo)) return fwht_supported(N) ? fwht_workspace_bytes(N, batch, algo == PAULI_ALGO_FWHT_F32) : 0;
+    if (is_i8(algo)) return i8_workspace_bytes(N, batch);
     return mfma_workspace_bytes(planes_of(algo), N, batch);
 }
 
 int pauli_tile_count(int algo) {
-    if (algo == PAULI_ALGO_FP64_GRAY || is_fwht(algo)) return 1;
+    if (algo == PAULI_ALGO_FP64_GRAY || is_fwht(algo) || is_i8(algo)) return 1;
     if (!valid_algo(algo)) return 0;
     return mfma_tile_count(planes_of(algo));
 }
@@ -460,6 +492,7 @@ int pauli_tile_count(int algo) {
 int pauli_tile_valid(int algo, int tile, int N) {
     if (algo == PAULI_ALGO_FP64_GRAY) return tile == 1 && N >= 0 && N <= N_MAX ? 1 : 0;
     if (is_fwht(algo)) return tile == 1 && fwht_supported(N) ? 1 : 0;
+    if (is_i8(algo)) return tile == 1 && N >= 0 && N <= N_MAX ? 1 : 0;
     if (!valid_algo(algo) || N < 0 || N > N_MAX) return 0;
     return mfma_tile_valid(planes_of(algo), tile, N) ? 1 : 0;
 }

@@ -1,0 +1,214 @@
+"""The fixed-point int8 path (split_i8) through the C ABI.
+
+Against the oracle: every coefficient at N = 0..10 (ragged N < 5 padded to
+32, the one-slice-at-a-time kernel below N = 8) and at the N = 12 Hermitian
+workload, a seeded 65,536-coefficient sample at N = 14 plus all coefficients
+against the binary64 Gray kernel.  The bar is the decomposition's 1e-6 of
+max|c| and, for every input, the path's own bound: the quantisation moves
+each component of G by at most m / (2L) (m the largest |Re|, |Im| of the
+matrix, L = 8355711), so each coefficient is off by at most sqrt(2) m / (2L)
+in modulus, plus the output's rounding.
+
+Exact properties: the int8 sums are exact integers, so wherever the
+quantisation itself is exact the result is the oracle's up to the final
+scaling, and the conjugate, transpose and power-of-two scaling identities
+hold bit for bit (the quantised matrix transforms the same way).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+L8 = 8355711.0
+
+
+def lib():
+    import paper_2401_16378_amd as p
+    p.load_library()
+    return p
+
+
+def threads():
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def dec(G, out_dtype=None):
+    return lib().decompose(dev(G), algo="split_i8", out_dtype=out_dtype).cpu().numpy()
+
+
+def bound(G, ref, out_dtype):
+    """The path's error bound in modulus: quantisation + output rounding."""
+    m = max(np.abs(G.real).max(), np.abs(G.imag).max())
+    rnd = (2.0 ** -24 if out_dtype == torch.complex64 else 2.0 ** -52) * np.abs(ref).max()
+    return np.sqrt(2.0) * (m / (2 * L8) + rnd) * (1 + 1e-9)
+
+
+def check(G, c, ref, out_dtype):
+    err = np.abs(c.astype(np.complex128) - ref).max()
+    assert err <= bound(G, ref, out_dtype), (err, bound(G, ref, out_dtype))
+    return err / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("N", list(range(0, 11)))
+def test_vs_oracle(N):
+    G = workloads.iid_complex(N, 8800 + N, np.complex64)
+    ref = oracle.decompose(G.astype(np.complex128), threads=threads())
+    rel = check(G, dec(G), ref, torch.complex64)
+    assert rel <= 1e-6, rel
+
+
+@pytest.mark.parametrize("N", [3, 7, 10])
+def test_complex128_in_and_out(N):
+    """Binary64 input is quantised from its binary64 values (the scale is
+    taken in binary64 too), binary64 output keeps the exact sums' scaling."""
+    G = workloads.iid_complex(N, 8850 + N, np.complex128)
+    ref = oracle.decompose(G, threads=threads())
+    rel = check(G, dec(G, torch.complex128), ref, torch.complex128)
+    assert rel <= 1e-6, rel
+
+
+def test_n12_hermitian_full():
+    """The N = 12 Hermitian workload, every coefficient; Hermitian input gives
+    exactly real coefficients (each pair i, i ^ x sums to a real or an
+    imaginary integer before the phase)."""
+    G = workloads.hermitian(12, workloads.SEED_N12)
+    c = dec(G)
+    ref = oracle.decompose(G.astype(np.complex128), threads=threads())
+    rel = check(G, c, ref, torch.complex64)
+    assert rel <= 1e-6, rel
+    assert np.all(c.imag == 0)
+
+
+def test_n14_hermitian_sample_and_gray():
+    """The N = 14 Hermitian workload in the benchmark's launch configuration:
+    65,536 seeded coefficients against the oracle, all coefficients against
+    the binary64 Gray kernel, exactly real, Parseval."""
+    p = lib()
+    N = 14
+    G = workloads.hermitian(N, workloads.SEED_N14)
+    Gd = dev(G)
+    c = p.decompose(Gd, algo="split_i8").cpu().numpy()
+    c64 = p.decompose(Gd, algo="fp64_gray", out_dtype=torch.complex128).cpu().numpy()
+    g2 = float((Gd.to(torch.complex128).abs() ** 2).sum().item()) / (1 << N)
+    del Gd
+    torch.cuda.empty_cache()
+    ns = workloads.sample_indices(4 ** N, 65536, seed=workloads.SEED_SAMPLE + N)
+    ref = oracle.coeffs_at(G.astype(np.complex128), ns, threads=threads())
+    idx = ns.astype(np.int64)
+    err = np.abs(c[idx].astype(np.complex128) - ref).max()
+    assert err <= bound(G, ref, torch.complex64)
+    assert err / np.abs(ref).max() <= 1e-6
+    rel = check(G, c, c64, torch.complex64)
+    assert rel <= 1e-6, rel
+    assert np.all(c.imag == 0)
+    s = float((np.abs(c.astype(np.complex128)) ** 2).sum())
+    assert abs(s - g2) <= 1e-6 * g2
+
+
+def test_exact_when_quantisation_is():
+    """Components in {0, +-1} 2^5 (the largest a power of two, so every q is 0
+    or +-L): the sums are exact and only the last scaling rounds."""
+    N = 9
+    rng = np.random.default_rng(8900)
+    G = (rng.integers(-1, 2, (1 << N, 1 << N)) + 1j * rng.integers(-1, 2, (1 << N, 1 << N))) * 32.0
+    G[0, 0] = 32.0
+    ref = oracle.decompose(G, threads=threads())
+    c = dec(G, torch.complex128)
+    assert np.abs(c - ref).max() <= 4e-16 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("N", [1, 3])
+def test_one_hot_strings_exact(N):
+    """G = P_m gives c = e_m exactly (complex64 output), for every m."""
+    D = 1 << N
+    for m in range(4 ** N):
+        P = np.array([[oracle.pauli_element(m, N, i, j) for j in range(D)] for i in range(D)], np.complex64)
+        c = dec(P)
+        want = np.zeros(4 ** N, np.complex64)
+        want[m] = 1
+        assert np.array_equal(c, want), m
+
+
+def test_conjugate_transpose_and_scaling_bit_exact():
+    """c(G^H) = conj c(G) and c(G^T)_n = (-1)^{#Y(n)} c(G)_n bit for bit, and
+    c(2^k G) = 2^k c(G) bit for bit (the quantised integers are the same)."""
+    N = 9
+    G = workloads.iid_complex(N, 8910, np.complex128)
+    c = dec(G, torch.complex128)
+    n = np.arange(4 ** N)
+    ny = np.zeros_like(n)                      # number of Y operators in string n
+    for t in range(N):
+        b0, b1 = (n >> (2 * t)) & 1, (n >> (2 * t + 1)) & 1
+        ny += (b0 ^ b1) & b1                   # Y on qubit t: x_t = z_t = 1
+    sign = np.where(ny & 1, -1.0, 1.0)
+    assert np.array_equal(dec(G.conj().T, torch.complex128), c.conj())
+    assert np.array_equal(dec(G.T, torch.complex128), sign * c)
+    for k in (-40, 40):
+        assert np.array_equal(dec(np.ldexp(G.real, k) + 1j * np.ldexp(G.imag, k), torch.complex128),
+                              np.ldexp(c.real, k) + 1j * np.ldexp(c.imag, k))
+
+
+def test_batch_scales_are_per_matrix():
+    """A batch of matrices 2^40 apart in size: each member equals its own
+    single call bit for bit (one scale record per matrix)."""
+    p = lib()
+    N = 8
+    mats = [workloads.iid_complex(N, 8920 + k, np.complex128) * 2.0 ** (40 * (k - 1)) for k in range(3)]
+    B = dev(np.stack(mats))
+    cb = p.decompose(B, algo="split_i8").cpu().numpy()
+    for k, G in enumerate(mats):
+        assert np.array_equal(cb[k], dec(G)), k
+
+
+def test_zero_and_non_finite():
+    """An all-zero matrix gives zeros; an infinite or NaN component makes every
+    coefficient of its matrix NaN and leaves the other batch members alone."""
+    p = lib()
+    N = 6
+    D = 1 << N
+    assert np.array_equal(dec(np.zeros((D, D), np.complex64)), np.zeros(D * D, np.complex64))
+    G = workloads.iid_complex(N, 8930, np.complex64)
+    good = dec(G)
+    for bad in (np.inf, -np.inf, np.nan):
+        H = G.copy()
+        H[3, 5] = complex(1.0, bad)
+        cb = p.decompose(dev(np.stack([H, G])), algo="split_i8").cpu().numpy()
+        assert np.all(np.isnan(cb[0].real)) and np.all(np.isnan(cb[0].imag))
+        assert np.array_equal(cb[1], good)
+
+
+def test_mixed_magnitudes_within_the_fixed_point_bound():
+    """Rows scaled by 2^-20 .. 2^20: entries far below the largest one keep
+    only the absolute precision m / (2L), so the error relative to max|c| can
+    exceed the floating-point splits' while staying within the stated bound."""
+    N = 9
+    D = 1 << N
+    G = workloads.iid_complex(N, 8940, np.complex128)
+    G *= np.ldexp(1.0, np.random.default_rng(8941).integers(-20, 21, D))[:, None]
+    ref = oracle.decompose(G, threads=threads())
+    check(G, dec(G, torch.complex128), ref, torch.complex128)
+
+
+def test_forward_only():
+    """The adjoint, Hermitian, two-pass and batched entry points refuse the
+    algorithm (PAULI_EUNSUPPORTED) without launching anything."""
+    p = lib()
+    N = 6
+    G = dev(workloads.iid_complex(N, 8950, np.complex64))
+    c = torch.zeros(4 ** N, dtype=torch.complex64, device="cuda")
+    for call in (lambda: p.decompose_backward(c, algo="split_i8"),
+                 lambda: p.reconstruct(c, algo="split_i8"),
+                 lambda: p.decompose_hermitian(G, algo="split_i8"),
+                 lambda: p.decompose_batched([G], algo="split_i8")):
+        with pytest.raises(p.PauliError) as e:
+            call()
+        assert e.value.status == 2

@@ -13,7 +13,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = {"split_bf16": 2, "split_fp16": 4, "fp32": 1, "fwht": 3, "fwht_f32": 5, "fp64_gray": 0}
+ALGOS = {"split_bf16": 2, "split_fp16": 4, "fp32": 1, "fwht": 3, "fwht_f32": 5, "fp64_gray": 0, "split_i8": 6}
 
 
 def lib():
