@@ -8,20 +8,22 @@ Workload: one complex64 Hermitian 16384 x 16384 matrix (N = 14 qubits),
 G = (A + A^H)/2 with A iid complex N(0,1) (numpy PCG64, seed 1014), resident in
 HBM before timing.  One step = one full decomposition into all 4^14
 coefficients (complex64 out) with a split matrix-core path, by default the
-two-plane fp16 split (--algo split_bf16: the three-plane bf16 split): the
-pack (prescale reduction, XOR gather, split, operand layout) then the
-contraction kernel (+-1 contraction, binary64 recombination, phase, 2^-N,
+fixed-point int8 path (--algo split_fp16: the two-plane fp16 split,
+--algo split_bf16: the three-plane bf16 split): the pack (scale reduction,
+XOR gather, quantisation or split, operand layout) then the contraction
+kernel (+-1 contraction, exact or binary64 recombination, phase, 2^-N,
 store).
 
 Printed: one JSON line with coefficients/s over the whole step, the roofline
-of the contraction kernel (the method's own 4 * 8^N flops per launch / its
-mean launch time from HIP events on its stream, against the 2.5 PFLOP/s
-dense fp16/bf16 peak; the executed matrix-core flops of the split in
-separate fields), the binary64 Gray-code GPU kernel on the same input for
-the speed ratio and the error (max |c - c_fp64| / max |c_fp64|), the other
-split path timed on the same input, and the CPU oracle timed on a bounded
-sample of the same coefficients on the host's cores (which also checks
-those coefficients).
+of the contraction kernel (the method's own 4 * 8^N operations per launch /
+its mean launch time from HIP events on its stream, against the dense
+matrix-core peak of the path's data type: 5.0 POP/s int8, 2.5 PFLOP/s
+fp16/bf16; the executed matrix-core operations of the split in separate
+fields), the binary64 Gray-code GPU kernel on the same input for the speed
+ratio and the error (max |c - c_fp64| / max |c_fp64|), another split path
+timed on the same input (split_fp16 beside split_i8), and the CPU oracle
+timed on a bounded sample of the same coefficients on the host's cores
+(which also checks those coefficients).
 """
 from __future__ import annotations
 
@@ -140,7 +142,7 @@ def bench_batch(a):
     G = [torch.from_numpy(m).to(dev) for m in mats]
     outs = [torch.empty(1 << (2 * n), dtype=torch.complex64, device=dev) for n in Ns]
     stream = torch.cuda.current_stream(dev)
-    algo = a.algo if a.algo in PLANES else "split_fp16"
+    algo = a.algo
     tile = pauli.autotune_batched(G, algo=algo, outs=outs)
     plan = pauli.BatchPlan(G, algo=algo, outs=outs)   # arguments marshalled once, as a serving loop would
     ms = timed(plan.run, a.steps, a.warmup, stream)
@@ -183,7 +185,7 @@ def bench_backward(a):
     wd = torch.from_numpy(w).to(dev).to(torch.float32)
     stream = torch.cuda.current_stream(dev)
 
-    algo = a.algo if a.algo in PLANES else "split_fp16"
+    algo = a.algo
 
     def step():
         g = Gd.detach().requires_grad_(True)
@@ -423,7 +425,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--N", type=int, default=14)
-    ap.add_argument("--algo", default="split_fp16")
+    ap.add_argument("--algo", default=None,
+                    help="path to time (default: split_i8 for n14, split_fp16 for hermitian, batch and "
+                         "backward, fwht for fwht)")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other split path")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -433,6 +437,10 @@ def main():
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a device copy of this many GiB (counter calibration)")
     a = ap.parse_args()
+    if a.algo is None:
+        a.algo = {"n14": "split_i8", "fwht": "fwht"}.get(a.workload, "split_fp16")
+    if a.workload in ("batch", "backward") and a.algo not in ("split_bf16", "split_fp16", "fp32"):
+        raise SystemExit("bench.py: the %s workload runs split_bf16, split_fp16 or fp32, not %s" % (a.workload, a.algo))
     if a.gpus != 1:
         print("bench.py: the decomposition runs on one GPU (it is not sharded across devices); --gpus %d is not supported" % a.gpus,
               file=sys.stderr)

@@ -54,7 +54,7 @@ constexpr int I8_SLICE = I8_NPL * FRAG;  // bytes per slice of one 32-mask slab
 constexpr int I8_WAVES = 4, I8_RB = 4;   // tile: 4 waves x 4 x 32 rows x 32 flip masks
 constexpr int I8_MT = I8_WAVES * I8_RB * 32;
 constexpr int I8_PF1 = 4, I8_PF2 = 8;    // ring depth (slices) of the two passes
-constexpr int I8_STEP = 8;               // slices per unrolled step
+constexpr int I8_STEP = 16;              // slices per unrolled step (8 when a slab has only 8)
 
 // Scale record of one matrix (see the header comment): q = rint(ldexp(g, -e) * s),
 // value = ldexp(sum * r, e) with r = mm / L times the caller's scale.
@@ -285,15 +285,16 @@ __device__ inline i32x4 sign_fragment(int lane) {
 // against slice s (K block s) is the Sylvester block times
 // (-1)^{popc((Pw/32 + rb) & s)}; Pw is a multiple of 128, so that sign is
 // (-1)^{popc((Pw/32) & s)} (one per group of 4 slices) times
-// (-1)^{popc(rb & s)} (fixed by s mod 4).  SMALL (nS < I8_STEP, N < 8): one
-// slice at a time with the signs evaluated at run time.  slab, nS and Pw are
+// (-1)^{popc(rb & s)} (fixed by s mod 4).  STEP slices per unrolled step;
+// STEP = 1 (nS < 8, N < 8): one slice at a time with the signs evaluated at
+// run time.  slab, nS and Pw are
 // uniform; everything per lane is derived here from the thread index, so
 // nothing of it stays live across the walks.
-template <int NP, int P0, int PF, bool SMALL>
+template <int NP, int P0, int PF, int STEP>
 __device__ __attribute__((always_inline)) inline void walk(const unsigned char* __restrict__ slab, uint32_t nS,
                                                            uint32_t Pw, i32x16 (&acc)[NP][I8_RB][2]) {
     constexpr int NF = 2 * NP;
-    static_assert(I8_STEP % PF == 0 && I8_STEP % 4 == 0, "ring and sign period nest in a step");
+    static_assert(STEP == 1 || (STEP % PF == 0 && STEP % 4 == 0), "ring and sign period nest in a step");
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63;
@@ -307,13 +308,19 @@ __device__ __attribute__((always_inline)) inline void walk(const unsigned char* 
 #pragma unroll
         for (int f = 0; f < NF; ++f) ring[slot][f] = *(const i32x4*)(p + f * FRAG);
     };
-    if constexpr (!SMALL) {
+    if constexpr (STEP > 1) {
 #pragma unroll
         for (int k = 0; k < PF; ++k) fetch(k, (uint32_t)k);
-        for (uint32_t s0 = 0; s0 < nS; s0 += I8_STEP) {
+        // Wait for the prefetch once here: with these loads still in flight
+        // at the loop head, the compiler's wait there (merging the prefetch
+        // with the refills of the previous step) is a full drain of every
+        // outstanding load, once per step; with them complete it waits only
+        // for the slot the step starts with.
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0); expcnt, lgkmcnt untouched
+        for (uint32_t s0 = 0; s0 < nS; s0 += STEP) {
             i32x4 A0, A1;   // the group's sign applied: A0 for popc(rb & s) even, A1 odd
 #pragma unroll
-            for (int uu = 0; uu < I8_STEP; ++uu) {
+            for (int uu = 0; uu < STEP; ++uu) {
                 const int slot = uu % PF;
                 if (uu % 4 == 0) {
                     const bool gneg = __popc(pw5 & (s0 + (uint32_t)uu)) & 1;
@@ -363,7 +370,7 @@ struct I8Params {
 // Output tile (slab xb, rows mb * 512 ..) of matrix blockIdx.y.  Waves whose
 // rows lie beyond Dp (N < 9) skip the walks but take part in the epilogue
 // barriers.  LDS: 4 waves x 1024 coefficients of staging.
-template <bool SMALL>
+template <int STEP>
 __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int N = prm.N;
@@ -392,7 +399,7 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[p][rb][cb][r] = 0;
     if (Pw < Dp) {
-        walk<2, 0, I8_PF1, SMALL>(slab, nS, Pw, acc);
+        walk<2, 0, I8_PF1, STEP>(slab, nS, Pw, acc);
 #pragma unroll
         for (int rb = 0; rb < I8_RB; ++rb)
 #pragma unroll
@@ -401,7 +408,7 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[1][rb][cb][r] = 0;
             }
-        walk<1, 2, I8_PF2, SMALL>(slab, nS, Pw, reinterpret_cast<i32x16(&)[1][I8_RB][2]>(acc[1]));
+        walk<1, 2, I8_PF2, STEP>(slab, nS, Pw, reinterpret_cast<i32x16(&)[1][I8_RB][2]>(acc[1]));
     }
     const auto& hi = acc[0];
     const i32x16(&lo)[1][I8_RB][2] = reinterpret_cast<const i32x16(&)[1][I8_RB][2]>(acc[1]);
@@ -470,12 +477,13 @@ hipError_t launch_i8_contract(const void* ws, void* out, bool out128, int N, int
     const uint32_t Dp = padded_dim(N);
     const uint32_t nMB = (Dp + I8_MT - 1) / I8_MT, nXB = Dp / XT;
     const int lds = I8_WAVES * 1024 * (out128 ? 16 : 8);
-    const bool small = Dp / I8_SK < (uint32_t)I8_STEP;
-    auto kern = small ? i8_contract_kernel<true> : i8_contract_kernel<false>;
+    // slices per slab: a power of two, so a multiple of the step it is given
+    const uint32_t nS = Dp / I8_SK;
+    auto kern = nS >= (uint32_t)I8_STEP ? i8_contract_kernel<I8_STEP> : (nS >= 8u ? i8_contract_kernel<8> : i8_contract_kernel<1>);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     I8Params p = {ws, out, N, out128 ? 1 : 0, scale, i8_scales(const_cast<void*>(ws), N, batch)};
-    hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(256), lds, s, p);
+    hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(I8_WAVES * 64), lds, s, p);
     return hipGetLastError();
 }
 
