@@ -70,7 +70,8 @@ FWHT_SOURCES = ["paper_2401_16378_amd/csrc/fwht.hip", "paper_2401_16378_amd/csrc
 FWHT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwht_n14.json")
 FWHT_F32_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwht_f32_n14.json")
 HERM_TRAFFIC_FILES = {"split_bf16": os.path.join(ROOT, "profiles", "traffic_hermitian_n14.json"),
-                      "split_fp16": os.path.join(ROOT, "profiles", "traffic_hermitian_fp16_n14.json")}
+                      "split_fp16": os.path.join(ROOT, "profiles", "traffic_hermitian_fp16_n14.json"),
+                      "split_i8": os.path.join(ROOT, "profiles", "traffic_hermitian_i8_n14.json")}
 
 
 def source_hash(sources=KERNEL_SOURCES) -> str:
@@ -426,7 +427,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--N", type=int, default=14)
     ap.add_argument("--algo", default=None,
-                    help="path to time (default: split_i8 for n14, split_fp16 for hermitian, batch and "
+                    help="path to time (default: split_i8 for n14 and hermitian, split_fp16 for batch and "
                          "backward, fwht for fwht)")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other split path")
     ap.add_argument("--tile", type=int, default=0)
@@ -438,7 +439,7 @@ def main():
                     help="also run a device copy of this many GiB (counter calibration)")
     a = ap.parse_args()
     if a.algo is None:
-        a.algo = {"n14": "split_i8", "fwht": "fwht"}.get(a.workload, "split_fp16")
+        a.algo = {"n14": "split_i8", "hermitian": "split_i8", "fwht": "fwht"}.get(a.workload, "split_fp16")
     if a.workload in ("batch", "backward") and a.algo not in ("split_bf16", "split_fp16", "fp32"):
         raise SystemExit("bench.py: the %s workload runs split_bf16, split_fp16 or fp32, not %s" % (a.workload, a.algo))
     if a.gpus != 1:
@@ -489,8 +490,6 @@ def main():
     if a.algo not in PLANES:
         raise SystemExit("bench.py: the n14 and hermitian workloads time a matrix-core algorithm (%s)"
                          % ", ".join(PLANES))
-    if herm and a.algo == "split_i8":
-        raise SystemExit("bench.py: split_i8 has no Hermitian variant")
     mode = 3 if herm else 0   # 3: pauli_decompose_hermitian split at the kernel boundary
 
     def step(mid=None):
@@ -600,7 +599,7 @@ def main():
         tile_used = 1   # its one tile shape
     traffic = None
     if N == 14 and herm and a.algo in HERM_TRAFFIC_FILES:
-        traffic = measured_traffic(HERM_TRAFFIC_FILES[a.algo])
+        traffic = measured_traffic(HERM_TRAFFIC_FILES[a.algo], TRAFFIC_SOURCES.get(a.algo, KERNEL_SOURCES))
     elif N == 14 and not herm and a.algo in TRAFFIC_FILES:
         traffic = measured_traffic(TRAFFIC_FILES[a.algo], TRAFFIC_SOURCES.get(a.algo, KERNEL_SOURCES))
     if herm:
@@ -629,7 +628,8 @@ def main():
                      "executed_tflops": executed, "executed_frac": executed / peak,
                      "executed_flops_per_launch": flops_exec,
                      "launch_ms": mean_launch, "launch_ms_median": float(np.median(launch_ms)),
-                     "kernel": ("i8_contract_kernel (split_i8, two walks over K)" if a.algo == "split_i8" else
+                     "kernel": ("i8_contract_kernel%s (split_i8, two walks over K)" % ("<16, HERM=true>" if herm else "<16>")
+                                if a.algo == "split_i8" else
                                 "%s%s (%s, tile %d)" % ("contract_lds_kernel" if tile_used >= 13 else "contract_kernel",
                                                         " <..., HERM=true>" if herm else "", a.algo, tile_used)),
                      "pack_ms": pack_ms},

@@ -116,10 +116,12 @@ typedef enum pauli_algo {
      * The bound is relative to the largest entry of the matrix, not to each
      * entry (fixed point); for iid inputs the error is about 2e-7 of
      * max|c| (2.2e-7 at N = 14).  Three quarters of SPLIT_FP16's
-     * matrix-core time at int8's doubled rate.  pauli_decompose and
-     * pauli_decompose_noalloc only (forward, equal-order batches, one tile
-     * shape), also split into pauli_pack / pauli_contract mode 0; the
-     * other entry points and modes return PAULI_EUNSUPPORTED.  An infinite
+     * matrix-core time at int8's doubled rate.  pauli_decompose,
+     * pauli_decompose_noalloc and pauli_decompose_hermitian (forward,
+     * equal-order batches, one tile shape; on Hermitian input the two give
+     * the same result bit for bit, the sums being exact), also split into
+     * pauli_pack / pauli_contract modes 0 and 3; the adjoint, batched and
+     * tuning entry points and modes 1, 2 return PAULI_EUNSUPPORTED.  An infinite
      * or NaN component makes every coefficient of that matrix NaN; an
      * all-zero matrix gives zeros. */
     PAULI_ALGO_SPLIT_I8 = 6
@@ -173,10 +175,12 @@ int pauli_decompose(const void* G, int N, int batch, void* out, const pauli_opts
  * the other the imaginary part, and where 2^b spans whole workgroup tiles
  * only one of the two row tiles is computed (a quarter of the general
  * work).  Every coefficient's imaginary part is written as exactly zero.
- * algo SPLIT_FP16, SPLIT_BF16 or FP32 (others: PAULI_EUNSUPPORTED);
- * register-ring tiles only (pauli_tile_valid_hermitian; a forced LDS-staged
- * tile fails with PAULI_EINVAL); pauli_tile_selected_hermitian gives the
- * tile it uses.  Limits, layouts, workspace and stream as pauli_decompose.
+ * algo SPLIT_FP16, SPLIT_BF16, FP32 or SPLIT_I8 (others:
+ * PAULI_EUNSUPPORTED); register-ring tiles only (pauli_tile_valid_hermitian;
+ * a forced LDS-staged tile fails with PAULI_EINVAL); pauli_tile_selected_hermitian
+ * gives the tile it uses (0 for SPLIT_I8, which has one shape: blocks of
+ * flip masks from 512 on take the half walk, and its exact integer sums make
+ * the result equal pauli_decompose's bit for bit).  Limits, layouts, workspace and stream as pauli_decompose.
  * The Hermitian property is the caller's promise and is not checked: the
  * kernel reads only one entry of most pairs (G[i xor x][i], G[i][i xor x]),
  * so for a non-Hermitian G the result is unspecified (finite input still
@@ -356,7 +360,7 @@ const char* pauli_last_error(void);
 
 /*
  * The two passes of the matrix-core algorithms (SPLIT_BF16, SPLIT_FP16,
- * FP32, and SPLIT_I8 for mode 0 only: its pack is the scale reduction, the
+ * FP32, and SPLIT_I8 for modes 0 and 3: its pack is the scale reduction, the
  * quantisation and the digit split), for callers that schedule or time them
  * separately; opts->workspace is required (pauli_workspace_bytes).  mode:
  * 0 = decompose, 1 = reconstruct,

@@ -252,7 +252,7 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
             if (e == hipSuccess) e = ef;
         }
     } else if (is_i8(o.algo)) {
-        if (dir != FORWARD || herm)
+        if (dir != FORWARD)
             return fail(PAULI_EUNSUPPORTED, "%s: algo %d computes the forward decomposition only", fn, o.algo);
         const size_t need = i8_workspace_bytes(N, batch);
         void* ws = o.workspace;
@@ -260,12 +260,12 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
             if (o.workspace_bytes < need)
                 return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
                             o.workspace_bytes);
-            e = launch_i8(in, in128, out, out128, N, batch, scale, ws, s);
+            e = launch_i8(in, in128, out, out128, N, batch, scale, ws, herm, s);
         } else {
             hipMemPool_t pool;
             if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
             if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
-            e = launch_i8(in, in128, out, out128, N, batch, scale, ws, s);
+            e = launch_i8(in, in128, out, out128, N, batch, scale, ws, herm, s);
             const hipError_t ef = hipFreeAsync(ws, s);
             if (e == hipSuccess) e = ef;
         }
@@ -376,7 +376,7 @@ size_t pauli_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 int pauli_decompose_hermitian(const void* G, int N, int batch, void* out, const pauli_opts* opts) {
     const char* fn = "pauli_decompose_hermitian";
     pauli_opts o = resolve(opts);
-    if (valid_algo(o.algo) && !is_mfma(o.algo))
+    if (valid_algo(o.algo) && !is_mfma(o.algo) && !is_i8(o.algo))
         return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no Hermitian variant (the matrix-core algorithms have)",
                     fn, o.algo);
     const int forced = o.tile;
@@ -384,7 +384,7 @@ int pauli_decompose_hermitian(const void* G, int N, int batch, void* out, const 
     int st = check_common(G, N, batch, out, o, fn);
     if (st != PAULI_OK) return st;
     if (forced < 0) return fail(PAULI_EINVAL, "%s: tile=%d must be >= 0", fn, forced);
-    if (forced > 0 && !mfma_tile_valid_hermitian(planes_of(o.algo), forced, N))
+    if (forced > 0 && (is_i8(o.algo) ? forced != 1 : !mfma_tile_valid_hermitian(planes_of(o.algo), forced, N)))
         return fail(PAULI_EINVAL, "%s: tile %d not valid for the Hermitian variant of algo %d at N=%d", fn, forced,
                     o.algo, N);
     o.tile = forced;
@@ -411,9 +411,9 @@ static int stage_check(int N, int batch, int mode, const pauli_opts& o, const ch
     if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
     if (batch < 1) return fail(PAULI_EINVAL, "%s: batch=%d must be >= 1", fn, batch);
     if (mode < 0 || mode > 3) return fail(PAULI_EINVAL, "%s: mode %d not in {0, 1, 2, 3}", fn, mode);
-    if (!is_mfma(o.algo) && !(is_i8(o.algo) && mode == 0))
+    if (!is_mfma(o.algo) && !(is_i8(o.algo) && (mode == 0 || mode == 3)))
         return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes%s", fn, o.algo,
-                    is_i8(o.algo) ? " except for mode 0" : "");
+                    is_i8(o.algo) ? " except for modes 0 and 3" : "");
     if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
         return fail(PAULI_EINVAL, "%s: unknown dtype (in %d, out %d)", fn, o.in_dtype, o.out_dtype);
     const size_t need = is_i8(o.algo) ? i8_workspace_bytes(N, batch) : mfma_workspace_bytes(planes_of(o.algo), N, batch);
@@ -440,7 +440,8 @@ int pauli_pack(const void* in, int N, int batch, int mode, const pauli_opts* opt
     if (overlaps(in, bytes, o.workspace, o.workspace_bytes))
         return fail(PAULI_EINVAL, "%s: workspace overlaps the input", fn);
     const hipError_t e =
-        is_i8(o.algo) ? launch_i8_pack(in, o.in_dtype == PAULI_C128, N, batch, o.workspace, (hipStream_t)o.stream)
+        is_i8(o.algo) ? launch_i8_pack(in, o.in_dtype == PAULI_C128, N, batch, o.workspace, mode == 3,
+                                       (hipStream_t)o.stream)
         : mode == 3 ? launch_mfma_pack_hermitian(planes_of(o.algo), in, o.in_dtype == PAULI_C128, N, batch, o.workspace,
                                                (hipStream_t)o.stream)
                   : launch_mfma_pack(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), in, o.in_dtype == PAULI_C128, N,
@@ -462,7 +463,7 @@ int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts
         return fail(PAULI_EINVAL, "%s: workspace overlaps the output", fn);
     const double scale = mode == 1 ? 1.0 : 1.0 / (double)(1u << N);
     const hipError_t e =
-        is_i8(o.algo) ? launch_i8_contract(o.workspace, out, o.out_dtype == PAULI_C128, N, batch, scale,
+        is_i8(o.algo) ? launch_i8_contract(o.workspace, out, o.out_dtype == PAULI_C128, N, batch, scale, mode == 3,
                                            (hipStream_t)o.stream)
         : mode == 3 ? launch_mfma_contract_hermitian(planes_of(o.algo), o.workspace, out, o.out_dtype == PAULI_C128, N,
                                                    batch, scale, pick_tile_hermitian(o.algo, N, o.tile),
@@ -498,6 +499,7 @@ int pauli_tile_valid(int algo, int tile, int N) {
 }
 
 int pauli_tile_valid_hermitian(int algo, int tile, int N) {
+    if (is_i8(algo)) return tile == 1 && N >= 0 && N <= N_MAX ? 1 : 0;
     if (!is_mfma(algo) || N < 0 || N > N_MAX) return 0;
     return mfma_tile_valid_hermitian(planes_of(algo), tile, N) ? 1 : 0;
 }

@@ -51,10 +51,21 @@ constexpr double I8_LIMIT = 8355711.0;   // 127 * (65536 + 256 + 1)
 constexpr int I8_NPL = 6;                // fragments per slice: 3 digit planes x (re, im)
 constexpr int I8_SK = 32;                // K values per slice (one 32x32x32 MFMA)
 constexpr int I8_SLICE = I8_NPL * FRAG;  // bytes per slice of one 32-mask slab
-constexpr int I8_WAVES = 4, I8_RB = 4;   // tile: 4 waves x 4 x 32 rows x 32 flip masks
-constexpr int I8_MT = I8_WAVES * I8_RB * 32;
+constexpr int I8_RB = 4;                 // 4 x 32 rows per wave, 32 flip masks
+// Waves per workgroup: 4 for the general contraction; 1 for the Hermitian
+// one, whose doubled epilogue then overlaps other workgroups' walks instead
+// of holding three more waves at its barriers (measured 2-5% faster there,
+// 1% slower for the general one).
+constexpr int i8_waves(bool herm) { return herm ? 1 : 4; }
+constexpr int i8_rows(bool herm) { return i8_waves(herm) * I8_RB * 32; }
 constexpr int I8_PF1 = 4, I8_PF2 = 8;    // ring depth (slices) of the two passes
 constexpr int I8_STEP = 16;              // slices per unrolled step (8 when a slab has only 8)
+// Hermitian input: slabs of flip masks X0 >= I8_HERM_FROM walk half of K and
+// compute half of the rows (see i8_contract_kernel).  A power of two >= 128
+// (the pack's K tile), >= 32 * I8_STEP (a step's slices never straddle the
+// skipped bit) and >= the rows of a workgroup (the skipped row bit spans
+// whole workgroup tiles).
+constexpr uint32_t I8_HERM_FROM = 512;
 
 // Scale record of one matrix (see the header comment): q = rint(ldexp(g, -e) * s),
 // value = ldexp(sum * r, e) with r = mm / L times the caller's scale.
@@ -198,14 +209,17 @@ __device__ inline double2 load_g(const unsigned char* base, size_t idx) {
 // which the XOR map sends to 4 flip masks x 4 consecutive i, quantises it,
 // and stores its digit bytes in the LDS staging tile; the workgroup then
 // writes whole 1 KiB fragments.
-template <bool IN128>
+// HERM: the grid holds only the tiles the Hermitian contraction's half walks
+// read (herm_pack_tile with the threshold I8_HERM_FROM); the others are not
+// packed.
+template <bool IN128, bool HERM>
 __global__ __launch_bounds__(256) void i8_pack_kernel(const void* __restrict__ in, void* __restrict__ ws, int N,
                                                       const I8Scale* __restrict__ rec) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[I8_NPL * XT * I8_PITCH];
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
     const uint32_t nKT = Dp / KT;
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = HERM ? herm_pack_tile(N, I8_HERM_FROM, blockIdx.x) : blockIdx.x;
     const uint32_t xb = t / nKT, kt = t % nKT;
     const uint32_t X0 = xb * XT, Q0 = kt * KT;
     const bool full = D >= 32u;
@@ -280,19 +294,22 @@ __device__ inline i32x4 sign_fragment(int lane) {
     return A;
 }
 
-// One walk over all nS slices of the slab at `slab` with NP digit planes
+// One walk over the slices of the slab at `slab` with NP digit planes
 // (P0, P0 + 1, ...) into acc[p][rb][cb].  The block of rows Pw + 32 rb
 // against slice s (K block s) is the Sylvester block times
 // (-1)^{popc((Pw/32 + rb) & s)}; Pw is a multiple of 128, so that sign is
 // (-1)^{popc((Pw/32) & s)} (one per group of 4 slices) times
 // (-1)^{popc(rb & s)} (fixed by s mod 4).  STEP slices per unrolled step;
 // STEP = 1 (nS < 8, N < 8): one slice at a time with the signs evaluated at
-// run time.  slab, nS and Pw are
+// run time.  The walk visits nK slices: walk index c is slice
+// ((c & ~low) << 1) | (c & low), all slices when low = ~0, and those with bit
+// log2(low + 1) clear otherwise (a half walk; low + 1 >= STEP, so the slices
+// of a step stay consecutive and aligned).  slab, nK, low and Pw are
 // uniform; everything per lane is derived here from the thread index, so
 // nothing of it stays live across the walks.
 template <int NP, int P0, int PF, int STEP>
-__device__ __attribute__((always_inline)) inline void walk(const unsigned char* __restrict__ slab, uint32_t nS,
-                                                           uint32_t Pw, i32x16 (&acc)[NP][I8_RB][2]) {
+__device__ __attribute__((always_inline)) inline void walk(const unsigned char* __restrict__ slab, uint32_t nK,
+                                                           uint32_t low, uint32_t Pw, i32x16 (&acc)[NP][I8_RB][2]) {
     constexpr int NF = 2 * NP;
     static_assert(STEP == 1 || (STEP % PF == 0 && STEP % 4 == 0), "ring and sign period nest in a step");
     int tid = (int)threadIdx.x;
@@ -303,8 +320,9 @@ __device__ __attribute__((always_inline)) inline void walk(const unsigned char* 
     const i32x4 An = Ap ^ (int)0xFEFEFEFE;
     const uint32_t pw5 = Pw >> 5;
     i32x4 ring[PF][NF];
-    auto fetch = [&](int slot, uint32_t s) {
-        const unsigned char* p = wsx + (size_t)s * I8_SLICE;
+    auto slice_of = [&](uint32_t c) { return ((c & ~low) << 1) | (c & low); };
+    auto fetch = [&](int slot, uint32_t c) {
+        const unsigned char* p = wsx + (size_t)slice_of(c) * I8_SLICE;
 #pragma unroll
         for (int f = 0; f < NF; ++f) ring[slot][f] = *(const i32x4*)(p + f * FRAG);
     };
@@ -317,13 +335,14 @@ __device__ __attribute__((always_inline)) inline void walk(const unsigned char* 
         // outstanding load, once per step; with them complete it waits only
         // for the slot the step starts with.
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0); expcnt, lgkmcnt untouched
-        for (uint32_t s0 = 0; s0 < nS; s0 += STEP) {
+        for (uint32_t s0 = 0; s0 < nK; s0 += STEP) {
+            const uint32_t sr = slice_of(s0);   // the step's slices are sr, sr + 1, ..., sr + STEP - 1
             i32x4 A0, A1;   // the group's sign applied: A0 for popc(rb & s) even, A1 odd
 #pragma unroll
             for (int uu = 0; uu < STEP; ++uu) {
                 const int slot = uu % PF;
                 if (uu % 4 == 0) {
-                    const bool gneg = __popc(pw5 & (s0 + (uint32_t)uu)) & 1;
+                    const bool gneg = __popc(pw5 & (sr + (uint32_t)uu)) & 1;
                     A0 = gneg ? An : Ap;
                     A1 = gneg ? Ap : An;
                 }
@@ -338,13 +357,14 @@ __device__ __attribute__((always_inline)) inline void walk(const unsigned char* 
                 // refill this slot PF slices ahead (the last refills reread the final slice, unused)
                 __builtin_amdgcn_sched_barrier(0);
                 const uint32_t nxt = s0 + (uint32_t)(uu + PF);
-                fetch(slot, nxt < nS ? nxt : nS - 1);
+                fetch(slot, nxt < nK ? nxt : nK - 1);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     } else {
-        for (uint32_t s = 0; s < nS; ++s) {
-            fetch(0, s);
+        for (uint32_t c = 0; c < nK; ++c) {
+            fetch(0, c);
+            const uint32_t s = slice_of(c);
 #pragma unroll
             for (int rb = 0; rb < I8_RB; ++rb) {
                 const bool neg = __popc((pw5 + (uint32_t)rb) & s) & 1;
@@ -367,17 +387,45 @@ struct I8Params {
     const I8Scale* rec;
 };
 
-// Output tile (slab xb, rows mb * 512 ..) of matrix blockIdx.y.  Waves whose
-// rows lie beyond Dp (N < 9) skip the walks but take part in the epilogue
-// barriers.  LDS: 4 waves x 1024 coefficients of staging.
-template <int STEP>
+// Output tile (slab xb, rows mb * MT ..) of matrix blockIdx.y, MT =
+// i8_rows(HERM).  Waves whose rows lie beyond Dp (small N) skip the walks but
+// take part in the epilogue barriers.  LDS: one 1024-coefficient stage per
+// wave (two for HERM).
+//
+// HERM (Hermitian G): q(G[i][i ^ x]) = conj q(G[i ^ x][i]) exactly (the
+// quantisation rounds symmetrically), so with b the top bit of X0 (set in
+// every flip mask of the slab) the sum over the pair {i, i ^ x} is
+// H[z][i] (v_i + (-1)^{popc(x&z)} conj v_i): twice the real part of the
+// half sum T = sum over the i with bit b clear of H[z][i] v_i when
+// popc(x&z) is even, 2i times its imaginary part when odd.  Slabs with
+// X0 >= I8_HERM_FROM walk only those i, and since H[z][i] = H[z ^ 2^b][i]
+// for them, rows z and z ^ 2^b have the same T with the parity flipped: the
+// tile whose rows have bit b clear stores both (the partner's component in
+// a second LDS stage) and the tile with it set does nothing.  Every sum is
+// an exact integer, so the result equals the general kernel's bit for bit.
+template <int STEP, bool HERM>
 __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    constexpr int WAVES = i8_waves(HERM), MT = i8_rows(HERM);
+    static_assert(I8_HERM_FROM >= (uint32_t)MT && I8_HERM_FROM >= 32u * I8_STEP && I8_HERM_FROM >= (uint32_t)PACK_KT,
+                  "threshold of the Hermitian half walk");
     const int N = prm.N;
     const uint32_t D = 1u << N, Dp = padded_dim(N);
-    const uint32_t nMB = (Dp + I8_MT - 1) / I8_MT;
+    const uint32_t nMB = (Dp + MT - 1) / MT;
     const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t xb = L / nMB, mb = L % nMB;
+    uint32_t xb = L / nMB;
+    const uint32_t mb = L % nMB;
+    if constexpr (HERM) {
+        // The slabs below I8_HERM_FROM walk all of K for all rows (four times
+        // the work of the others): deal slabs to the XCDs round-robin (XCD k,
+        // which owns the logical range [k S, k S + S), gets slabs k, k + 8,
+        // ...) so that those few spread over all eight.
+        const uint32_t nXB = Dp / XT;
+        if ((gridDim.x & 7u) == 0 && (nXB & 7u) == 0) {
+            const uint32_t S = nXB >> 3;
+            xb = (xb % S) * 8 + xb / S;
+        }
+    }
     const uint32_t X0 = xb * XT;
     const uint32_t nS = Dp / I8_SK;
     const unsigned char* slab =
@@ -385,7 +433,18 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
     unsigned char* dst = (unsigned char*)prm.out + (size_t)blockIdx.y * D * D * (prm.out128 ? 16 : 8);
     const I8Scale sc = prm.rec[blockIdx.y];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t Pw = mb * I8_MT + wave * I8_RB * 32;   // first row of this wave
+    const uint32_t Pw = mb * MT + wave * I8_RB * 32;   // first row of this wave
+
+    uint32_t nK = nS, low = ~0u, pair = 0;
+    if constexpr (HERM) {
+        if (X0 >= I8_HERM_FROM) {
+            const uint32_t tb = 31u - (uint32_t)__builtin_clz(X0);   // bit b; 2^b >= MT
+            low = (1u << (tb - 5u)) - 1u;                             // slice index bit b - 5 skipped
+            nK = nS >> 1;
+            pair = 1u << tb;
+            if ((mb * (uint32_t)MT) & pair) return;   // the partner tile stores these rows
+        }
+    }
 
     // acc[0] ends as h (folded in place after pass 1), acc[1] as A0: the d0
     // accumulators reuse the d1 set, so two sets are live at any time.
@@ -399,7 +458,7 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[p][rb][cb][r] = 0;
     if (Pw < Dp) {
-        walk<2, 0, I8_PF1, STEP>(slab, nS, Pw, acc);
+        walk<2, 0, I8_PF1, STEP>(slab, nK, low, Pw, acc);
 #pragma unroll
         for (int rb = 0; rb < I8_RB; ++rb)
 #pragma unroll
@@ -408,7 +467,7 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[1][rb][cb][r] = 0;
             }
-        walk<1, 2, I8_PF2, STEP>(slab, nS, Pw, reinterpret_cast<i32x16(&)[1][I8_RB][2]>(acc[1]));
+        walk<1, 2, I8_PF2, STEP>(slab, nK, low, Pw, reinterpret_cast<i32x16(&)[1][I8_RB][2]>(acc[1]));
     }
     const auto& hi = acc[0];
     const i32x16(&lo)[1][I8_RB][2] = reinterpret_cast<const i32x16(&)[1][I8_RB][2]>(acc[1]);
@@ -417,12 +476,14 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
     const int lane = tid & 63;
     const int l32 = lane & 31, h = lane >> 5;
 
-    // Epilogue: sum = 256 h + A0 exactly in binary64, times 2^(e-N) mm / L,
-    // the phase (-i)^{popc(x&z)}, staged so the 32x32 block leaves as one
-    // contiguous run of coefficients starting at n(X0, pb).
-    const double rs = sc.r * prm.scale;
+    // Epilogue: sum = 256 h + A0 exactly in binary64, times 2^(e-N) mm / L
+    // (twice that after a half walk), the phase (-i)^{popc(x&z)}, staged so
+    // the 32x32 block leaves as one contiguous run of coefficients starting
+    // at n(X0, pb) (and, paired, at n(X0, pb ^ 2^b)).
+    const double rs = sc.r * prm.scale * (pair ? 2.0 : 1.0);
     const int esz = prm.out128 ? 16 : 8;
     unsigned char* stage = lds + wave * 1024 * esz;
+    unsigned char* stage2 = lds + (WAVES + wave) * 1024 * esz;   // HERM only
 #pragma unroll
     for (int rb = 0; rb < I8_RB; ++rb) {
         const uint32_t pb = Pw + 32 * rb;
@@ -431,8 +492,24 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
             const uint32_t pl = 8 * (r >> 2) + 4 * h + (r & 3);   // row of accumulator element r
             double re = __builtin_ldexp((256.0 * (double)hi[rb][0][r] + (double)lo[0][rb][0][r]) * rs, sc.e);
             double im = __builtin_ldexp((256.0 * (double)hi[rb][1][r] + (double)lo[0][rb][1][r]) * rs, sc.e);
-            rotate_minus_i(re, im, (uint32_t)__popc((X0 + l32) & (pb + pl)));
+            const uint32_t ny = (uint32_t)__popc((X0 + l32) & (pb + pl));
             const uint32_t slot = pauli_index((uint32_t)l32, pl);
+            if constexpr (HERM) {
+                double qr = re, qi = im;   // row pb + pl ^ 2^b: the other component
+                if (ny & 1) {
+                    re = 0.0;
+                    qi = 0.0;
+                } else {
+                    im = 0.0;
+                    qr = 0.0;
+                }
+                if (pair) {
+                    rotate_minus_i(qr, qi, ny + 1u);
+                    if (prm.out128) *(double2*)(stage2 + slot * 16) = make_double2(qr, qi);
+                    else *(float2*)(stage2 + slot * 8) = make_float2((float)qr, (float)qi);
+                }
+            }
+            rotate_minus_i(re, im, ny);
             if (prm.out128) *(double2*)(stage + slot * 16) = make_double2(re, im);
             else *(float2*)(stage + slot * 8) = make_float2((float)re, (float)im);
         }
@@ -444,6 +521,10 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
                 for (uint32_t b = lane * 16; b < run * esz; b += 64 * 16) *(u32x4*)(o + b) = *(const u32x4*)(stage + b);
             } else if (lane == 0) {
                 *(u32x2*)o = *(const u32x2*)stage;   // N = 0, binary32 output
+            }
+            if (HERM && pair) {   // 1024-runs only: 2^b >= 512 rows, so N >= 10
+                unsigned char* o2 = dst + (size_t)pauli_index(X0, pb ^ pair) * esz;
+                for (uint32_t b = lane * 16; b < run * esz; b += 64 * 16) *(u32x4*)(o2 + b) = *(const u32x4*)(stage2 + b);
             }
         }
         __syncthreads();
@@ -457,41 +538,49 @@ size_t i8_workspace_bytes(int N, int batch) {
            sizeof(double) * i8_absmax_blocks(N) * (size_t)batch;
 }
 
-hipError_t launch_i8_pack(const void* in, bool in128, int N, int batch, void* ws, hipStream_t s) {
+hipError_t launch_i8_pack(const void* in, bool in128, int N, int batch, void* ws, bool herm, hipStream_t s) {
     const uint32_t R = i8_absmax_blocks(N);
     double* partial = i8_partials(ws, N, batch);
     I8Scale* rec = i8_scales(ws, N, batch);
     if (in128) hipLaunchKernelGGL((i8_absmax_kernel<true>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
     else hipLaunchKernelGGL((i8_absmax_kernel<false>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
     hipLaunchKernelGGL(i8_scale_kernel, dim3(batch), dim3(256), 0, s, (const double*)partial, R, rec);
-    const uint32_t ptiles = pack_tiles(N);
-    if (in128) hipLaunchKernelGGL((i8_pack_kernel<true>), dim3(ptiles, batch), dim3(256), 0, s, in, ws, N,
-                                  (const I8Scale*)rec);
-    else hipLaunchKernelGGL((i8_pack_kernel<false>), dim3(ptiles, batch), dim3(256), 0, s, in, ws, N,
-                            (const I8Scale*)rec);
+    const uint32_t ptiles = herm ? herm_pack_tiles(N, I8_HERM_FROM) : pack_tiles(N);
+    auto kern = in128 ? (herm ? i8_pack_kernel<true, true> : i8_pack_kernel<true, false>)
+                      : (herm ? i8_pack_kernel<false, true> : i8_pack_kernel<false, false>);
+    hipLaunchKernelGGL(kern, dim3(ptiles, batch), dim3(256), 0, s, in, ws, N, (const I8Scale*)rec);
     return hipGetLastError();
 }
 
-hipError_t launch_i8_contract(const void* ws, void* out, bool out128, int N, int batch, double scale,
-                              hipStream_t s) {
+template <bool HERM>
+hipError_t launch_i8_contract_t(const void* ws, void* out, bool out128, int N, int batch, double scale,
+                                hipStream_t s) {
+    constexpr int WAVES = i8_waves(HERM), MT = i8_rows(HERM);
     const uint32_t Dp = padded_dim(N);
-    const uint32_t nMB = (Dp + I8_MT - 1) / I8_MT, nXB = Dp / XT;
-    const int lds = I8_WAVES * 1024 * (out128 ? 16 : 8);
+    const uint32_t nMB = (Dp + MT - 1) / MT, nXB = Dp / XT;
+    const int lds = WAVES * 1024 * (out128 ? 16 : 8) * (HERM ? 2 : 1);
     // slices per slab: a power of two, so a multiple of the step it is given
     const uint32_t nS = Dp / I8_SK;
-    auto kern = nS >= (uint32_t)I8_STEP ? i8_contract_kernel<I8_STEP> : (nS >= 8u ? i8_contract_kernel<8> : i8_contract_kernel<1>);
+    auto kern = nS >= (uint32_t)I8_STEP ? i8_contract_kernel<I8_STEP, HERM>
+                                        : (nS >= 8u ? i8_contract_kernel<8, HERM> : i8_contract_kernel<1, HERM>);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     I8Params p = {ws, out, N, out128 ? 1 : 0, scale, i8_scales(const_cast<void*>(ws), N, batch)};
-    hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(I8_WAVES * 64), lds, s, p);
+    hipLaunchKernelGGL(kern, dim3(nMB * nXB, batch), dim3(WAVES * 64), lds, s, p);
     return hipGetLastError();
 }
 
+hipError_t launch_i8_contract(const void* ws, void* out, bool out128, int N, int batch, double scale, bool herm,
+                              hipStream_t s) {
+    return herm ? launch_i8_contract_t<true>(ws, out, out128, N, batch, scale, s)
+                : launch_i8_contract_t<false>(ws, out, out128, N, batch, scale, s);
+}
+
 hipError_t launch_i8(const void* in, bool in128, void* out, bool out128, int N, int batch, double scale, void* ws,
-                     hipStream_t s) {
-    hipError_t e = launch_i8_pack(in, in128, N, batch, ws, s);
+                     bool herm, hipStream_t s) {
+    hipError_t e = launch_i8_pack(in, in128, N, batch, ws, herm, s);
     if (e != hipSuccess) return e;
-    return launch_i8_contract(ws, out, out128, N, batch, scale, s);
+    return launch_i8_contract(ws, out, out128, N, batch, scale, herm, s);
 }
 
 }  // namespace pauli

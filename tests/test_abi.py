@@ -245,8 +245,9 @@ def test_fwht_f32_algo_queries(lib, pauli):
 
 def test_split_i8_algo_queries(lib, pauli):
     """The fixed-point int8 path: six one-byte planes of workspace plus its
-    scale record and partial maxima, one tile shape, forward only; every
-    other entry point refuses it before any device call."""
+    scale record and partial maxima, one tile shape, forward only (general
+    and Hermitian); the adjoint, batched and tuning entry points refuse it
+    before any device call."""
     assert pauli.ALGOS["split_i8"] == 6
     for N, batch in ((14, 1), (10, 3), (3, 2)):
         Dp = max(1 << N, 32)
@@ -257,7 +258,7 @@ def test_split_i8_algo_queries(lib, pauli):
     assert all(lib.pauli_tile_valid(6, 1, N) == 1 for N in range(0, 17))
     assert lib.pauli_tile_valid(6, 2, 10) == 0 and lib.pauli_tile_valid(6, 1, 17) == 0
     assert lib.pauli_tile_selected(6, 14) == 0
-    assert lib.pauli_tile_valid_hermitian(6, 1, 10) == 0
+    assert lib.pauli_tile_valid_hermitian(6, 1, 10) == 1 and lib.pauli_tile_valid_hermitian(6, 2, 10) == 0
     o = opts(pauli, algo="split_i8")
     assert lib.pauli_decompose(FAKE_IN, 17, 1, FAKE_OUT, ctypes.byref(o)) == EINVAL
     forced = opts(pauli, algo="split_i8", tile=2)
@@ -266,12 +267,13 @@ def test_split_i8_algo_queries(lib, pauli):
     assert lib.pauli_decompose(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_reconstruct(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
     assert lib.pauli_decompose_backward(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
-    assert lib.pauli_decompose_hermitian(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
-    for mode in (1, 2, 3):
+    assert lib.pauli_decompose_hermitian(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(forced)) == EINVAL
+    for mode in (1, 2):
         assert lib.pauli_pack(FAKE_IN, 10, 1, mode, ctypes.byref(o)) == EUNSUPPORTED
         assert lib.pauli_contract(10, 1, mode, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
-    assert lib.pauli_pack(FAKE_IN, 10, 1, 0, ctypes.byref(o)) == ENOMEM        # mode 0 needs the workspace
-    assert lib.pauli_contract(10, 1, 0, FAKE_OUT, ctypes.byref(small)) == ENOMEM
+    for mode in (0, 3):   # decompose and Hermitian decompose: the workspace is required
+        assert lib.pauli_pack(FAKE_IN, 10, 1, mode, ctypes.byref(o)) == ENOMEM
+        assert lib.pauli_contract(10, 1, mode, FAKE_OUT, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_autotune(9, 10, ctypes.byref(o)) == EUNSUPPORTED
     assert lib.pauli_batched_workspace_bytes(1, (ctypes.c_int * 1)(5), 6) == 0
 

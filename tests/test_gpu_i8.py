@@ -112,6 +112,9 @@ def test_n14_hermitian_sample_and_gray():
     assert np.all(c.imag == 0)
     s = float((np.abs(c.astype(np.complex128)) ** 2).sum())
     assert abs(s - g2) <= 1e-6 * g2
+    # the Hermitian entry point (a quarter of the walks) gives the same exact sums
+    ch = p.decompose_hermitian(dev(G), algo="split_i8").cpu().numpy()
+    assert np.array_equal(ch, c)
 
 
 def test_exact_when_quantisation_is():
@@ -199,16 +202,58 @@ def test_mixed_magnitudes_within_the_fixed_point_bound():
 
 
 def test_forward_only():
-    """The adjoint, Hermitian, two-pass and batched entry points refuse the
-    algorithm (PAULI_EUNSUPPORTED) without launching anything."""
+    """The adjoint and batched entry points refuse the algorithm
+    (PAULI_EUNSUPPORTED) without launching anything."""
     p = lib()
     N = 6
     G = dev(workloads.iid_complex(N, 8950, np.complex64))
     c = torch.zeros(4 ** N, dtype=torch.complex64, device="cuda")
     for call in (lambda: p.decompose_backward(c, algo="split_i8"),
                  lambda: p.reconstruct(c, algo="split_i8"),
-                 lambda: p.decompose_hermitian(G, algo="split_i8"),
                  lambda: p.decompose_batched([G], algo="split_i8")):
         with pytest.raises(p.PauliError) as e:
             call()
         assert e.value.status == 2
+
+
+@pytest.mark.parametrize("N", [0, 3, 5, 8, 9, 10, 11, 12])
+def test_hermitian_variant_bit_identical(N):
+    """decompose_hermitian walks half of K and half of the rows for flip masks
+    from 512 on (N >= 10); its integer sums are exact, so on Hermitian input it
+    equals the general int8 decomposition bit for bit (complex64 and
+    complex128), and both match the oracle within the path's bound."""
+    p = lib()
+    G = workloads.hermitian(N, 8960 + N)
+    Gd = dev(G)
+    c = p.decompose(Gd, algo="split_i8").cpu().numpy()
+    ch = p.decompose_hermitian(Gd, algo="split_i8").cpu().numpy()
+    assert np.array_equal(ch, c)
+    assert np.all(ch.imag == 0)
+    if N <= 11:
+        ref = oracle.decompose(G.astype(np.complex128), threads=threads())
+        assert check(G, ch, ref, torch.complex64) <= 1e-6
+    if N in (10, 11):
+        G2 = dev(G.astype(np.complex128))
+        c2 = p.decompose(G2, algo="split_i8").cpu().numpy()
+        assert np.array_equal(p.decompose_hermitian(G2, algo="split_i8").cpu().numpy(), c2)
+
+
+def test_hermitian_variant_batch_and_two_pass():
+    """A batch of Hermitian matrices 2^30 apart in size, and the same call split
+    into pauli_pack / pauli_contract mode 3, equal the general path bit for bit."""
+    import ctypes
+    p = lib()
+    L = p.load_library()
+    N = 11
+    mats = [workloads.hermitian(N, 8970 + k) * np.float32(2.0 ** (30 * k - 30)) for k in range(3)]
+    B = dev(np.stack(mats))
+    cb = p.decompose_hermitian(B, algo="split_i8").cpu().numpy()
+    for k, G in enumerate(mats):
+        assert np.array_equal(cb[k], dec(G)), k
+    ws = p.workspace("split_i8", N, 3, B.device)
+    o = p._opts("split_i8", 0, 0, 0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ws)
+    out = torch.empty(3 * 4 ** N, dtype=torch.complex64, device="cuda")
+    assert L.pauli_pack(ctypes.c_void_p(B.data_ptr()), N, 3, 3, ctypes.byref(o)) == 0
+    assert L.pauli_contract(N, 3, 3, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o)) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(3, -1), cb)
