@@ -34,9 +34,12 @@
 // Kernels, launched in order on one stream (every value a kernel reads was
 // written by an earlier one, so the workspace needs no clearing):
 //   i8_absmax_kernel   partial maxima of |Re g|, |Im g| over R ranges
+//                      (i8_absmax_lower_kernel: the lower triangle of a
+//                      Hermitian matrix)
 //   i8_scale_kernel    one scale record per matrix
 //   i8_pack_kernel     gather + quantise + digit split into fragments
-//   i8_contract_kernel the two-pass contraction and the epilogue
+//   i8_contract_kernel the two walks over K and the epilogue (HERM: the
+//                      Hermitian shortcut, a quarter of the walks)
 #include "mfma_tile.hpp"
 
 namespace pauli {
@@ -140,6 +143,36 @@ __global__ __launch_bounds__(256) void i8_absmax_kernel(const void* __restrict__
         for (size_t i = threadIdx.x; i < per; i += 256) {
             const float2 v = p[i];
             m = __builtin_fmax(m, __builtin_fmax(mag(v.x), mag(v.y)));
+        }
+    }
+    m = block_max256_f64(m, red);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * R + blockIdx.x] = m;
+}
+
+// The same reduction over the lower triangle of a Hermitian matrix (whose
+// upper triangle repeats it with the imaginary parts negated): workgroup
+// blockIdx.x takes row pairs r, D-1-r (r + 1 and D - r elements of the
+// triangle, D + 1 together), so R = min(i8_absmax_blocks(N), D / 2)
+// workgroups read half of G.  D >= 2.
+template <bool IN128>
+__global__ __launch_bounds__(256) void i8_absmax_lower_kernel(const void* __restrict__ in, int N,
+                                                              double* __restrict__ partial, uint32_t R) {
+    __shared__ double red[4];
+    const uint32_t D = 1u << N;
+    const uint32_t ppb = (D / 2u) / R;   // row pairs per workgroup
+    const size_t mat = (size_t)D * D;
+    double m = 0.0;
+    for (uint32_t pp = 0; pp < ppb; ++pp) {
+        const uint32_t r = blockIdx.x * ppb + pp;
+        for (uint32_t e = threadIdx.x; e <= D; e += 256) {
+            const size_t idx = e <= r ? (size_t)r * D + e : (size_t)(D - 1u - r) * D + (e - r - 1u);
+            if constexpr (IN128) {
+                const double2 v = ((const double2*)in)[(size_t)blockIdx.y * mat + idx];
+                m = __builtin_fmax(m, __builtin_fmax(mag(v.x), mag(v.y)));
+            } else {
+                const float2 v = ((const float2*)in)[(size_t)blockIdx.y * mat + idx];
+                m = __builtin_fmax(m, __builtin_fmax(mag(v.x), mag(v.y)));
+            }
         }
     }
     m = block_max256_f64(m, red);
@@ -539,11 +572,19 @@ size_t i8_workspace_bytes(int N, int batch) {
 }
 
 hipError_t launch_i8_pack(const void* in, bool in128, int N, int batch, void* ws, bool herm, hipStream_t s) {
-    const uint32_t R = i8_absmax_blocks(N);
+    uint32_t R = i8_absmax_blocks(N);
     double* partial = i8_partials(ws, N, batch);
     I8Scale* rec = i8_scales(ws, N, batch);
-    if (in128) hipLaunchKernelGGL((i8_absmax_kernel<true>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
-    else hipLaunchKernelGGL((i8_absmax_kernel<false>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+    const uint32_t half = (1u << N) / 2u;
+    if (herm && half >= 1u) {
+        R = R < half ? R : half;   // both powers of two: R divides D / 2
+        if (in128) hipLaunchKernelGGL((i8_absmax_lower_kernel<true>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+        else hipLaunchKernelGGL((i8_absmax_lower_kernel<false>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+    } else if (in128) {
+        hipLaunchKernelGGL((i8_absmax_kernel<true>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+    } else {
+        hipLaunchKernelGGL((i8_absmax_kernel<false>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
+    }
     hipLaunchKernelGGL(i8_scale_kernel, dim3(batch), dim3(256), 0, s, (const double*)partial, R, rec);
     const uint32_t ptiles = herm ? herm_pack_tiles(N, I8_HERM_FROM) : pack_tiles(N);
     auto kern = in128 ? (herm ? i8_pack_kernel<true, true> : i8_pack_kernel<true, false>)

@@ -18,15 +18,16 @@ def lib():
     return p
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray", "fwht"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray", "fwht", "split_i8"])
 def test_capture_and_replay(algo):
     p = lib()
+    adjoint = algo != "split_i8"   # the int8 path is forward only
     N = 10
     G = torch.from_numpy(workloads.iid_complex(N, 1500, np.complex64)).cuda()
     G2 = torch.from_numpy(workloads.iid_complex(N, 1501, np.complex64)).cuda()
     eager = p.decompose(G, algo=algo)
     eager2 = p.decompose(G2, algo=algo)
-    back = p.reconstruct(eager, algo=algo)
+    back = p.reconstruct(eager, algo=algo) if adjoint else None
     torch.cuda.synchronize()
 
     src = G.clone()
@@ -39,7 +40,7 @@ def test_capture_and_replay(algo):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         c = p.decompose(src, algo=algo)
-        r = p.reconstruct(c, algo=algo)
+        r = p.reconstruct(c, algo=algo) if adjoint else None
     for rep in range(4):
         junk = torch.randn(1 << 18, device="cuda").sum()   # eager work between replays
         src.copy_(G if rep % 2 == 0 else G2)
@@ -47,13 +48,13 @@ def test_capture_and_replay(algo):
         torch.cuda.synchronize()
         want = eager if rep % 2 == 0 else eager2
         assert torch.equal(c, want), (algo, rep)
-        if rep % 2 == 0:
+        if adjoint and rep % 2 == 0:
             assert torch.equal(r, back), (algo, rep)
         del junk
     del g
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "split_i8"])
 def test_capture_and_replay_hermitian(algo):
     """The Hermitian entry point enqueues the same two kernels (pack, then
     the Hermitian contraction): captured, it must match the eager result on
