@@ -210,7 +210,8 @@ def bench_backward(a):
                                    "and adjoint backward through torch.autograd" % algo, "batch": 8, "N": 11,
                        "algo": algo},
             "forward_ms": ms_fwd, "backward_kernel_ms": ms_bwd,
-            "executed_tflops_fwd_bwd_kernels": flops / ((ms_fwd + ms_bwd) / 1e3) / 1e12}
+            ("executed_tops_fwd_bwd_kernels" if algo == "split_i8" else "executed_tflops_fwd_bwd_kernels"):
+                flops / ((ms_fwd + ms_bwd) / 1e3) / 1e12}
     print(json.dumps(line), flush=True)
 
 
@@ -440,8 +441,10 @@ def main():
     a = ap.parse_args()
     if a.algo is None:
         a.algo = {"n14": "split_i8", "hermitian": "split_i8", "fwht": "fwht"}.get(a.workload, "split_fp16")
-    if a.workload in ("batch", "backward") and a.algo not in ("split_bf16", "split_fp16", "fp32"):
-        raise SystemExit("bench.py: the %s workload runs split_bf16, split_fp16 or fp32, not %s" % (a.workload, a.algo))
+    if a.workload == "batch" and a.algo not in ("split_bf16", "split_fp16", "fp32"):
+        raise SystemExit("bench.py: the batch workload runs split_bf16, split_fp16 or fp32, not %s" % a.algo)
+    if a.workload == "backward" and a.algo not in ("split_bf16", "split_fp16", "fp32", "split_i8"):
+        raise SystemExit("bench.py: the backward workload runs a matrix-core path, not %s" % a.algo)
     if a.gpus != 1:
         print("bench.py: the decomposition runs on one GPU (it is not sharded across devices); --gpus %d is not supported" % a.gpus,
               file=sys.stderr)

@@ -117,13 +117,15 @@ typedef enum pauli_algo {
      * entry (fixed point); for iid inputs the error is about 2e-7 of
      * max|c| (2.2e-7 at N = 14).  Three quarters of SPLIT_FP16's
      * matrix-core time at int8's doubled rate.  pauli_decompose,
-     * pauli_decompose_noalloc and pauli_decompose_hermitian (forward,
-     * equal-order batches, one tile shape; on Hermitian input the two give
-     * the same result bit for bit, the sums being exact), also split into
-     * pauli_pack / pauli_contract modes 0 and 3; the adjoint, batched and
-     * tuning entry points and modes 1, 2 return PAULI_EUNSUPPORTED.  An infinite
-     * or NaN component makes every coefficient of that matrix NaN; an
-     * all-zero matrix gives zeros. */
+     * pauli_decompose_noalloc, pauli_decompose_hermitian (on Hermitian
+     * input it equals pauli_decompose bit for bit, the sums being exact),
+     * pauli_reconstruct and pauli_decompose_backward (the coefficient vector
+     * quantised the same way from its own largest component m_c: each entry
+     * of G off by at most 2^N m_c / (2 * 8355711) per component, times the
+     * gradient's 2^-N), equal-order batches, one tile shape, also split into
+     * pauli_pack / pauli_contract (every mode); the batched and tuning entry
+     * points return PAULI_EUNSUPPORTED.  An infinite or NaN component makes
+     * every output of that matrix NaN; an all-zero input gives zeros. */
     PAULI_ALGO_SPLIT_I8 = 6
 } pauli_algo;
 

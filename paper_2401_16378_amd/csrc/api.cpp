@@ -252,20 +252,18 @@ int run(Dir dir, const void* in, int N, int batch, void* out, const pauli_opts& 
             if (e == hipSuccess) e = ef;
         }
     } else if (is_i8(o.algo)) {
-        if (dir != FORWARD)
-            return fail(PAULI_EUNSUPPORTED, "%s: algo %d computes the forward decomposition only", fn, o.algo);
         const size_t need = i8_workspace_bytes(N, batch);
         void* ws = o.workspace;
         if (ws) {
             if (o.workspace_bytes < need)
                 return fail(PAULI_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need,
                             o.workspace_bytes);
-            e = launch_i8(in, in128, out, out128, N, batch, scale, ws, herm, s);
+            e = launch_i8(dir, in, in128, out, out128, N, batch, scale, ws, herm, s);
         } else {
             hipMemPool_t pool;
             if ((e = pool_for_current_device(&pool)) != hipSuccess) return hip_fail(e, fn);
             if ((e = hipMallocFromPoolAsync(&ws, need, pool, s)) != hipSuccess) return hip_fail(e, fn);
-            e = launch_i8(in, in128, out, out128, N, batch, scale, ws, herm, s);
+            e = launch_i8(dir, in, in128, out, out128, N, batch, scale, ws, herm, s);
             const hipError_t ef = hipFreeAsync(ws, s);
             if (e == hipSuccess) e = ef;
         }
@@ -411,9 +409,8 @@ static int stage_check(int N, int batch, int mode, const pauli_opts& o, const ch
     if (N < 0 || N > N_MAX) return fail(PAULI_EINVAL, "%s: N=%d outside [0, %d]", fn, N, N_MAX);
     if (batch < 1) return fail(PAULI_EINVAL, "%s: batch=%d must be >= 1", fn, batch);
     if (mode < 0 || mode > 3) return fail(PAULI_EINVAL, "%s: mode %d not in {0, 1, 2, 3}", fn, mode);
-    if (!is_mfma(o.algo) && !(is_i8(o.algo) && (mode == 0 || mode == 3)))
-        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes%s", fn, o.algo,
-                    is_i8(o.algo) ? " except for modes 0 and 3" : "");
+    if (!is_mfma(o.algo) && !is_i8(o.algo))
+        return fail(PAULI_EUNSUPPORTED, "%s: algo %d has no separate passes", fn, o.algo);
     if (!valid_dtype(o.in_dtype) || !valid_dtype(o.out_dtype))
         return fail(PAULI_EINVAL, "%s: unknown dtype (in %d, out %d)", fn, o.in_dtype, o.out_dtype);
     const size_t need = is_i8(o.algo) ? i8_workspace_bytes(N, batch) : mfma_workspace_bytes(planes_of(o.algo), N, batch);
@@ -440,8 +437,8 @@ int pauli_pack(const void* in, int N, int batch, int mode, const pauli_opts* opt
     if (overlaps(in, bytes, o.workspace, o.workspace_bytes))
         return fail(PAULI_EINVAL, "%s: workspace overlaps the input", fn);
     const hipError_t e =
-        is_i8(o.algo) ? launch_i8_pack(in, o.in_dtype == PAULI_C128, N, batch, o.workspace, mode == 3,
-                                       (hipStream_t)o.stream)
+        is_i8(o.algo) ? launch_i8_pack(in, o.in_dtype == PAULI_C128, N, batch, o.workspace,
+                                       mode == 1 || mode == 2 ? ADJOINT : FORWARD, mode == 3, (hipStream_t)o.stream)
         : mode == 3 ? launch_mfma_pack_hermitian(planes_of(o.algo), in, o.in_dtype == PAULI_C128, N, batch, o.workspace,
                                                (hipStream_t)o.stream)
                   : launch_mfma_pack(mode == 0 ? FORWARD : ADJOINT, planes_of(o.algo), in, o.in_dtype == PAULI_C128, N,
@@ -463,8 +460,8 @@ int pauli_contract(int N, int batch, int mode, void* out, const pauli_opts* opts
         return fail(PAULI_EINVAL, "%s: workspace overlaps the output", fn);
     const double scale = mode == 1 ? 1.0 : 1.0 / (double)(1u << N);
     const hipError_t e =
-        is_i8(o.algo) ? launch_i8_contract(o.workspace, out, o.out_dtype == PAULI_C128, N, batch, scale, mode == 3,
-                                           (hipStream_t)o.stream)
+        is_i8(o.algo) ? launch_i8_contract(o.workspace, out, o.out_dtype == PAULI_C128, N, batch, scale,
+                                           mode == 1 || mode == 2 ? ADJOINT : FORWARD, mode == 3, (hipStream_t)o.stream)
         : mode == 3 ? launch_mfma_contract_hermitian(planes_of(o.algo), o.workspace, out, o.out_dtype == PAULI_C128, N,
                                                    batch, scale, pick_tile_hermitian(o.algo, N, o.tile),
                                                    (hipStream_t)o.stream)

@@ -41,18 +41,19 @@ int mfma_tile_count(int planes);
 bool mfma_tile_valid(int planes, int tile, int N);
 int mfma_default_tile(int planes, int N);
 
-// Fixed-point int8 contraction (forward only): G quantised per matrix to
-// integers of at most 23 bits, split into three int8 digit planes, summed
-// exactly by int8 MFMA.  ws = device scratch of i8_workspace_bytes(N, batch).
-// herm: Hermitian G (half of K and of the rows for most flip masks; the same
-// result bit for bit).
+// Fixed-point int8 contraction: the input (G, or the coefficients for
+// ADJOINT) quantised per matrix to integers of at most 23 bits, split into
+// three int8 digit planes, summed exactly by int8 MFMA.  ws = device scratch
+// of i8_workspace_bytes(N, batch).  herm (FORWARD only): Hermitian G (half of
+// K and of the rows for most flip masks; the same result bit for bit).
 size_t i8_workspace_bytes(int N, int batch);
-hipError_t launch_i8(const void* in, bool in_c128, void* out, bool out_c128, int N, int batch, double scale,
+hipError_t launch_i8(Dir dir, const void* in, bool in_c128, void* out, bool out_c128, int N, int batch, double scale,
                      void* ws, bool herm, hipStream_t stream);
 // The two halves of launch_i8: scale + quantise + pack, then the contraction.
-hipError_t launch_i8_pack(const void* in, bool in_c128, int N, int batch, void* ws, bool herm, hipStream_t stream);
-hipError_t launch_i8_contract(const void* ws, void* out, bool out_c128, int N, int batch, double scale, bool herm,
-                              hipStream_t stream);
+hipError_t launch_i8_pack(const void* in, bool in_c128, int N, int batch, void* ws, Dir dir, bool herm,
+                          hipStream_t stream);
+hipError_t launch_i8_contract(const void* ws, void* out, bool out_c128, int N, int batch, double scale, Dir dir,
+                              bool herm, hipStream_t stream);
 
 // Uneven batch: device descriptor table built by the host, one entry per
 // matrix in processing order.

@@ -304,6 +304,77 @@ __global__ __launch_bounds__(256) void i8_pack_kernel(const void* __restrict__ i
     }
 }
 
+// Adjoint pack (reconstruction, gradient): the contraction input is
+// In[z][x] = i^{popc(x&z)} c[n(x, z)], K = z.  The 32 x 32 coefficients of
+// flip masks X0.. and phase masks zb = Q0 + 32 g .. are the 1024 consecutive
+// entries from n(X0, zb); thread w6 takes 16 of them, o = 16 w6 + r with
+// r = (x^z)_0 | z_0 << 1 | (x^z)_1 << 2 | z_1 << 3, i.e. 4 flip masks x 4
+// consecutive z, applies the phase, quantises with the vector's scale record
+// (the phase only permutes and negates components, so the largest component
+// is the same) and stages the digits exactly as the forward pack does.
+template <bool IN128>
+__global__ __launch_bounds__(256) void i8_pack_adj_kernel(const void* __restrict__ in, void* __restrict__ ws, int N,
+                                                          const I8Scale* __restrict__ rec) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[I8_NPL * XT * I8_PITCH];
+    const uint32_t D = 1u << N, Dp = padded_dim(N);
+    const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
+    const uint32_t nKT = Dp / KT;
+    const uint32_t t = blockIdx.x;
+    const uint32_t xb = t / nKT, kt = t % nKT;
+    const uint32_t X0 = xb * XT, Q0 = kt * KT;
+    const bool full = D >= 32u;
+    const unsigned char* src = (const unsigned char*)in + (size_t)blockIdx.y * D * D * (IN128 ? 16 : 8);
+    unsigned char* wsm = (unsigned char*)ws + (size_t)blockIdx.y * i8_packed_bytes(N);
+    const I8Scale sc = rec[blockIdx.y];
+    const int tid = threadIdx.x;
+    const int g = tid >> 6, w6 = tid & 63;
+
+    if ((uint32_t)tid < 2 * KT) {
+        const uint32_t zb = Q0 + 32 * g;
+        const uint32_t nb = pauli_index(X0, zb);
+        double2 v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t o = 16 * w6 + r;
+            const uint32_t zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
+            const uint32_t z = zb + zl, x = X0 + xl;
+            double2 c = make_double2(0.0, 0.0);
+            if (full || (z < D && x < D)) c = load_g<IN128>(src, nb + o);
+            rotate_minus_i(c.x, c.y, 3u * (uint32_t)__popc(x & z));   // times i^{popc(x&z)}
+            v[r] = c;
+        }
+        const uint32_t o = 16 * w6;
+        const uint32_t zl0 = compact_even(o >> 1), xl0 = compact_even(o) ^ zl0;
+        const int xh = (int)(xl0 >> 2);             // flip masks 4 xh .. 4 xh + 3 of the slab
+        const int kh = 32 * g + (int)zl0;           // K slots (phase masks) kh .. kh + 3 of the tile
+#pragma unroll
+        for (int x2 = 0; x2 < 4; ++x2) {
+            uint32_t w[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int d = x2 ^ b;   // (x ^ z) low bits for flip mask 4 xh + x2, phase mask kh + b
+                const double2 e = v[(d & 1) | ((b & 1) << 1) | ((d >> 1) << 2) | ((b >> 1) << 3)];
+                digits(quantise(e.x, sc.s, sc.e), 8 * b, w[0], w[2], w[4]);
+                digits(quantise(e.y, sc.s, sc.e), 8 * b, w[1], w[3], w[5]);
+            }
+            unsigned char* row = lds + (xh * 4 + x2) * I8_PITCH + kh;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) *(uint32_t*)(row + f * XT * I8_PITCH) = w[f];
+        }
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int xl = lane & 31, h = lane >> 5;
+    const uint32_t nfrag = (KT / I8_SK) * I8_NPL;
+    unsigned char* dst = wsm + ((size_t)xb * (Dp / I8_SK) + Q0 / I8_SK) * I8_SLICE;
+    for (uint32_t f = wave; f < nfrag; f += 4) {
+        const uint32_t s = f / I8_NPL, pl = f % I8_NPL;
+        const unsigned char* p = lds + pl * XT * I8_PITCH + xl * I8_PITCH + s * I8_SK + h * 16;
+        *(u32x4*)(dst + (size_t)f * FRAG + lane * 16) = *(const u32x4*)p;
+    }
+}
+
 __device__ inline i32x16 mfma_i8(const i32x4& a, const i32x4& b, const i32x16& c) {
     return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
@@ -436,10 +507,16 @@ struct I8Params {
 // tile whose rows have bit b clear stores both (the partner's component in
 // a second LDS stage) and the tile with it set does nothing.  Every sum is
 // an exact integer, so the result equals the general kernel's bit for bit.
-template <int STEP, bool HERM>
+//
+// ADJ (reconstruction, gradient): rows are i, K is z, and the sum for row i,
+// column x is G[i ^ x][i] (times the caller's scale): the epilogue stages
+// each 32 x 32 block as the aligned square of G it fills and stores it row
+// by row.
+template <int STEP, bool HERM, bool ADJ = false>
 __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     constexpr int WAVES = i8_waves(HERM), MT = i8_rows(HERM);
+    static_assert(!(HERM && ADJ), "the Hermitian shortcut is a forward-only property");
     static_assert(I8_HERM_FROM >= (uint32_t)MT && I8_HERM_FROM >= 32u * I8_STEP && I8_HERM_FROM >= (uint32_t)PACK_KT,
                   "threshold of the Hermitian half walk");
     const int N = prm.N;
@@ -525,6 +602,12 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
             const uint32_t pl = 8 * (r >> 2) + 4 * h + (r & 3);   // row of accumulator element r
             double re = __builtin_ldexp((256.0 * (double)hi[rb][0][r] + (double)lo[0][rb][0][r]) * rs, sc.e);
             double im = __builtin_ldexp((256.0 * (double)hi[rb][1][r] + (double)lo[0][rb][1][r]) * rs, sc.e);
+            if constexpr (ADJ) {
+                const uint32_t slot = ((pl ^ (uint32_t)l32) << 5) | pl;   // (row, col) inside the square
+                if (prm.out128) *(double2*)(stage + slot * 16) = make_double2(re, im);
+                else *(float2*)(stage + slot * 8) = make_float2((float)re, (float)im);
+                continue;
+            }
             const uint32_t ny = (uint32_t)__popc((X0 + l32) & (pb + pl));
             const uint32_t slot = pauli_index((uint32_t)l32, pl);
             if constexpr (HERM) {
@@ -547,6 +630,24 @@ __global__ __launch_bounds__(256) void i8_contract_kernel(I8Params prm) {
             else *(float2*)(stage + slot * 8) = make_float2((float)re, (float)im);
         }
         __syncthreads();
+        if constexpr (ADJ) {
+            // 32x32 square of G: rows ((pb ^ X0) & ~31) + rl, columns pb + cl
+            const uint32_t w = D < 32u ? D : 32u;
+            const uint32_t rowbytes = w * esz;
+            const uint32_t r0 = (pb ^ X0) & ~31u;
+            if (pb < D) {
+                if (rowbytes >= 16) {
+                    for (uint32_t b = lane * 16; b < w * rowbytes; b += 64 * 16) {
+                        const uint32_t rl = b / rowbytes, cb = b % rowbytes;
+                        *(u32x4*)(dst + ((size_t)(r0 + rl) * D + pb) * esz + cb) = *(const u32x4*)(stage + rl * 32 * esz + cb);
+                    }
+                } else if (lane == 0) {
+                    *(u32x2*)dst = *(const u32x2*)stage;   // N = 0, binary32 output
+                }
+            }
+            __syncthreads();
+            continue;
+        }
         const uint32_t run = D < 32u ? D * D : 1024u;
         unsigned char* o = dst + (size_t)pauli_index(X0, pb) * esz;
         if (pb < D) {
@@ -571,7 +672,8 @@ size_t i8_workspace_bytes(int N, int batch) {
            sizeof(double) * i8_absmax_blocks(N) * (size_t)batch;
 }
 
-hipError_t launch_i8_pack(const void* in, bool in128, int N, int batch, void* ws, bool herm, hipStream_t s) {
+hipError_t launch_i8_pack(const void* in, bool in128, int N, int batch, void* ws, Dir dir, bool herm,
+                          hipStream_t s) {
     uint32_t R = i8_absmax_blocks(N);
     double* partial = i8_partials(ws, N, batch);
     I8Scale* rec = i8_scales(ws, N, batch);
@@ -586,6 +688,11 @@ hipError_t launch_i8_pack(const void* in, bool in128, int N, int batch, void* ws
         hipLaunchKernelGGL((i8_absmax_kernel<false>), dim3(R, batch), dim3(256), 0, s, in, N, partial, R);
     }
     hipLaunchKernelGGL(i8_scale_kernel, dim3(batch), dim3(256), 0, s, (const double*)partial, R, rec);
+    if (dir == ADJOINT) {
+        auto kern = in128 ? i8_pack_adj_kernel<true> : i8_pack_adj_kernel<false>;
+        hipLaunchKernelGGL(kern, dim3(pack_tiles(N), batch), dim3(256), 0, s, in, ws, N, (const I8Scale*)rec);
+        return hipGetLastError();
+    }
     const uint32_t ptiles = herm ? herm_pack_tiles(N, I8_HERM_FROM) : pack_tiles(N);
     auto kern = in128 ? (herm ? i8_pack_kernel<true, true> : i8_pack_kernel<true, false>)
                       : (herm ? i8_pack_kernel<false, true> : i8_pack_kernel<false, false>);
@@ -593,7 +700,7 @@ hipError_t launch_i8_pack(const void* in, bool in128, int N, int batch, void* ws
     return hipGetLastError();
 }
 
-template <bool HERM>
+template <bool HERM, bool ADJ>
 hipError_t launch_i8_contract_t(const void* ws, void* out, bool out128, int N, int batch, double scale,
                                 hipStream_t s) {
     constexpr int WAVES = i8_waves(HERM), MT = i8_rows(HERM);
@@ -602,8 +709,8 @@ hipError_t launch_i8_contract_t(const void* ws, void* out, bool out128, int N, i
     const int lds = WAVES * 1024 * (out128 ? 16 : 8) * (HERM ? 2 : 1);
     // slices per slab: a power of two, so a multiple of the step it is given
     const uint32_t nS = Dp / I8_SK;
-    auto kern = nS >= (uint32_t)I8_STEP ? i8_contract_kernel<I8_STEP, HERM>
-                                        : (nS >= 8u ? i8_contract_kernel<8, HERM> : i8_contract_kernel<1, HERM>);
+    auto kern = nS >= (uint32_t)I8_STEP ? i8_contract_kernel<I8_STEP, HERM, ADJ>
+                                        : (nS >= 8u ? i8_contract_kernel<8, HERM, ADJ> : i8_contract_kernel<1, HERM, ADJ>);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     I8Params p = {ws, out, N, out128 ? 1 : 0, scale, i8_scales(const_cast<void*>(ws), N, batch)};
@@ -611,17 +718,18 @@ hipError_t launch_i8_contract_t(const void* ws, void* out, bool out128, int N, i
     return hipGetLastError();
 }
 
-hipError_t launch_i8_contract(const void* ws, void* out, bool out128, int N, int batch, double scale, bool herm,
-                              hipStream_t s) {
-    return herm ? launch_i8_contract_t<true>(ws, out, out128, N, batch, scale, s)
-                : launch_i8_contract_t<false>(ws, out, out128, N, batch, scale, s);
+hipError_t launch_i8_contract(const void* ws, void* out, bool out128, int N, int batch, double scale, Dir dir,
+                              bool herm, hipStream_t s) {
+    if (dir == ADJOINT) return launch_i8_contract_t<false, true>(ws, out, out128, N, batch, scale, s);
+    return herm ? launch_i8_contract_t<true, false>(ws, out, out128, N, batch, scale, s)
+                : launch_i8_contract_t<false, false>(ws, out, out128, N, batch, scale, s);
 }
 
-hipError_t launch_i8(const void* in, bool in128, void* out, bool out128, int N, int batch, double scale, void* ws,
-                     bool herm, hipStream_t s) {
-    hipError_t e = launch_i8_pack(in, in128, N, batch, ws, herm, s);
+hipError_t launch_i8(Dir dir, const void* in, bool in128, void* out, bool out128, int N, int batch, double scale,
+                     void* ws, bool herm, hipStream_t s) {
+    hipError_t e = launch_i8_pack(in, in128, N, batch, ws, dir, herm, s);
     if (e != hipSuccess) return e;
-    return launch_i8_contract(ws, out, out128, N, batch, scale, herm, s);
+    return launch_i8_contract(ws, out, out128, N, batch, scale, dir, herm, s);
 }
 
 }  // namespace pauli

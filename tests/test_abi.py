@@ -245,9 +245,9 @@ def test_fwht_f32_algo_queries(lib, pauli):
 
 def test_split_i8_algo_queries(lib, pauli):
     """The fixed-point int8 path: six one-byte planes of workspace plus its
-    scale record and partial maxima, one tile shape, forward only (general
-    and Hermitian); the adjoint, batched and tuning entry points refuse it
-    before any device call."""
+    scale record and partial maxima, one tile shape; every single-matrix entry
+    point takes it (a short workspace fails before any device call), the
+    batched and tuning ones refuse it."""
     assert pauli.ALGOS["split_i8"] == 6
     for N, batch in ((14, 1), (10, 3), (3, 2)):
         Dp = max(1 << N, 32)
@@ -265,13 +265,10 @@ def test_split_i8_algo_queries(lib, pauli):
     assert lib.pauli_decompose(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(forced)) == EINVAL
     small = opts(pauli, algo="split_i8", ws=0x30000000, ws_bytes=6 * 4 ** 10)
     assert lib.pauli_decompose(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
-    assert lib.pauli_reconstruct(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
-    assert lib.pauli_decompose_backward(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
+    assert lib.pauli_reconstruct(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
+    assert lib.pauli_decompose_backward(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_decompose_hermitian(FAKE_IN, 10, 1, FAKE_OUT, ctypes.byref(forced)) == EINVAL
-    for mode in (1, 2):
-        assert lib.pauli_pack(FAKE_IN, 10, 1, mode, ctypes.byref(o)) == EUNSUPPORTED
-        assert lib.pauli_contract(10, 1, mode, FAKE_OUT, ctypes.byref(o)) == EUNSUPPORTED
-    for mode in (0, 3):   # decompose and Hermitian decompose: the workspace is required
+    for mode in (0, 1, 2, 3):   # every mode; the workspace is required
         assert lib.pauli_pack(FAKE_IN, 10, 1, mode, ctypes.byref(o)) == ENOMEM
         assert lib.pauli_contract(10, 1, mode, FAKE_OUT, ctypes.byref(small)) == ENOMEM
     assert lib.pauli_autotune(9, 10, ctypes.byref(o)) == EUNSUPPORTED

@@ -9,7 +9,7 @@ torch.autograd) is checked on 64 seeded entries against
     coefficients re-evaluated by the oracle (L is quadratic, so central
     differences are exact up to rounding).
 
-Tolerance: 1e-5 max|grad| for split-bf16 and fp32, 1e-10 for binary64.
+Tolerance: 1e-5 max|grad| for the split, int8 and fp32 paths, 1e-10 for binary64.
 The oracle gradient itself is pinned to the finite differences on the CPU.
 """
 import numpy as np
@@ -20,7 +20,7 @@ from tests import backward_workload as bw
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"split_bf16": 1e-5, "split_fp16": 1e-5, "fp32": 1e-5, "fp64_gray": 1e-10, "fwht": 1e-10}
+TOL = {"split_bf16": 1e-5, "split_fp16": 1e-5, "fp32": 1e-5, "split_i8": 1e-5, "fp64_gray": 1e-10, "fwht": 1e-10}
 
 
 @pytest.fixture(scope="module")
@@ -51,7 +51,7 @@ def gpu_gradient(problem, algo):
     return g.to(torch.complex128).cpu().numpy()
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray", "fwht"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "split_i8", "fp64_gray", "fwht"])
 def test_adjoint_gradient_vs_oracle(problem, algo):
     ref = oracle_gradient(problem)
     got = gpu_gradient(problem, algo)
@@ -59,7 +59,7 @@ def test_adjoint_gradient_vs_oracle(problem, algo):
     assert err <= TOL[algo], err
 
 
-@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "fp64_gray", "fwht"])
+@pytest.mark.parametrize("algo", ["split_bf16", "split_fp16", "fp32", "split_i8", "fp64_gray", "fwht"])
 def test_adjoint_gradient_vs_finite_differences(problem, finite_differences, algo):
     """The GPU gradient (hand-written adjoint through torch.autograd) against
     the central differences directly, all 64 entries.  The differences carry

@@ -1,4 +1,5 @@
-"""The fixed-point int8 path (split_i8) through the C ABI.
+"""The fixed-point int8 path (split_i8) through the C ABI: decomposition,
+its Hermitian variant, reconstruction and the backward (adjoint).
 
 Against the oracle: every coefficient at N = 0..10 (ragged N < 5 padded to
 32, the one-slice-at-a-time kernel below N = 8) and at the N = 12 Hermitian
@@ -201,19 +202,75 @@ def test_mixed_magnitudes_within_the_fixed_point_bound():
     check(G, dec(G, torch.complex128), ref, torch.complex128)
 
 
-def test_forward_only():
-    """The adjoint and batched entry points refuse the algorithm
-    (PAULI_EUNSUPPORTED) without launching anything."""
+def test_batched_refused():
+    """The uneven-batch entry point refuses the algorithm (PAULI_EUNSUPPORTED)
+    without launching anything."""
     p = lib()
-    N = 6
-    G = dev(workloads.iid_complex(N, 8950, np.complex64))
-    c = torch.zeros(4 ** N, dtype=torch.complex64, device="cuda")
-    for call in (lambda: p.decompose_backward(c, algo="split_i8"),
-                 lambda: p.reconstruct(c, algo="split_i8"),
-                 lambda: p.decompose_batched([G], algo="split_i8")):
-        with pytest.raises(p.PauliError) as e:
-            call()
-        assert e.value.status == 2
+    G = dev(workloads.iid_complex(6, 8950, np.complex64))
+    with pytest.raises(p.PauliError) as e:
+        p.decompose_batched([G], algo="split_i8")
+    assert e.value.status == 2
+
+
+def adjoint_bound(c, ref, out_dtype, scale):
+    """Each entry of the adjoint sums 2^N quantised terms: at most 2^N m / (2L)
+    per component (m the largest component of c), times the scale, plus the
+    output's rounding."""
+    m = max(np.abs(c.real).max(), np.abs(c.imag).max())
+    n = c.shape[-1]
+    D = int(round(np.sqrt(n)))
+    rnd = (2.0 ** -24 if out_dtype == torch.complex64 else 2.0 ** -52) * np.abs(ref).max()
+    return np.sqrt(2.0) * (scale * D * m / (2 * L8) + rnd) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("N", [0, 1, 3, 5, 7, 8, 9, 10])
+def test_reconstruct_and_backward_vs_oracle(N):
+    """pauli_reconstruct (G = sum_n c_n P_n) and pauli_decompose_backward
+    (2^-N sum_n g_n P_n) against the oracle's recomposition, within the
+    adjoint's bound and 1e-6 of max|G|."""
+    p = lib()
+    c = workloads.iid_complex(N, 8980 + N, np.complex64).reshape(-1)
+    ref = oracle.recompose(c.astype(np.complex128))
+    G = p.reconstruct(dev(c), algo="split_i8").cpu().numpy()
+    err = np.abs(G.astype(np.complex128) - ref).max()
+    assert err <= adjoint_bound(c, ref, torch.complex64, 1.0), err
+    assert err <= 1e-6 * np.abs(ref).max()
+    gG = p.decompose_backward(dev(c), algo="split_i8").cpu().numpy()
+    ref2 = ref / (1 << N)
+    err2 = np.abs(gG.astype(np.complex128) - ref2).max()
+    assert err2 <= adjoint_bound(c, ref2, torch.complex64, 2.0 ** -N), err2
+    assert err2 <= 1e-6 * np.abs(ref2).max()
+
+
+def test_round_trip_two_pass_and_autograd():
+    """reconstruct(decompose(G)) = G within 8e-6 of max|G| (two quantised
+    passes); modes 1 and 2 of the two-pass entry points equal the one-call
+    adjoints bit for bit; through torch.autograd the gradient is
+    pauli_decompose_backward of grad_c."""
+    import ctypes
+    p = lib()
+    L = p.load_library()
+    N = 9
+    G = workloads.iid_complex(N, 8990, np.complex64)
+    Gd = dev(G)
+    c = p.decompose(Gd, algo="split_i8")
+    G2 = p.reconstruct(c, algo="split_i8").cpu().numpy()
+    assert np.abs(G2 - G).max() <= 1e-6 * np.abs(G).max() * 8
+    ws = p.workspace("split_i8", N, 1, Gd.device)
+    o = p._opts("split_i8", 0, 0, 0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ws)
+    for mode, fn, scale in ((1, p.reconstruct, 1.0), (2, p.decompose_backward, None)):
+        out = torch.empty(4 ** N, dtype=torch.complex64, device="cuda")
+        assert L.pauli_pack(ctypes.c_void_p(c.data_ptr()), N, 1, mode, ctypes.byref(o)) == 0
+        assert L.pauli_contract(N, 1, mode, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o)) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(out.reshape(1 << N, 1 << N), fn(c, algo="split_i8")), mode
+    Gg = Gd.clone().requires_grad_(True)
+    cg = p.PauliDecompose.apply(Gg, "split_i8")
+    w = torch.rand(cg.shape, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    (w * cg.abs() ** 2).sum().backward()
+    gc = (2 * w * cg.detach()).contiguous()   # dL/dRe + i dL/dIm, up to autograd's own rounding
+    want = p.decompose_backward(gc, algo="split_i8")
+    assert (Gg.grad - want).abs().max().item() <= 1e-5 * want.abs().max().item()
 
 
 @pytest.mark.parametrize("N", [0, 3, 5, 8, 9, 10, 11, 12])
