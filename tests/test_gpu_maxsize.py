@@ -10,7 +10,8 @@ stay below 2^24), binary32, the binary64 string list and the binary64 fast
 Walsh-Hadamard path (whose 64 GiB intermediate replaces split-bf16's 48 GiB
 workspace), and the Hermitian entry point on (A + A^H) (x) (B + B^H).
 Sampled outputs are therefore compared for equality.  Needs about 180 GiB
-of device memory.
+of device memory.  The int8 path's largest exact sums are checked first, on
+an all-equal matrix.
 """
 import numpy as np
 import pytest
@@ -28,6 +29,33 @@ def small_int_matrix(seed):
     re = rng.integers(-2, 3, (256, 256))
     im = rng.integers(-2, 3, (256, 256))
     return (re + 1j * im).astype(np.complex64)
+
+
+def test_n16_int8_largest_sums():
+    """The int8 path's extreme at N = 16: every component equal (G = (1 + i)
+    J), so every q is the largest L and the phase mask z = 0 sums 2^16 equal
+    digits, the largest |256 A2 + A1| the int32 fold can meet (2^16 x 32639 <
+    2^31).  c = 1 + i for the 2^16 strings with z = 0 (any flip mask), 0 for
+    all others.  Runs before the Kronecker fixture takes its memory."""
+    import paper_2401_16378_amd as p
+    p.load_library()
+    print("N=16 int8 all-equal matrix", flush=True)
+    G = torch.full((1 << N, 1 << N), 1 + 1j, dtype=torch.complex64, device="cuda")
+    c = p.decompose(G, algo="split_i8")
+    del G
+    p.release_workspace()
+    torch.cuda.synchronize()
+    assert int((c != 0).sum().item()) == 1 << N
+    # the strings with z = 0: n = spread_even(x), x < 2^16 (index them directly:
+    # boolean-mask indexing of 2^32 elements is not usable in torch)
+    x = np.arange(1 << N, dtype=np.int64)
+    n = np.zeros_like(x)
+    for t in range(N):
+        n |= ((x >> t) & 1) << (2 * t)
+    picked = c[torch.from_numpy(n).cuda()]
+    assert bool(torch.all(picked == (1 + 1j)).item())
+    del c, picked
+    torch.cuda.empty_cache()
 
 
 @pytest.fixture(scope="module")
@@ -111,7 +139,7 @@ def test_n16_hermitian_exact(kron_case):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("algo", ["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("algo", ["split_fp16", "split_bf16", "split_i8"])
 def test_n15_random_vs_binary64(algo):
     """N = 15 on dense random data (no structure that keeps sums exact): every
     one of the 2^30 coefficients of the matrix-core path within 1e-6 of
