@@ -428,8 +428,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--N", type=int, default=14)
     ap.add_argument("--algo", default=None,
-                    help="path to time (default: split_i8 for n14 and hermitian, split_fp16 for batch and "
-                         "backward, fwht for fwht)")
+                    help="path to time (default: split_i8 for n14, hermitian and backward, split_fp16 for "
+                         "batch, fwht for fwht)")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other split path")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -440,7 +440,8 @@ def main():
                     help="also run a device copy of this many GiB (counter calibration)")
     a = ap.parse_args()
     if a.algo is None:
-        a.algo = {"n14": "split_i8", "hermitian": "split_i8", "fwht": "fwht"}.get(a.workload, "split_fp16")
+        a.algo = {"n14": "split_i8", "hermitian": "split_i8", "backward": "split_i8", "fwht": "fwht"}.get(
+            a.workload, "split_fp16")
     if a.workload == "batch" and a.algo not in ("split_bf16", "split_fp16", "fp32"):
         raise SystemExit("bench.py: the batch workload runs split_bf16, split_fp16 or fp32, not %s" % a.algo)
     if a.workload == "backward" and a.algo not in ("split_bf16", "split_fp16", "fp32", "split_i8"):

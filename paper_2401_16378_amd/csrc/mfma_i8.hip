@@ -315,7 +315,16 @@ __global__ __launch_bounds__(256) void i8_pack_kernel(const void* __restrict__ i
 template <bool IN128>
 __global__ __launch_bounds__(256) void i8_pack_adj_kernel(const void* __restrict__ in, void* __restrict__ ws, int N,
                                                           const I8Scale* __restrict__ rec) {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[I8_NPL * XT * I8_PITCH];
+    // LDS: first each wave's 1024 coefficients (read lane-consecutive from
+    // HBM, PADE elements of padding after every 16 so that the per-thread
+    // reads of 16 consecutive entries fall in distinct banks), then, after a
+    // barrier, the digit staging tile.
+    constexpr int EW = IN128 ? 16 : 8;             // bytes per coefficient
+    constexpr int PADE = IN128 ? 1 : 2;            // 16 bytes of padding per 16 coefficients
+    constexpr int BLK = 1024 + 64 * PADE;          // elements per wave block
+    constexpr int STAGE = I8_NPL * XT * I8_PITCH;
+    constexpr int ADJB = 4 * BLK * EW;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[STAGE > ADJB ? STAGE : ADJB];
     const uint32_t D = 1u << N, Dp = padded_dim(N);
     const uint32_t KT = Dp < (uint32_t)PACK_KT ? Dp : (uint32_t)PACK_KT;
     const uint32_t nKT = Dp / KT;
@@ -328,18 +337,49 @@ __global__ __launch_bounds__(256) void i8_pack_adj_kernel(const void* __restrict
     const I8Scale sc = rec[blockIdx.y];
     const int tid = threadIdx.x;
     const int g = tid >> 6, w6 = tid & 63;
+    const bool active = (uint32_t)tid < 2 * KT;
+    const uint32_t zb = Q0 + 32 * g;
+    const uint32_t nb = pauli_index(X0, zb);
+    double2 v[16];
 
-    if ((uint32_t)tid < 2 * KT) {
-        const uint32_t zb = Q0 + 32 * g;
-        const uint32_t nb = pauli_index(X0, zb);
-        double2 v[16];
+    if (full) {   // uniform
+        unsigned char* blk = lds + g * BLK * EW;
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t o = 64 * i + w6;
+                const unsigned char* sp = src + (size_t)(nb + o) * EW;
+                unsigned char* dp = blk + (o + PADE * (o >> 4)) * EW;
+                if constexpr (IN128) *(double2*)dp = *(const double2*)sp;
+                else *(float2*)dp = *(const float2*)sp;
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const unsigned char* mine = blk + w6 * (16 + PADE) * EW;   // entries 16 w6 .. 16 w6 + 15
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if constexpr (IN128) {
+                    v[2 * j] = ((const double2*)mine)[2 * j];
+                    v[2 * j + 1] = ((const double2*)mine)[2 * j + 1];
+                } else {
+                    const float4 q = ((const float4*)mine)[j];
+                    v[2 * j] = make_double2((double)q.x, (double)q.y);
+                    v[2 * j + 1] = make_double2((double)q.z, (double)q.w);
+                }
+            }
+        }
+        __syncthreads();   // the staging below overwrites the LDS
+    }
+
+    if (active) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const uint32_t o = 16 * w6 + r;
             const uint32_t zl = compact_even(o >> 1), xl = compact_even(o) ^ zl;
             const uint32_t z = zb + zl, x = X0 + xl;
-            double2 c = make_double2(0.0, 0.0);
-            if (full || (z < D && x < D)) c = load_g<IN128>(src, nb + o);
+            double2 c = full ? v[r] : make_double2(0.0, 0.0);
+            if (!full && z < D && x < D) c = load_g<IN128>(src, nb + o);
             rotate_minus_i(c.x, c.y, 3u * (uint32_t)__popc(x & z));   // times i^{popc(x&z)}
             v[r] = c;
         }
