@@ -5,8 +5,9 @@ linearity, and the adjoint relation Re<g, D(G)> = Re<D^H g, G> between the
 decomposition D and its backward entry point D^H.
 
 Tolerances are those of the parity tests (error relative to max|c|): 1e-12
-for the binary64 paths, 1e-5 for binary32, 1e-6 for the splits, and bit
-equality where every path's sums are exact (small integers, powers of two).
+for the binary64 paths, 1e-5 for binary32, 1e-6 for the splits and the int8
+path, and bit equality where every floating-point path's sums are exact
+(small integers, powers of two).
 """
 import numpy as np
 import pytest
@@ -18,8 +19,12 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64_gray": 1e-12, "fwht": 1e-12, "fwht_f32": 1e-6, "fp32": 1e-5, "split_bf16": 1e-6,
-       "split_fp16": 1e-6}
+       "split_fp16": 1e-6, "split_i8": 1e-6}
 ALGOS = list(TOL)
+# every path whose sums of small dyadic values are exact all the way to the
+# output (the int8 path's sums are exact too, but its final scaling by a
+# rounded mm / L can leave binary64 outputs one unit in the last place off)
+EXACT_ALGOS = [a for a in ALGOS if a != "split_i8"]
 
 
 def lib():
@@ -52,7 +57,7 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("algo", EXACT_ALGOS)
 @pytest.mark.parametrize("N", [6, 9])
 def test_all_ones_and_ground_projector_exact(algo, N):
     """J (every entry 1): c = 1 exactly on the strings of I and X only (z = 0),
