@@ -314,3 +314,26 @@ def test_hermitian_variant_batch_and_two_pass():
     assert L.pauli_contract(N, 3, 3, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o)) == 0
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().reshape(3, -1), cb)
+
+
+@pytest.mark.parametrize("N", [0, 2, 4, 7])
+def test_batches_equal_single_calls(N):
+    """Equal-order batches (including the orders below 5, padded to 32 x 32)
+    through the decomposition, its Hermitian variant and both adjoints:
+    every member equals its own single call bit for bit."""
+    p = lib()
+    count = 3
+    mats = [workloads.iid_complex(N, 9000 + 10 * N + k, np.complex64) for k in range(count)]
+    herm = [((m + m.conj().T) / 2).astype(np.complex64) for m in mats]
+    B, H = dev(np.stack(mats)), dev(np.stack(herm))
+    cb = p.decompose(B, algo="split_i8").cpu().numpy()
+    hb = p.decompose_hermitian(H, algo="split_i8").cpu().numpy()
+    vecs = dev(np.stack([m.reshape(-1) for m in mats]))
+    rb = p.reconstruct(vecs, algo="split_i8").cpu().numpy()
+    gb = p.decompose_backward(vecs, algo="split_i8").cpu().numpy()
+    for k in range(count):
+        assert np.array_equal(cb[k], dec(mats[k])), ("decompose", k)
+        assert np.array_equal(hb[k], p.decompose_hermitian(dev(herm[k]), algo="split_i8").cpu().numpy()), ("herm", k)
+        v = dev(mats[k].reshape(-1))
+        assert np.array_equal(rb[k], p.reconstruct(v, algo="split_i8").cpu().numpy()), ("reconstruct", k)
+        assert np.array_equal(gb[k], p.decompose_backward(v, algo="split_i8").cpu().numpy()), ("backward", k)
