@@ -267,13 +267,26 @@ __global__ __launch_bounds__(256) void i8_pack_kernel(const void* __restrict__ i
         const uint32_t q0 = Q0 + 32 * g + 4 * mc;                  // first column (= first i)
         const uint32_t r0 = (((Q0 + 32 * g) ^ X0) & ~31u) + 4 * mr;  // first row
         double2 v[16];
+        if (!IN128 && full) {
+            // complex64, D >= 32: each row's 4 elements are 32 aligned bytes, two 16-byte loads
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t r = r0 + a, q = q0 + b;
-                v[a * 4 + b] = (full || (r < D && q < D)) ? load_g<IN128>(src, (size_t)r * D + q) : make_double2(0.0, 0.0);
+            for (int a = 0; a < 4; ++a) {
+                const float4* rp = (const float4*)(src + ((size_t)(r0 + a) * D + q0) * 8);
+                const float4 u0 = rp[0], u1 = rp[1];
+                v[a * 4 + 0] = make_double2((double)u0.x, (double)u0.y);
+                v[a * 4 + 1] = make_double2((double)u0.z, (double)u0.w);
+                v[a * 4 + 2] = make_double2((double)u1.x, (double)u1.y);
+                v[a * 4 + 3] = make_double2((double)u1.z, (double)u1.w);
             }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t r = r0 + a, q = q0 + b;
+                    v[a * 4 + b] = (full || (r < D && q < D)) ? load_g<IN128>(src, (size_t)r * D + q) : make_double2(0.0, 0.0);
+                }
+        }
         // element (row r0 + a, column q0 + b) lies on flip mask (r0 ^ q0) + (a ^ b) at i = q0 + b
         const int xh = mr ^ mc;               // flip masks 4 xh .. 4 xh + 3 of the slab
         const int kh = 32 * g + 4 * mc;       // K slots kh .. kh + 3 of the tile
