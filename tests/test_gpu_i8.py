@@ -337,3 +337,25 @@ def test_batches_equal_single_calls(N):
         v = dev(mats[k].reshape(-1))
         assert np.array_equal(rb[k], p.reconstruct(v, algo="split_i8").cpu().numpy()), ("reconstruct", k)
         assert np.array_equal(gb[k], p.decompose_backward(v, algo="split_i8").cpu().numpy()), ("backward", k)
+
+
+@pytest.mark.parametrize("which", ["decompose", "reconstruct", "decompose_backward"])
+def test_dtype_pairs(which):
+    """Every input/output dtype pair of the three entry points: complex64
+    input widens exactly (the same quantised integers), and complex64 output
+    is the binary64 result rounded once, so all four pairs follow from one
+    result bit for bit.  (Unlike the floating-point splits, a general
+    complex128 input is quantised from its binary64 values, not from its
+    complex64 rounding.)"""
+    p = lib()
+    fn = getattr(p, which)
+    N = 7
+    x64 = workloads.iid_complex(N, 9100 + N, np.complex64)
+    if which != "decompose":
+        x64 = x64.reshape(-1)
+    x128 = x64.astype(np.complex128)
+    ref = fn(dev(x64), algo="split_i8", out_dtype=torch.complex128)
+    assert torch.equal(fn(dev(x128), algo="split_i8", out_dtype=torch.complex128), ref)
+    ref64 = ref.to(torch.complex64)
+    assert torch.equal(fn(dev(x64), algo="split_i8", out_dtype=torch.complex64), ref64)
+    assert torch.equal(fn(dev(x128), algo="split_i8", out_dtype=torch.complex64), ref64)
