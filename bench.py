@@ -39,7 +39,7 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Pauli coeffs/sec + % MFMA peak at N=14, split-BF16 vs FP64 at err≤1e-6"
-METRIC_HERM = ("Pauli coeffs/sec at N=14, Hermitian-aware split-BF16 (not the paper's general method), "
+METRIC_HERM = ("Pauli coeffs/sec at N=14, Hermitian-aware decomposition (not the paper's general method), "
                "err<=1e-6")
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_I8_TOPS = 5000.0   # dense int8 matrix-core peak
